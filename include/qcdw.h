@@ -1,0 +1,172 @@
+/*
+ * qcdw — even-odd preconditioned Wilson-clover inversion for AMD MI355X (gfx950).
+ *
+ * C ABI of the HIP library libqcdw.so.  Plain pointers and sizes only.
+ *
+ * Field layouts at the boundary are the ones of arXiv 2411.08461, Sec. II.A
+ * ("Convention"), complex numbers stored as interleaved FP64 (re, im):
+ *   lattice   L = [Lx, Ly, Lz, Lt], every extent even and >= 2;
+ *             even-odd site order [2, Lt, Lz, Ly, Lx/2], parity (x+y+z+t)%2,
+ *             x fastest.  V = Lx Ly Lz Lt, Vh = V/2.
+ *   gauge     [4, 2, Lt, Lz, Ly, Lx/2, 3, 3] complex, row-column colour order
+ *             (576 V bytes).  Links must be SU(3) when reconstruct-12 is used.
+ *   fermion   [2, Lt, Lz, Ly, Lx/2, 4, 3] complex (192 V bytes).
+ *   clover    [2, Lt, Lz, Ly, Lx/2, 2, 36] doubles (576 V bytes): per
+ *             chirality block (spins {0,1}, then {2,3}) the 6 real diagonal
+ *             entries followed by the 15 complex strictly-lower entries
+ *             (1,0),(2,0),(2,1),(3,0),...,(5,4) as (re, im); block row/column
+ *             index 3*(spin%2)+colour.  The blocks are Hermitian.
+ * Dirac matrices: DeGrand-Rossi basis (Sec. II.A).
+ *
+ * Operator (Sec. III.B, Eq. "clover", isotropic: xi0 = nu = 1, c_t = c_r = csw):
+ *   M psi = A psi - kappa H psi,
+ *   H psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu),
+ *   A = 1 - kappa csw C,   C = sum_{mu<nu} sigma_{mu nu} F_{mu nu},
+ *   sigma_{mu nu} = [g_mu, g_nu]/2,  F = traceless part of (Q - Q^+)/8 with Q
+ *   the four-leaf clover sum.  kappa = 1/(2 m0 + 8).
+ * Even-odd (Sec. II.A and II.D): the solver works on the symmetric Schur
+ * complement on even sites, M_hat = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe.
+ * Solver (Sec. II.E): BiCGStab.
+ *
+ * Ownership and errors, for every call:
+ *   - every field pointer is device memory owned by the caller (e.g. a
+ *     contiguous torch tensor); the library never frees it;
+ *   - the library owns its workspaces (packed links, clover inverse, Krylov
+ *     vectors) inside a context or operator and frees them in *_destroy;
+ *   - no exception crosses the ABI: each call returns a qcdw_status, and
+ *     qcdw_last_error(ctx) describes the last failure on that context;
+ *   - invalid arguments (odd extents, null pointers, host pointers, tol <= 0)
+ *     give QCDW_EINVAL before any GPU work;
+ *   - all work is enqueued on the context's stream; calls return after the
+ *     results are complete on that stream unless stated otherwise.
+ */
+#ifndef QCDW_H
+#define QCDW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qcdw_ctx qcdw_ctx;
+typedef struct qcdw_op qcdw_op;
+
+typedef struct {
+    int32_t L[4];  /* Lx, Ly, Lz, Lt: each even and >= 2 */
+    int32_t t_bc;  /* +1 periodic, -1 antiperiodic in t (the paper's t_boundary) */
+} qcdw_lattice;
+
+typedef enum {
+    QCDW_OK = 0,
+    QCDW_EINVAL = -1,     /* bad argument */
+    QCDW_ENOMEM = -2,     /* device allocation failed */
+    QCDW_EHIP = -3,       /* HIP runtime error */
+    QCDW_ENOCONV = -4,    /* maxiter reached before tol */
+    QCDW_EBREAKDOWN = -5, /* BiCGStab breakdown that restarts could not cure */
+    QCDW_ENAN = -6,       /* NaN/Inf in the source or the iteration */
+    QCDW_ENOTPD = -7      /* a clover block A is not positive definite */
+} qcdw_status;
+
+typedef enum { QCDW_F64 = 0, QCDW_F32 = 1, QCDW_BF16 = 2, QCDW_F16 = 3 } qcdw_prec;
+
+typedef struct {
+    double tol;            /* target FP64 ||b - M x|| / ||b|| on the full lattice, > 0 */
+    int32_t maxiter;       /* iteration cap summed over restarts and reliable updates */
+    qcdw_prec inner;       /* storage precision of the Krylov iteration (F64: plain solve) */
+    double delta;          /* reliable-update trigger: recompute the FP64 residual when the
+                              iterated residual has fallen by this factor (mixed precision) */
+    int32_t check_every;   /* host polls convergence every this many iterations (>= 1) */
+    int32_t max_restarts;  /* restarts allowed after a breakdown */
+    int32_t collect_timing;/* 1: time every hop launch with HIP events (eager path) */
+    int32_t fault_inject;  /* tests only: > 0 forces a breakdown at that iteration */
+} qcdw_solver_params;
+
+typedef struct {
+    int32_t status;        /* qcdw_status of the solve */
+    int32_t iters;         /* Krylov iterations (all restarts, all RHS max for multi) */
+    int32_t n_reliable;    /* FP64 residual recomputations (reliable updates) */
+    int32_t n_restarts;    /* restarts after breakdown */
+    double true_res;       /* FP64 ||b - M x|| / ||b|| on the full lattice, from x */
+    double iter_res;       /* last iterated relative residual of the Schur system */
+    double time_ms;        /* wall time of the solve on the host */
+    double hop_ms[3];      /* collect_timing = 1: summed time of the hop launches of the Krylov
+                              iteration, by kind: [0] H_oe with A_oo^-1 (into odd sites),
+                              [1] H_eo, A_ee^-1, xpay and (r0, v), [2] the same with (t, s), (t, t) */
+    int32_t n_hop[3];      /* launches timed, same kinds */
+    int32_t hist_len;      /* in: capacity of res_hist (entries) */
+    int32_t hist_count;    /* out: entries written */
+    double *res_hist;      /* in: host buffer or NULL; out: relative residual after each
+                              iteration (entry 0 = initial) */
+} qcdw_solve_info;
+
+/* Defaults: tol 1e-10, maxiter 10000, inner F64, delta 0.1, check_every 8,
+   max_restarts 8, collect_timing 0, fault_inject 0. */
+void qcdw_solver_params_default(qcdw_solver_params *p);
+
+/* Context bound to one device and one HIP stream (hipStream_t, may be NULL for
+   the default stream, e.g. torch.cuda.current_stream().cuda_stream). */
+qcdw_status qcdw_ctx_create(qcdw_ctx **ctx, int device, void *hip_stream);
+void qcdw_ctx_destroy(qcdw_ctx *ctx);
+const char *qcdw_last_error(const qcdw_ctx *ctx);
+qcdw_status qcdw_ctx_set_stream(qcdw_ctx *ctx, void *hip_stream);
+
+/* Clover field construction when the gauge field is loaded (Sec. III.B, the
+   clover term of Eq. "clover"): clover = C = sum_{mu<nu} sigma F, without
+   kappa or csw.  U: gauge layout (read); clover: clover layout (written). */
+qcdw_status qcdw_clover_build(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, void *clover);
+
+/* out = A psi with A = 1 - kappa csw C (the site-local part of Eq. "clover").
+   clover: clover layout; psi, out: fermion layout; out may not alias psi. */
+qcdw_status qcdw_clover_apply(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *clover, const void *psi,
+                              void *out, double kappa, double csw);
+
+/* clover_inv = A^-1 blockwise (Cholesky), same packed layout as the clover.
+   Returns QCDW_ENOTPD if some block of A is not positive definite. */
+qcdw_status qcdw_clover_invert(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *clover, double kappa,
+                               double csw, void *clover_inv);
+
+/* Parity block of the hopping term: out = H psi on sites of parity out_parity,
+   zero on the other parity (psi's values on out_parity are not read).
+   psi, out: fermion layout (full lattice). */
+qcdw_status qcdw_hop(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, const void *psi, void *out,
+                     int out_parity);
+
+/* out = M psi (the full Wilson-clover matrix of Eq. "clover").  clover may be
+   NULL, then it is built from U.  psi, out: fermion layout, no aliasing. */
+qcdw_status qcdw_dslash(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, const void *clover, const void *psi,
+                        void *out, double kappa, double csw);
+
+/* Operator object (the getDirac + loadGauge step of Sec. III.B): packs U into
+   the internal site-major layout (reconstruct-12 when recon == 12, else 18),
+   builds the clover field, inverts A on both parities, and keeps FP64 copies
+   plus copies in `inner` storage precision.  U is not referenced afterwards. */
+qcdw_status qcdw_op_create(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, double kappa, double csw,
+                           qcdw_prec inner, int recon, qcdw_op **op);
+void qcdw_op_destroy(qcdw_op *op);
+
+/* out_e = M_hat in_e on even sites.  in_e, out_e: [Lt, Lz, Ly, Lx/2, 4, 3]
+   complex FP64 (the even half of the fermion layout).  prec selects the
+   storage precision of the kernels used (F64, or the op's inner precision);
+   the result is returned in FP64. */
+qcdw_status qcdw_op_matpc(qcdw_op *op, qcdw_prec prec, const void *in_e, void *out_e);
+
+/* Solve M x = b (fermion layout).  x holds the initial guess on entry (zeros
+   for none) and the solution on exit; it is written on QCDW_OK and
+   QCDW_ENOCONV (best iterate).  info is always filled.  The acceptance test is
+   the FP64 true residual of the full system, recomputed from x. */
+qcdw_status qcdw_invert(qcdw_op *op, const void *b, void *x, const qcdw_solver_params *params,
+                        qcdw_solve_info *info);
+
+/* nrhs right-hand sides solved together (Sec. III.B: a propagator is 12
+   solves).  b, x: nrhs consecutive fermion fields.  info: nrhs entries.  The
+   hop kernel applies each link to all right-hand sides of a site in one
+   launch; each RHS keeps its own recurrence and stops on its own. */
+qcdw_status qcdw_invert_multi(qcdw_op *op, int nrhs, const void *b, void *x, const qcdw_solver_params *params,
+                              qcdw_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCDW_H */

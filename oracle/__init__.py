@@ -64,6 +64,7 @@ def lib():
         _lib.orc_site_index.argtypes = [p, p]
         _lib.orc_site_index.restype = ctypes.c_long
         _lib.orc_site_coords.argtypes = [p, ctypes.c_long, p]
+        _lib.orc_num_threads.restype = i
     return _lib
 
 
@@ -103,6 +104,11 @@ def gamma_bitmask(n: int) -> np.ndarray:
         if (n >> mu) & 1:
             m = m @ gamma(mu)
     return m
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().orc_num_threads())
 
 
 def site_index(L, c) -> int:

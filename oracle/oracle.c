@@ -31,6 +31,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -76,6 +77,7 @@ static long neighbour(const int L[4], const int c[4], int mu, int step)
 }
 
 long orc_site_index(const int L[4], const int c[4]) { return site_index(L, c); }
+int orc_num_threads(void) { return omp_get_max_threads(); }
 void orc_site_coords(const int L[4], long i, int c[4]) { site_coords(L, i, c); }
 
 /* ------------------------------------------------------------------ */

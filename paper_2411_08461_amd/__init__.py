@@ -1,0 +1,360 @@
+"""qcdw: even-odd preconditioned Wilson-clover inversion for AMD MI355X (gfx950).
+
+Thin ctypes binding of the HIP library ``libqcdw.so`` (C ABI in
+``include/qcdw.h``).  Every function has the name of the C entry point it
+calls and only marshals arguments: torch tensors on the GPU provide device
+memory and the HIP stream, every step of the computation runs in the library's
+own kernels.  There is no CPU fallback: importing works without a GPU, but any
+call raises if the library or the device is missing.
+
+Field layouts follow arXiv 2411.08461, Sec. II.A (complex128 tensors):
+  gauge   [4, 2, Lt, Lz, Ly, Lx/2, 3, 3]
+  fermion [2, Lt, Lz, Ly, Lx/2, 4, 3]
+  clover  [2, Lt, Lz, Ly, Lx/2, 2, 36] float64
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqcdw.so")
+
+QCDW_OK, QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP, QCDW_ENOCONV, QCDW_EBREAKDOWN, QCDW_ENAN, QCDW_ENOTPD = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "EBREAKDOWN", -6: "ENAN",
+                -7: "ENOTPD"}
+QCDW_F64, QCDW_F32, QCDW_BF16, QCDW_F16 = 0, 1, 2, 3
+PREC = {"f64": QCDW_F64, "f32": QCDW_F32, "bf16": QCDW_BF16, "f16": QCDW_F16}
+
+# every symbol declared in include/qcdw.h
+EXPORTED = (
+    "qcdw_solver_params_default", "qcdw_ctx_create", "qcdw_ctx_destroy", "qcdw_last_error", "qcdw_ctx_set_stream",
+    "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_op_create",
+    "qcdw_op_destroy", "qcdw_op_matpc", "qcdw_invert", "qcdw_invert_multi",
+)
+
+
+class QcdwError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class qcdw_lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("t_bc", ctypes.c_int32)]
+
+
+class qcdw_solver_params(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("inner", ctypes.c_int32),
+        ("delta", ctypes.c_double),
+        ("check_every", ctypes.c_int32),
+        ("max_restarts", ctypes.c_int32),
+        ("collect_timing", ctypes.c_int32),
+        ("fault_inject", ctypes.c_int32),
+    ]
+
+
+class qcdw_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("n_reliable", ctypes.c_int32),
+        ("n_restarts", ctypes.c_int32),
+        ("true_res", ctypes.c_double),
+        ("iter_res", ctypes.c_double),
+        ("time_ms", ctypes.c_double),
+        ("hop_ms", ctypes.c_double * 3),
+        ("n_hop", ctypes.c_int32 * 3),
+        ("hist_len", ctypes.c_int32),
+        ("hist_count", ctypes.c_int32),
+        ("res_hist", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqcdw.so (built in-tree by ``paper_2411_08461_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2411_08461_amd.build`")
+    lib = ctypes.CDLL(path)
+    p, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lat = ctypes.POINTER(qcdw_lattice)
+    sig = {
+        "qcdw_solver_params_default": (None, [ctypes.POINTER(qcdw_solver_params)]),
+        "qcdw_ctx_create": (i, [ctypes.POINTER(p), i, p]),
+        "qcdw_ctx_destroy": (None, [p]),
+        "qcdw_last_error": (ctypes.c_char_p, [p]),
+        "qcdw_ctx_set_stream": (i, [p, p]),
+        "qcdw_clover_build": (i, [p, lat, p, p]),
+        "qcdw_clover_apply": (i, [p, lat, p, p, p, d, d]),
+        "qcdw_clover_invert": (i, [p, lat, p, d, d, p]),
+        "qcdw_hop": (i, [p, lat, p, p, p, i]),
+        "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
+        "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
+        "qcdw_op_destroy": (None, [p]),
+        "qcdw_op_matpc": (i, [p, i, p, p]),
+        "qcdw_invert": (i, [p, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
+        "qcdw_invert_multi": (i, [p, i, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")  # Sec. II.B: contiguous arrays only
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _volume(lat: qcdw_lattice) -> int:
+    return int(lat.L[0]) * int(lat.L[1]) * int(lat.L[2]) * int(lat.L[3])
+
+
+def _need(t, numel: int, name: str):
+    """Reject tensors whose size does not match the layout the kernels index."""
+    if t is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, the lattice needs {numel}")
+
+
+def make_lattice(L, t_bc: int = 1) -> qcdw_lattice:
+    lat = qcdw_lattice()
+    for k in range(4):
+        lat.L[k] = int(L[k])
+    lat.t_bc = int(t_bc)
+    return lat
+
+
+def _check(ctx_handle, st: int):
+    if st != QCDW_OK:
+        lib = load_library()
+        msg = lib.qcdw_last_error(ctx_handle)
+        raise QcdwError(st, msg.decode() if msg else "")
+
+
+class Context:
+    """qcdw_ctx bound to one device and one HIP stream (torch's current one by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the qcdw library has no CPU path")
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib.qcdw_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != QCDW_OK:
+            raise QcdwError(st, "qcdw_ctx_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().qcdw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qcdw_solver_params_default() -> qcdw_solver_params:
+    prm = qcdw_solver_params()
+    load_library().qcdw_solver_params_default(ctypes.byref(prm))
+    return prm
+
+
+def qcdw_clover_build(ctx: Context, lat: qcdw_lattice, U, clover) -> None:
+    V = _volume(lat)
+    _need(U, 36 * V, "U")
+    _need(clover, 72 * V, "clover")
+    st = load_library().qcdw_clover_build(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                          _ptr(clover, torch.float64, "clover"))
+    _check(ctx.handle, st)
+
+
+def qcdw_clover_apply(ctx: Context, lat: qcdw_lattice, clover, psi, out, kappa: float, csw: float) -> None:
+    V = _volume(lat)
+    _need(clover, 72 * V, "clover")
+    _need(psi, 12 * V, "psi")
+    _need(out, 12 * V, "out")
+    st = load_library().qcdw_clover_apply(ctx.handle, ctypes.byref(lat), _ptr(clover, torch.float64, "clover"),
+                                          _ptr(psi, torch.complex128, "psi"), _ptr(out, torch.complex128, "out"),
+                                          float(kappa), float(csw))
+    _check(ctx.handle, st)
+
+
+def qcdw_clover_invert(ctx: Context, lat: qcdw_lattice, clover, kappa: float, csw: float, clover_inv) -> None:
+    V = _volume(lat)
+    _need(clover, 72 * V, "clover")
+    _need(clover_inv, 72 * V, "clover_inv")
+    st = load_library().qcdw_clover_invert(ctx.handle, ctypes.byref(lat), _ptr(clover, torch.float64, "clover"),
+                                           float(kappa), float(csw), _ptr(clover_inv, torch.float64, "clover_inv"))
+    _check(ctx.handle, st)
+
+
+def qcdw_hop(ctx: Context, lat: qcdw_lattice, U, psi, out, out_parity: int) -> None:
+    V = _volume(lat)
+    _need(U, 36 * V, "U")
+    _need(psi, 12 * V, "psi")
+    _need(out, 12 * V, "out")
+    st = load_library().qcdw_hop(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                 _ptr(psi, torch.complex128, "psi"), _ptr(out, torch.complex128, "out"),
+                                 int(out_parity))
+    _check(ctx.handle, st)
+
+
+def qcdw_dslash(ctx: Context, lat: qcdw_lattice, U, clover, psi, out, kappa: float, csw: float) -> None:
+    V = _volume(lat)
+    _need(U, 36 * V, "U")
+    _need(clover, 72 * V, "clover")
+    _need(psi, 12 * V, "psi")
+    _need(out, 12 * V, "out")
+    st = load_library().qcdw_dslash(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                    _ptr(clover, torch.float64, "clover"), _ptr(psi, torch.complex128, "psi"),
+                                    _ptr(out, torch.complex128, "out"), float(kappa), float(csw))
+    _check(ctx.handle, st)
+
+
+class Operator:
+    """qcdw_op: packed links, clover inverse and solver workspace for one (U, kappa, csw)."""
+
+    def __init__(self, ctx: Context, lat: qcdw_lattice, U, kappa: float, csw: float, inner="f64", recon: int = 12):
+        self.ctx = ctx
+        self.lat = lat
+        self.kappa = kappa
+        self.csw = csw
+        self.inner = PREC[inner] if isinstance(inner, str) else int(inner)
+        self.volume = _volume(lat)
+        _need(U, 36 * self.volume, "U")
+        h = ctypes.c_void_p()
+        st = load_library().qcdw_op_create(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                           float(kappa), float(csw), self.inner, int(recon), ctypes.byref(h))
+        _check(ctx.handle, st)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().qcdw_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qcdw_op_create(ctx: Context, lat: qcdw_lattice, U, kappa: float, csw: float, inner="f64", recon: int = 12):
+    return Operator(ctx, lat, U, kappa, csw, inner, recon)
+
+
+def qcdw_op_destroy(op: Operator) -> None:
+    op.close()
+
+
+def qcdw_op_matpc(op: Operator, prec, in_e, out_e) -> None:
+    prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    _need(in_e, 6 * op.volume, "in_e")
+    _need(out_e, 6 * op.volume, "out_e")
+    st = load_library().qcdw_op_matpc(op.handle, prec, _ptr(in_e, torch.complex128, "in_e"),
+                                      _ptr(out_e, torch.complex128, "out_e"))
+    _check(op.ctx.handle, st)
+
+
+class SolveInfo:
+    def __init__(self, info: qcdw_solve_info, hist):
+        self.status = info.status
+        self.status_name = STATUS_NAMES.get(info.status, str(info.status))
+        self.iters = info.iters
+        self.n_reliable = info.n_reliable
+        self.n_restarts = info.n_restarts
+        self.true_res = info.true_res
+        self.iter_res = info.iter_res
+        self.time_ms = info.time_ms
+        self.hop_ms = list(info.hop_ms)
+        self.n_hop = list(info.n_hop)
+        self.res_hist = list(hist[: info.hist_count]) if hist is not None else []
+
+    def __repr__(self):
+        return (f"SolveInfo(status={self.status_name}, iters={self.iters}, true_res={self.true_res:.3e}, "
+                f"reliable={self.n_reliable}, restarts={self.n_restarts}, time_ms={self.time_ms:.2f})")
+
+
+def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8, max_restarts=8,
+                collect_timing=False, fault_inject=0) -> qcdw_solver_params:
+    prm = qcdw_solver_params_default()
+    prm.tol = float(tol)
+    prm.maxiter = int(maxiter)
+    prm.inner = PREC[inner] if isinstance(inner, str) else int(inner)
+    prm.delta = float(delta)
+    prm.check_every = int(check_every)
+    prm.max_restarts = int(max_restarts)
+    prm.collect_timing = 1 if collect_timing else 0
+    prm.fault_inject = int(fault_inject)
+    return prm
+
+
+def qcdw_invert(op: Operator, b, x, params: qcdw_solver_params | None = None, raise_on_error: bool = False):
+    """Solve M x = b; x holds the initial guess.  Returns a SolveInfo."""
+    if params is None:
+        params = make_params()
+    _need(b, 12 * op.volume, "b")
+    _need(x, 12 * op.volume, "x")
+    n_hist = max(1, params.maxiter + 2)
+    hist = (ctypes.c_double * n_hist)()
+    info = qcdw_solve_info()
+    info.hist_len = n_hist
+    info.res_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    st = load_library().qcdw_invert(op.handle, _ptr(b, torch.complex128, "b"), _ptr(x, torch.complex128, "x"),
+                                    ctypes.byref(params), ctypes.byref(info))
+    if raise_on_error:
+        _check(op.ctx.handle, st)
+    elif st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
+        _check(op.ctx.handle, st)
+    return SolveInfo(info, hist)
+
+
+def qcdw_invert_multi(op: Operator, b, x, params: qcdw_solver_params | None = None):
+    """Solve for nrhs = b.shape[0] stacked fermion fields; returns a list of SolveInfo."""
+    if params is None:
+        params = make_params()
+    nrhs = int(b.shape[0])
+    _need(b, 12 * op.volume * nrhs, "b")
+    _need(x, 12 * op.volume * nrhs, "x")
+    n_hist = max(1, params.maxiter + 2)
+    hists = [(ctypes.c_double * n_hist)() for _ in range(nrhs)]
+    infos = (qcdw_solve_info * nrhs)()
+    for k in range(nrhs):
+        infos[k].hist_len = n_hist
+        infos[k].res_hist = ctypes.cast(hists[k], ctypes.POINTER(ctypes.c_double))
+    st = load_library().qcdw_invert_multi(op.handle, nrhs, _ptr(b, torch.complex128, "b"),
+                                          _ptr(x, torch.complex128, "x"), ctypes.byref(params), infos)
+    if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
+        _check(op.ctx.handle, st)
+    return [SolveInfo(infos[k], hists[k]) for k in range(nrhs)]

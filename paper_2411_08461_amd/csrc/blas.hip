@@ -1,0 +1,450 @@
+// BLAS-1 kernels of the Krylov solver with fused, deterministic reductions,
+// and the small single-block kernels that turn reduction partials into the
+// BiCGStab scalars on the device (van der Vorst 1992; paper Sec. II.E names
+// BiCGStab as the clover solver).  Every reduction sums in a fixed order
+// (fixed grid, lane-ordered wave sums, wave-ordered block sums, block-ordered
+// final sum), so results are bitwise reproducible.
+#include "internal.h"
+
+namespace qcdw {
+
+#define QCDW_GRID_LOOP(e, n) \
+    for (long e = (long)blockIdx.x * BLAS_THREADS + threadIdx.x; e < (n); e += (long)gridDim.x * BLAS_THREADS)
+
+// ---------------------------------------------------------------------------
+// generic vector kernels
+// ---------------------------------------------------------------------------
+template <class P>
+__global__ __launch_bounds__(256) void k_norm2(const void* x, long n, double* partials)
+{
+    double v[1] = {0.0};
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto a = P::ld(x, e);
+        v[0] += (double)a.re * a.re + (double)a.im * a.im;
+    }
+    block_sum_store<1>(v, partials + blockIdx.x);
+}
+
+template <class PB, class PY>
+__global__ __launch_bounds__(256) void k_xmy_norm2(const void* b, const void* y, double2* r, long n,
+                                                   double* partials)
+{
+    double v[1] = {0.0};
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto bb = PB::ld(b, e);
+        const auto yy = PY::ld(y, e);
+        const double re = (double)bb.re - (double)yy.re, im = (double)bb.im - (double)yy.im;
+        if (r) r[e] = make_double2(re, im);
+        v[0] += re * re + im * im;
+    }
+    block_sum_store<1>(v, partials + blockIdx.x);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_sum_partials(const double* partials, int nb, double* out)
+{
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256)
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += partials[(long)b * K + k];
+    block_sum_store<K>(v, out);
+}
+
+template <class PI, class PO>
+__global__ __launch_bounds__(256) void k_convert(const void* in, void* out, long n, double scale)
+{
+    using T = typename PO::real;
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto a = PI::ld(in, e);
+        PO::st(out, e, cx<T>{(T)(scale * (double)a.re), (T)(scale * (double)a.im)});
+    }
+}
+
+template <class PX>
+__global__ __launch_bounds__(256) void k_axpy_hi(double a, const void* x, double2* y, long n)
+{
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto xv = PX::ld(x, e);
+        double2 yv = y[e];
+        yv.x += a * (double)xv.re;
+        yv.y += a * (double)xv.im;
+        y[e] = yv;
+    }
+}
+
+// out = B in, B the packed Hermitian clover-type matrix of each site (internal
+// reordered packing, see hop.hip); one thread per (site, chirality, row half).
+template <class P>
+__global__ __launch_bounds__(256) void k_clov_apply(const void* clov, const void* in, void* out, int Vh)
+{
+    using T = typename P::real;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 4L * Vh) return;
+    const int site = (int)(gid >> 2), q = (int)(gid & 3);  // q = spin
+    const int h = q & 1, partner = q ^ 1;
+    T win[27];
+    const long base = ((long)site * 2 + (q >> 1)) * 36 + 9 * h;
+#pragma unroll
+    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + e);
+    cx<T> vo[3], vx[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        vo[c] = P::ld(in, ((long)q * Vh + site) * 3 + c);
+        vx[c] = P::ld(in, ((long)partner * Vh + site) * 3 + c);
+    }
+    // same row formula as the hop epilogue
+    T d[3], lo[6], Xr[9], Xi[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++) d[i] = h ? win[18 + i] : win[i];
+#pragma unroll
+    for (int i = 0; i < 6; i++) lo[i] = h ? win[21 + i] : win[3 + i];
+#pragma unroll
+    for (int m = 0; m < 9; m++) {
+        Xr[m] = h ? win[2 * m] : win[9 + 2 * m];
+        Xi[m] = h ? win[2 * m + 1] : win[10 + 2 * m];
+    }
+    const cx<T> l10 = {lo[0], lo[1]}, l20 = {lo[2], lo[3]}, l21 = {lo[4], lo[5]};
+    cx<T> own[3][3];
+    own[0][0] = {d[0], T(0)};
+    own[1][1] = {d[1], T(0)};
+    own[2][2] = {d[2], T(0)};
+    own[1][0] = l10;
+    own[2][0] = l20;
+    own[2][1] = l21;
+    own[0][1] = conj(l10);
+    own[0][2] = conj(l20);
+    own[1][2] = conj(l21);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        cx<T> s = {T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b < 3; b++) s = s + own[a][b] * vo[b];
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            cx<T> cb = h ? cx<T>{Xr[3 * a + b], Xi[3 * a + b]} : cx<T>{Xr[3 * b + a], -Xi[3 * b + a]};
+            s = s + cb * vx[b];
+        }
+        P::st(out, ((long)q * Vh + site) * 3 + a, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab pieces
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b)
+{
+    const double d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+__device__ __forceinline__ cx<double> ld2(const double* p) { return {p[0], p[1]}; }
+__device__ __forceinline__ void st2(double* p, cx<double> v)
+{
+    p[0] = v.re;
+    p[1] = v.im;
+}
+
+// p = r + beta (p - omega v)
+template <class P>
+__global__ __launch_bounds__(256) void k_bicg_p(void* p, const void* r, const void* v, long n, const Scal* S)
+{
+    if (S->flags) return;
+    using T = typename P::real;
+    const cx<T> beta = {(T)S->beta[0], (T)S->beta[1]}, omega = {(T)S->omega[0], (T)S->omega[1]};
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto pv = P::ld(p, e), rv = P::ld(r, e), vv = P::ld(v, e);
+        P::st(p, e, rv + beta * (pv - omega * vv));
+    }
+}
+
+// s = r - alpha v
+template <class P>
+__global__ __launch_bounds__(256) void k_bicg_s(void* sv, const void* r, const void* v, long n, const Scal* S)
+{
+    if (S->flags) return;
+    using T = typename P::real;
+    const cx<T> alpha = {(T)S->alpha[0], (T)S->alpha[1]};
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto rv = P::ld(r, e), vv = P::ld(v, e);
+        P::st(sv, e, rv - alpha * vv);
+    }
+}
+
+// x += alpha p + omega s ; r = s - omega t ; partials (r0, r), ||r||^2
+template <class P, class PX>
+__global__ __launch_bounds__(256) void k_bicg_xr(void* x, const void* p, const void* sv, void* r, const void* t,
+                                                 const void* r0, long n, const Scal* S, double* partials)
+{
+    if (S->flags) return;
+    using T = typename P::real;
+    using TX = typename PX::real;
+    const cx<TX> alpha = {(TX)S->alpha[0], (TX)S->alpha[1]}, omega_x = {(TX)S->omega[0], (TX)S->omega[1]};
+    const cx<T> omega = {(T)S->omega[0], (T)S->omega[1]};
+    double acc[3] = {0.0, 0.0, 0.0};
+    QCDW_GRID_LOOP(e, n)
+    {
+        const auto pv = P::ld(p, e), sv_ = P::ld(sv, e), tv = P::ld(t, e), w = P::ld(r0, e);
+        const cx<TX> xv = PX::ld(x, e);
+        const cx<TX> pX = {(TX)pv.re, (TX)pv.im}, sX = {(TX)sv_.re, (TX)sv_.im};
+        PX::st(x, e, xv + alpha * pX + omega_x * sX);
+        const auto rn = P::rt(sv_ - omega * tv);
+        P::st(r, e, rn);
+        acc[0] += (double)w.re * rn.re + (double)w.im * rn.im;
+        acc[1] += (double)w.re * rn.im - (double)w.im * rn.re;
+        acc[2] += (double)rn.re * rn.re + (double)rn.im * rn.im;
+    }
+    block_sum_store<3>(acc, partials + 3L * blockIdx.x);
+}
+
+// fixed-order sum of nb x 3 partials, result valid in thread 0
+__device__ __forceinline__ void sum3(const double* partials, int nb, double (&v)[3])
+{
+    __shared__ double res[3];
+    v[0] = v[1] = v[2] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        v[0] += partials[3L * b];
+        v[1] += partials[3L * b + 1];
+        v[2] += partials[3L * b + 2];
+    }
+    block_sum_store<3>(v, res);
+    __syncthreads();
+    v[0] = res[0];
+    v[1] = res[1];
+    v[2] = res[2];
+}
+
+// start (or restart) from the residual r with r0 = r: rho = (r0, r) = ||r||^2
+__global__ void k_bicg_init(Scal* S, const double* rr_dev)
+{
+    if (threadIdx.x != 0) return;
+    const double rr = *rr_dev;
+    S->rho[0] = rr;
+    S->rho[1] = 0.0;
+    S->rr = rr;
+    S->r0n2 = rr;
+    S->alpha[0] = 1.0;
+    S->alpha[1] = 0.0;
+    S->omega[0] = 1.0;
+    S->omega[1] = 0.0;
+    S->beta[0] = 0.0;
+    S->beta[1] = 0.0;
+    S->flags = (rr <= S->stop_rr) ? FLAG_CONV : 0;
+    if (!isfinite(rr)) S->flags = FLAG_NAN;
+}
+
+__global__ __launch_bounds__(256) void k_fin_alpha(Scal* S, const double* partials, int nb)
+{
+    if (S->flags) return;
+    double v[3];
+    sum3(partials, nb, v);
+    if (threadIdx.x == 0) {
+        const cx<double> rv = {v[0], v[1]};
+        const double arv = sqrt(rv.re * rv.re + rv.im * rv.im);
+        if (!isfinite(arv)) {
+            S->flags = FLAG_NAN;
+        } else if (arv <= 1e-30 * sqrt(S->r0n2 * S->rr)) {
+            S->flags = FLAG_BREAK;
+        } else {
+            st2(S->alpha, cdiv(ld2(S->rho), rv));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fin_omega(Scal* S, const double* partials, int nb)
+{
+    if (S->flags) return;
+    double v[3];
+    sum3(partials, nb, v);
+    if (threadIdx.x == 0) {
+        const double tt = v[2];
+        if (!isfinite(tt) || !isfinite(v[0]) || !isfinite(v[1])) {
+            S->flags = FLAG_NAN;
+        } else if (tt == 0.0) {
+            // s = 0: x + alpha p is exact; omega = 0 finishes the step
+            S->omega[0] = 0.0;
+            S->omega[1] = 0.0;
+        } else {
+            S->omega[0] = v[0] / tt;
+            S->omega[1] = v[1] / tt;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fin_beta(Scal* S, const double* partials, int nb, double* hist)
+{
+    if (S->flags) return;
+    double v[3];
+    sum3(partials, nb, v);
+    if (threadIdx.x == 0) {
+        const cx<double> rho_new = {v[0], v[1]};
+        const double rr = v[2];
+        const int it = S->iter + 1;
+        S->iter = it;
+        S->rr = rr;
+        if (hist && it < S->hist_len) hist[it] = sqrt(rr) * S->hist_norm;
+        const cx<double> omega = ld2(S->omega);
+        if (!isfinite(rr) || !isfinite(rho_new.re) || !isfinite(rho_new.im)) {
+            S->flags = FLAG_NAN;
+        } else if (rr <= S->stop_rr) {
+            S->flags = FLAG_CONV;
+        } else if (omega.re == 0.0 && omega.im == 0.0) {
+            S->flags = FLAG_BREAK;
+        } else if (sqrt(rho_new.re * rho_new.re + rho_new.im * rho_new.im) <= 1e-30 * sqrt(S->r0n2 * rr)) {
+            S->flags = FLAG_BREAK;
+        } else {
+            st2(S->beta, cdiv(rho_new, ld2(S->rho)) * cdiv(ld2(S->alpha), omega));
+            st2(S->rho, rho_new);
+            if (S->fault_iter > 0 && it == S->fault_iter) S->flags = FLAG_BREAK;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define QCDW_DISPATCH1(prec, KERNEL, ...)                                              \
+    switch (prec) {                                                                    \
+    case F64: hipLaunchKernelGGL(KERNEL<P64>, __VA_ARGS__); break;                     \
+    case F32: hipLaunchKernelGGL(KERNEL<P32>, __VA_ARGS__); break;                     \
+    case BF16: hipLaunchKernelGGL(KERNEL<PBF16>, __VA_ARGS__); break;                  \
+    case F16: hipLaunchKernelGGL(KERNEL<PF16>, __VA_ARGS__); break;                    \
+    default: return hipErrorInvalidValue;                                              \
+    }
+
+hipError_t launch_norm2(hipStream_t s, int prec, const void* x, long n, double* partials, double* out)
+{
+    const int nb = blas_blocks(n);
+    QCDW_DISPATCH1(prec, k_norm2, dim3(nb), dim3(256), 0, s, x, n, partials)
+    hipLaunchKernelGGL(k_sum_partials<1>, dim3(1), dim3(256), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+template <class PB>
+static hipError_t xmy_b(hipStream_t s, int prec_y, const void* b, const void* y, void* r, long n, double* partials)
+{
+    const int nb = blas_blocks(n);
+    switch (prec_y) {
+    case F64: hipLaunchKernelGGL((k_xmy_norm2<PB, P64>), dim3(nb), dim3(256), 0, s, b, y, (double2*)r, n, partials); break;
+    case F32: hipLaunchKernelGGL((k_xmy_norm2<PB, P32>), dim3(nb), dim3(256), 0, s, b, y, (double2*)r, n, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_xmy_norm2(hipStream_t s, int prec_b, int prec_y, const void* b, const void* y, void* r, long n,
+                            double* partials, double* out)
+{
+    hipError_t e;
+    if (prec_b == F64) e = xmy_b<P64>(s, prec_y, b, y, r, n, partials);
+    else if (prec_b == F32) e = xmy_b<P32>(s, prec_y, b, y, r, n, partials);
+    else return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials<1>, dim3(1), dim3(256), 0, s, partials, blas_blocks(n), out);
+    return hipGetLastError();
+}
+
+template <class PI>
+static hipError_t convert_in(hipStream_t s, int prec_out, const void* in, void* out, long n, double scale)
+{
+    const int nb = blas_blocks(n);
+    switch (prec_out) {
+    case F64: hipLaunchKernelGGL((k_convert<PI, P64>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
+    case F32: hipLaunchKernelGGL((k_convert<PI, P32>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
+    case BF16: hipLaunchKernelGGL((k_convert<PI, PBF16>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
+    case F16: hipLaunchKernelGGL((k_convert<PI, PF16>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(hipStream_t s, int prec_in, int prec_out, const void* in, void* out, long n, double scale)
+{
+    switch (prec_in) {
+    case F64: return convert_in<P64>(s, prec_out, in, out, n, scale);
+    case F32: return convert_in<P32>(s, prec_out, in, out, n, scale);
+    case BF16: return convert_in<PBF16>(s, prec_out, in, out, n, scale);
+    case F16: return convert_in<PF16>(s, prec_out, in, out, n, scale);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_axpy_hi(hipStream_t s, int prec_x, double a, const void* x, void* y, long n)
+{
+    QCDW_DISPATCH1(prec_x, k_axpy_hi, dim3(blas_blocks(n)), dim3(256), 0, s, a, x, (double2*)y, n)
+    return hipGetLastError();
+}
+
+hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, const void* clov, const void* in,
+                                      void* out)
+{
+    const long n = 4L * g.Vh;
+    if (n == 0) return hipSuccess;
+    QCDW_DISPATCH1(prec, k_clov_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, clov, in, out, g.Vh)
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev)
+{
+    hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(64), 0, s, S, rr_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S)
+{
+    QCDW_DISPATCH1(prec, k_bicg_p, dim3(blas_blocks(n)), dim3(256), 0, s, p, r, v, n, S)
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S)
+{
+    QCDW_DISPATCH1(prec, k_bicg_s, dim3(blas_blocks(n)), dim3(256), 0, s, sv, r, v, n, S)
+    return hipGetLastError();
+}
+
+template <class PX>
+static hipError_t bicg_xr_x(hipStream_t s, int prec, void* x, const void* p, const void* sv, void* r, const void* t,
+                            const void* r0, long n, const Scal* S, double* partials)
+{
+    const int nb = blas_blocks(n);
+    switch (prec) {
+    case F64: hipLaunchKernelGGL((k_bicg_xr<P64, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
+    case F32: hipLaunchKernelGGL((k_bicg_xr<P32, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
+    case BF16: hipLaunchKernelGGL((k_bicg_xr<PBF16, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
+    case F16: hipLaunchKernelGGL((k_bicg_xr<PF16, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr(hipStream_t s, int prec, int prec_x, void* x, const void* p, const void* sv, void* r,
+                          const void* t, const void* r0, long n, const Scal* S, double* partials)
+{
+    if (prec_x == F64) return bicg_xr_x<P64>(s, prec, x, p, sv, r, t, r0, n, S, partials);
+    if (prec_x == F32) return bicg_xr_x<P32>(s, prec, x, p, sv, r, t, r0, n, S, partials);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb)
+{
+    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, S, partials, nb);
+    return hipGetLastError();
+}
+hipError_t launch_fin_omega(hipStream_t s, Scal* S, const double* partials, int nb)
+{
+    hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(256), 0, s, S, partials, nb);
+    return hipGetLastError();
+}
+hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int nb, double* hist)
+{
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, S, partials, nb, hist);
+    return hipGetLastError();
+}
+
+}  // namespace qcdw

@@ -1,0 +1,202 @@
+// Device-side building blocks shared by the qcdw HIP kernels: complex
+// arithmetic, storage-precision traits for the internal layouts, lattice
+// geometry and deterministic block reductions.
+//
+// Internal (library-owned) layouts, one parity of Vh sites each:
+//   spinor  [4 spin][Vh site][3 colour] complex        (spin-major, colour inner)
+//   gauge   [4 mu][2 parity][Vh site][R] complex, R = 6 (rows 0,1: reconstruct-12)
+//           or 9 (full link), row-major colour order
+//   clover  [Vh site][2 chirality][36] reals in the reordered packing below
+// Each lane of a hop kernel reads one spin (3 contiguous complex) of a
+// neighbour, so consecutive sites give contiguous, fully coalesced accesses.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qcdw {
+
+// ---------------------------------------------------------------------------
+// complex
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_conj(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// storage precisions: FP64, FP32, BF16, FP16.  `real` is the arithmetic type.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t f2bf_bits(float f)
+{
+    // round to nearest even; NaN kept quiet
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf_bits2f(uint32_t b) { return __uint_as_float(b << 16); }
+
+struct P64 {
+    using real = double;
+    static constexpr int cbytes = 16;  // bytes per complex
+    __device__ static cx<double> ld(const void* base, long k)
+    {
+        double2 v = reinterpret_cast<const double2*>(base)[k];
+        return {v.x, v.y};
+    }
+    __device__ static void st(void* base, long k, cx<double> z)
+    {
+        reinterpret_cast<double2*>(base)[k] = make_double2(z.re, z.im);
+    }
+    __device__ static cx<double> rt(cx<double> z) { return z; }
+    __device__ static double ldr(const void* base, long k) { return reinterpret_cast<const double*>(base)[k]; }
+    __device__ static void str(void* base, long k, double v) { reinterpret_cast<double*>(base)[k] = v; }
+};
+
+struct P32 {
+    using real = float;
+    static constexpr int cbytes = 8;
+    __device__ static cx<float> ld(const void* base, long k)
+    {
+        float2 v = reinterpret_cast<const float2*>(base)[k];
+        return {v.x, v.y};
+    }
+    __device__ static void st(void* base, long k, cx<float> z)
+    {
+        reinterpret_cast<float2*>(base)[k] = make_float2(z.re, z.im);
+    }
+    __device__ static cx<float> rt(cx<float> z) { return z; }
+    __device__ static float ldr(const void* base, long k) { return reinterpret_cast<const float*>(base)[k]; }
+    __device__ static void str(void* base, long k, float v) { reinterpret_cast<float*>(base)[k] = v; }
+};
+
+struct PBF16 {
+    using real = float;
+    static constexpr int cbytes = 4;
+    __device__ static cx<float> ld(const void* base, long k)
+    {
+        uint32_t v = reinterpret_cast<const uint32_t*>(base)[k];
+        return {bf_bits2f(v & 0xffffu), bf_bits2f(v >> 16)};
+    }
+    __device__ static void st(void* base, long k, cx<float> z)
+    {
+        reinterpret_cast<uint32_t*>(base)[k] = f2bf_bits(z.re) | (f2bf_bits(z.im) << 16);
+    }
+    __device__ static cx<float> rt(cx<float> z) { return {bf_bits2f(f2bf_bits(z.re)), bf_bits2f(f2bf_bits(z.im))}; }
+    __device__ static float ldr(const void* base, long k)
+    {
+        return bf_bits2f(reinterpret_cast<const uint16_t*>(base)[k]);
+    }
+    __device__ static void str(void* base, long k, float v)
+    {
+        reinterpret_cast<uint16_t*>(base)[k] = (uint16_t)f2bf_bits(v);
+    }
+};
+
+struct PF16 {
+    using real = float;
+    static constexpr int cbytes = 4;
+    __device__ static cx<float> ld(const void* base, long k)
+    {
+        const _Float16* p = reinterpret_cast<const _Float16*>(base) + 2 * k;
+        return {(float)p[0], (float)p[1]};
+    }
+    __device__ static void st(void* base, long k, cx<float> z)
+    {
+        _Float16* p = reinterpret_cast<_Float16*>(base) + 2 * k;
+        p[0] = (_Float16)z.re;
+        p[1] = (_Float16)z.im;
+    }
+    __device__ static cx<float> rt(cx<float> z) { return {(float)(_Float16)z.re, (float)(_Float16)z.im}; }
+    __device__ static float ldr(const void* base, long k) { return (float)reinterpret_cast<const _Float16*>(base)[k]; }
+    __device__ static void str(void* base, long k, float v) { reinterpret_cast<_Float16*>(base)[k] = (_Float16)v; }
+};
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct Geom {
+    int Lx, Ly, Lz, Lt;
+    int Lxh;   // Lx / 2
+    int Vh;    // sites per parity
+    int t_bc;  // +1 / -1
+};
+
+// coordinates of checkerboard index i on parity p
+__device__ __forceinline__ void site_coords(const Geom& g, int i, int p, int& x, int& y, int& z, int& t)
+{
+    int xh = i % g.Lxh;
+    int r = i / g.Lxh;
+    y = r % g.Ly;
+    r /= g.Ly;
+    z = r % g.Lz;
+    t = r / g.Lz;
+    x = 2 * xh + ((p + y + z + t) & 1);
+}
+
+// ---------------------------------------------------------------------------
+// block mapping: consecutive logical tiles on one XCD (workgroups are
+// dispatched round-robin over the 8 XCDs, each with its own L2)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int b, int nblk)
+{
+    const int nx = 8;
+    int per = nblk / nx, rem = nblk % nx;
+    int xcd = b % nx, k = b / nx;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions (fixed lane/wave order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum K values over a 256-thread block; thread 0 writes them to out[0..K).
+template <int K>
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out)
+{
+    __shared__ double red[4][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) red[wv][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+}  // namespace qcdw

@@ -1,0 +1,315 @@
+// Parity hop kernel of the Wilson-clover operator with fused epilogues.
+//
+// Computes on the sites of one parity (paper, Sec. III.B, Eq. "clover", the
+// Wilson hopping term written out):
+//   (H psi)(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)
+// with periodic wrap computed in the kernel and the time boundary sign t_bc.
+//
+// Work split: four lanes per site.  Lane q = 2 gq + k handles directions
+// mu = 2 gq and 2 gq + 1 (forward and backward), and only row k of the
+// half-spinor that (1 -/+ g_mu) projects onto.  In the DeGrand-Rossi basis the
+// projection is  h_k = psi_k + c psi_l  with a unit coefficient c and
+// l = 3 - k (mu = x, y) or 2 + k (mu = z, t); the projected product W h_k
+// adds to spin k and conj(c) W h_k to spin l.  So every lane reads just two
+// spins (6 complex) of each neighbour plus the link, and owns partial sums of
+// two output spins; one in-quad shuffle gives lane q the finished spin q.
+// That keeps register use low and gives 4 Vh threads per launch.
+#include "internal.h"
+
+namespace qcdw {
+
+template <class P, int R>
+__device__ __forceinline__ void load_link(const void* gauge, long off, cx<typename P::real> (&u)[9])
+{
+    if constexpr (R == 9) {
+#pragma unroll
+        for (int e = 0; e < 9; e++) u[e] = P::ld(gauge, off + e);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 6; e++) u[e] = P::ld(gauge, off + e);
+        // third row of an SU(3) matrix: complex conjugate of row0 x row1
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+}
+
+// Rows 3h..3h+2 of a Hermitian 6x6 block times the 6-vector (own | other),
+// own = the 3 entries of this lane's spin.  `win` holds the lane's 27-real
+// window of the reordered packing:
+//   [d0 d1 d2 | L10 L20 L21 | L30 L31 L32 L40 L41 L42 L50 L51 L52 | d3 d4 d5 | L43 L53 L54]
+//   half 0 reads entries 0..26, half 1 reads entries 9..35.
+template <typename T>
+__device__ __forceinline__ void herm_rows(const T (&win)[27], int h, const cx<T> (&vo)[3], const cx<T> (&vx)[3],
+                                          cx<T> (&out)[3])
+{
+    T d[3], lo[6], Xr[9], Xi[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++) d[i] = h ? win[18 + i] : win[i];
+#pragma unroll
+    for (int i = 0; i < 6; i++) lo[i] = h ? win[21 + i] : win[3 + i];
+#pragma unroll
+    for (int m = 0; m < 9; m++) {
+        Xr[m] = h ? win[2 * m] : win[9 + 2 * m];
+        Xi[m] = h ? win[2 * m + 1] : win[10 + 2 * m];
+    }
+    const cx<T> l10 = {lo[0], lo[1]}, l20 = {lo[2], lo[3]}, l21 = {lo[4], lo[5]};
+    cx<T> own[3][3];
+    own[0][0] = {d[0], T(0)};
+    own[1][1] = {d[1], T(0)};
+    own[2][2] = {d[2], T(0)};
+    own[1][0] = l10;
+    own[2][0] = l20;
+    own[2][1] = l21;
+    own[0][1] = conj(l10);
+    own[0][2] = conj(l20);
+    own[1][2] = conj(l21);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        cx<T> s = {T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b < 3; b++) s = s + own[a][b] * vo[b];
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            // cross block: rows of this half, columns of the other half
+            cx<T> cb = h ? cx<T>{Xr[3 * a + b], Xi[3 * a + b]} : cx<T>{Xr[3 * b + a], -Xi[3 * b + a]};
+            s = s + cb * vx[b];
+        }
+        out[a] = s;
+    }
+}
+
+template <class P>
+__device__ __forceinline__ void load_window(const void* clov, int site, int q, typename P::real (&win)[27])
+{
+    const long base = ((long)site * 2 + (q >> 1)) * 36 + 9 * (q & 1);
+#pragma unroll
+    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + e);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src)
+{
+    return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
+{
+    return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
+}
+
+template <class P, int R, int EPI, int RED>
+__global__ __launch_bounds__(256) void hop_kernel(HopArgs a)
+{
+    using T = typename P::real;
+    if (a.stop && *a.stop) return;
+    const Geom g = a.g;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = threadIdx.x & 3;
+    const int site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
+    const bool valid = site < g.Vh;
+    const int gq = q >> 1, k = q & 1;
+    const int p = a.parity;
+    const long Vh = g.Vh;
+
+    cx<T> acc_u[3], acc_l[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) acc_u[c] = acc_l[c] = {T(0), T(0)};
+
+    if (valid) {
+        int x, y, z, t;
+        site_coords(g, site, p, x, y, z, t);
+        const int xh = site % g.Lxh;
+        const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
+        const int Sy = g.Lxh, Sz = g.Lxh * g.Ly, St = g.Lxh * g.Ly * g.Lz;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int mu = 2 * gq + j;
+            int fwd, bwd;
+            bool fcross = false, bcross = false;
+            T cre, cim;  // projection coefficient of the forward hop
+            if (j == 0) {
+                if (gq == 0) {  // x: the neighbour lies in the same row of the other parity
+                    const int row = site - xh;
+                    const int xp = (x + 1 == g.Lx) ? 0 : x + 1;
+                    const int xm = (x == 0) ? g.Lx - 1 : x - 1;
+                    fwd = row + (xp >> 1);
+                    bwd = row + (xm >> 1);
+                    cre = T(0);
+                    cim = T(-1);
+                } else {  // z
+                    fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
+                    bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
+                    cre = T(0);
+                    cim = k == 0 ? T(-1) : T(1);
+                }
+            } else {
+                if (gq == 0) {  // y
+                    fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
+                    bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
+                    cre = k == 0 ? T(1) : T(-1);
+                    cim = T(0);
+                } else {  // t
+                    fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
+                    bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
+                    fcross = (t + 1 == g.Lt);
+                    bcross = (t == 0);
+                    cre = T(-1);
+                    cim = T(0);
+                }
+            }
+#pragma unroll
+            for (int dir = 0; dir < 2; dir++) {
+                const int nb = dir == 0 ? fwd : bwd;
+                const T sc = dir == 0 ? T(1) : T(-1);  // (1 + g) on the backward hop flips c
+                const cx<T> cc = {sc * cre, sc * cim};
+                const long loff = dir == 0 ? ((long)(mu * 2 + p) * Vh + site) * R
+                                           : ((long)(mu * 2 + (1 - p)) * Vh + nb) * R;
+                cx<T> u[9];
+                load_link<P, R>(a.gauge, loff, u);
+                cx<T> hv[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const cx<T> pu = P::ld(a.psi, ((long)su * Vh + nb) * 3 + c);
+                    const cx<T> pl = P::ld(a.psi, ((long)sl * Vh + nb) * 3 + c);
+                    hv[c] = pu + cc * pl;
+                }
+                cx<T> w[3];
+#pragma unroll
+                for (int r = 0; r < 3; r++) {
+                    cx<T> s = {T(0), T(0)};
+#pragma unroll
+                    for (int c = 0; c < 3; c++) s = dir == 0 ? s + u[3 * r + c] * hv[c] : s + cmul_conj(u[3 * c + r], hv[c]);
+                    w[r] = s;
+                }
+                const bool flip = g.t_bc < 0 && (dir == 0 ? fcross : bcross);
+                const T fs = flip ? T(-1) : T(1);
+                const cx<T> cd = conj(cc);
+#pragma unroll
+                for (int r = 0; r < 3; r++) {
+                    const cx<T> wr = fs * w[r];
+                    acc_u[r] = acc_u[r] + wr;
+                    acc_l[r] = acc_l[r] + cd * wr;
+                }
+            }
+        }
+    }
+
+    // gather: lane q finishes spin q
+    const int lane = threadIdx.x & 63;
+    const int src = (lane & ~3) + (q < 2 ? q + 2 : 3 - q);
+    cx<T> res[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<T> mine = gq == 0 ? acc_u[c] : acc_l[c];
+        const cx<T> theirs = gq == 0 ? acc_l[c] : acc_u[c];
+        res[c] = mine + shfl_cx(theirs, src);
+    }
+
+    cx<T> outv[3];
+    cx<T> yv[3];
+    if constexpr (EPI == EPI_CLOV_XPAY || EPI == EPI_XPAY_CLOVY || RED == RED_TS) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) yv[c] = valid ? P::ld(a.y, ((long)q * Vh + site) * 3 + c) : cx<T>{T(0), T(0)};
+    }
+    if constexpr (EPI == EPI_NONE) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) outv[c] = res[c];
+    } else {
+        T win[27];
+        if (valid) {
+            load_window<P>(a.clov, site, q, win);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 27; e++) win[e] = T(0);
+        }
+        const T aa = (T)a.a;
+        if constexpr (EPI == EPI_XPAY_CLOVY) {
+            cx<T> ox[3], by[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(yv[c], 1);
+            herm_rows(win, q & 1, yv, ox, by);
+#pragma unroll
+            for (int c = 0; c < 3; c++) outv[c] = by[c] - aa * res[c];
+        } else {
+            cx<T> ox[3], br[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
+            herm_rows(win, q & 1, res, ox, br);
+            if constexpr (EPI == EPI_CLOV) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) outv[c] = br[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; c++) outv[c] = yv[c] - aa * br[c];
+            }
+        }
+    }
+
+    // reductions use the values as stored, so the solver's scalars match the
+    // vectors it reads back
+#pragma unroll
+    for (int c = 0; c < 3; c++) outv[c] = P::rt(outv[c]);
+    if (valid) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) P::st(a.out, ((long)q * Vh + site) * 3 + c, outv[c]);
+    }
+
+    if constexpr (RED != RED_NONE) {
+        double v[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const cx<T> o = outv[c];
+                if constexpr (RED == RED_WDOT) {
+                    const cx<T> wv = P::ld(a.w, ((long)q * Vh + site) * 3 + c);
+                    v[0] += (double)wv.re * o.re + (double)wv.im * o.im;
+                    v[1] += (double)wv.re * o.im - (double)wv.im * o.re;
+                } else {
+                    v[0] += (double)o.re * yv[c].re + (double)o.im * yv[c].im;
+                    v[1] += (double)o.re * yv[c].im - (double)o.im * yv[c].re;
+                    v[2] += (double)o.re * o.re + (double)o.im * o.im;
+                }
+            }
+        }
+        block_sum_store<3>(v, a.partials + 3 * (long)tile);
+    }
+}
+
+template <class P, int R>
+static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a)
+{
+    dim3 grid(hop_blocks(a.g.Vh)), block(256);
+#define QCDW_HOP_CASE(E, D)                                                   \
+    if (epi == E && red == D) {                                              \
+        hipLaunchKernelGGL((hop_kernel<P, R, E, D>), grid, block, 0, s, a);   \
+        return hipGetLastError();                                            \
+    }
+    QCDW_HOP_CASE(EPI_NONE, RED_NONE)
+    QCDW_HOP_CASE(EPI_CLOV, RED_NONE)
+    QCDW_HOP_CASE(EPI_CLOV_XPAY, RED_NONE)
+    QCDW_HOP_CASE(EPI_CLOV_XPAY, RED_WDOT)
+    QCDW_HOP_CASE(EPI_CLOV_XPAY, RED_TS)
+    QCDW_HOP_CASE(EPI_XPAY_CLOVY, RED_NONE)
+#undef QCDW_HOP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a)
+{
+    if (a.g.Vh <= 0) return hipSuccess;
+    if (recon == 18) {
+        if (prec == F64) return launch_hop_pr<P64, 9>(s, epi, red, a);
+        if (prec == F32) return launch_hop_pr<P32, 9>(s, epi, red, a);
+        return hipErrorInvalidValue;
+    }
+    switch (prec) {
+    case F64: return launch_hop_pr<P64, 6>(s, epi, red, a);
+    case F32: return launch_hop_pr<P32, 6>(s, epi, red, a);
+    case BF16: return launch_hop_pr<PBF16, 6>(s, epi, red, a);
+    case F16: return launch_hop_pr<PF16, 6>(s, epi, red, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace qcdw

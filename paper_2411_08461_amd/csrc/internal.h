@@ -1,0 +1,114 @@
+// Host-side internal interfaces of libqcdw: launch descriptors and launcher
+// declarations shared between the kernel files and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev.h"
+
+namespace qcdw {
+
+enum Prec { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
+
+inline int cplx_bytes(int prec) { return prec == F64 ? 16 : prec == F32 ? 8 : 4; }
+inline int real_bytes(int prec) { return prec == F64 ? 8 : prec == F32 ? 4 : 2; }
+
+// hop epilogues
+enum Epi {
+    EPI_NONE = 0,       // out = H psi
+    EPI_CLOV = 1,       // out = B (H psi)
+    EPI_CLOV_XPAY = 2,  // out = y - a B (H psi)
+    EPI_XPAY_CLOVY = 3  // out = B y - a (H psi)
+};
+// hop fused reductions (per-block partials)
+enum Red {
+    RED_NONE = 0,
+    RED_WDOT = 1,  // (w, out)              -> 2 doubles
+    RED_TS = 2     // (out, y), ||out||^2   -> 3 doubles
+};
+
+struct HopArgs {
+    const void* psi;    // input spinor, parity 1 - parity
+    void* out;          // output spinor, parity `parity`
+    const void* gauge;  // [4][2][Vh][R]
+    const void* clov;   // clover-type matrix of the output parity, [Vh][2][36] reordered
+    const void* y;      // xpay / dot operand on the output parity
+    const void* w;      // dot operand on the output parity
+    double a;           // xpay coefficient
+    double* partials;   // [nblocks][3]
+    Geom g;
+    int parity;
+    int nrhs;           // right-hand sides interleaved per site (1 or more)
+    const int* active;  // multi-RHS: per-RHS active flag (nullptr: all active)
+    const int* stop;    // if non-null and *stop != 0 the launch does nothing
+};
+
+constexpr int HOP_SITES_PER_BLOCK = 64;  // 4 lanes per site, 256 threads
+inline int hop_blocks(int Vh) { return (Vh + HOP_SITES_PER_BLOCK - 1) / HOP_SITES_PER_BLOCK; }
+
+hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a);
+
+// BiCGStab scalars kept on the device (complex values as re, im pairs)
+struct Scal {
+    double rho[2];    // (r0, r)
+    double alpha[2];
+    double omega[2];
+    double beta[2];
+    double rr;        // ||r||^2 of the iterated residual
+    double r0n2;      // ||r0||^2 (breakdown thresholds)
+    double stop_rr;   // convergence when rr <= stop_rr
+    double hist_norm; // history entry = sqrt(rr) * hist_norm
+    int iter;         // iterations completed
+    int flags;        // FLAG_* below
+    int fault_iter;   // > 0: force a breakdown when iter reaches this value
+    int hist_len;     // capacity of the device history
+};
+enum { FLAG_CONV = 1, FLAG_BREAK = 2, FLAG_NAN = 4 };
+
+constexpr int BLAS_THREADS = 256;
+// number of blocks used by the BLAS reductions on n complex elements
+inline int blas_blocks(long n)
+{
+    long b = (n + BLAS_THREADS * 4 - 1) / (BLAS_THREADS * 4);
+    if (b < 1) b = 1;
+    if (b > 2048) b = 2048;
+    return (int)b;
+}
+
+// generic reductions over n complex elements; results (doubles) land in out
+hipError_t launch_norm2(hipStream_t s, int prec, const void* x, long n, double* partials, double* out);
+hipError_t launch_xmy_norm2(hipStream_t s, int prec_b, int prec_y, const void* b, const void* y, void* r, long n,
+                            double* partials, double* out);  // r = b - y (FP64 r), out[0] = ||r||^2
+hipError_t launch_convert(hipStream_t s, int prec_in, int prec_out, const void* in, void* out, long n, double scale);
+hipError_t launch_axpy_hi(hipStream_t s, int prec_x, double a, const void* x, void* y, long n);  // y(f64) += a x
+hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, const void* clov, const void* in,
+                                      void* out);
+
+// BiCGStab iteration pieces
+hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev);
+hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S);
+hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S);
+hipError_t launch_bicg_xr(hipStream_t s, int prec, int prec_x, void* x, const void* p, const void* sv, void* r,
+                          const void* t, const void* r0, long n, const Scal* S, double* partials);
+hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb);
+hipError_t launch_fin_omega(hipStream_t s, Scal* S, const double* partials, int nb);
+hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int nb, double* hist);
+
+// pack / unpack between the paper layouts and the internal ones
+hipError_t launch_pack_spinor(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal,
+                              double scale);
+hipError_t launch_unpack_spinor(hipStream_t s, int prec, const Geom& g, const void* internal, int parity, void* paper,
+                                double scale);
+hipError_t launch_pack_gauge(hipStream_t s, int prec, int recon, const Geom& g, const void* paper, void* internal);
+hipError_t launch_pack_clover(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal);
+
+// clover kernels on the paper layouts (FP64)
+hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover);
+hipError_t launch_clover_apply(hipStream_t s, const Geom& g, const void* clover, const void* psi, void* out,
+                               double kappa, double csw);
+hipError_t launch_clover_invert(hipStream_t s, const Geom& g, const void* clover, double kappa, double csw,
+                                void* inv, int* notpd_count);
+// packed A = 1 - kappa csw C (paper clover layout) for the full-operator epilogue
+hipError_t launch_clover_to_A(hipStream_t s, const Geom& g, const void* clover, double kappa, double csw, void* A);
+
+}  // namespace qcdw

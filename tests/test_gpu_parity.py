@@ -1,0 +1,339 @@
+"""GPU parity: the HIP kernels, called through the C ABI, against the CPU oracle.
+
+FP64 kernels must agree with the oracle to 1e-13 (relative, max over the
+field); solves must reach an FP64 true residual <= 1e-10, recomputed by the
+oracle from the returned x.  Lattices include extents whose half volume is not
+a multiple of the 64-site tile (ragged tails) and antiperiodic time.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+import paper_2411_08461_amd as q
+
+pytestmark = pytest.mark.gpu
+
+# (L, ragged?)  Vh = 128, 144 (2.25 tiles), 720 (11.25 tiles), 4096
+SMALL = [(4, 4, 4, 4), (6, 4, 2, 6), (10, 6, 4, 6), (8, 8, 8, 16)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = q.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _gauge(L, eps=0.3, seed=0):
+    return li.random_gauge(L, eps, seed)
+
+
+@pytest.mark.parametrize("L", SMALL)
+def test_clover_build_matches_oracle(ctx, L):
+    U = _gauge(L, 0.4, 1)
+    lat = q.make_lattice(L)
+    C = torch.empty(oracle.packed_shape(L), dtype=torch.float64, device="cuda")
+    q.qcdw_clover_build(ctx, lat, dev(U), C)
+    expect = oracle.clover_build(L, U)
+    assert rel(host(C), expect) < 1e-13
+
+
+@pytest.mark.parametrize("L", SMALL[:3])
+def test_clover_apply_and_invert_match_oracle(ctx, L):
+    U = _gauge(L, 0.4, 2)
+    kappa, csw = 0.125, 1.1
+    Cn = oracle.clover_build(L, U)
+    lat = q.make_lattice(L)
+    C = dev(Cn)
+    psi = li.gaussian_source(L, 3)
+    out = torch.empty(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    q.qcdw_clover_apply(ctx, lat, C, dev(psi), out, kappa, csw)
+    assert rel(host(out), oracle.clover_apply(L, Cn, psi, kappa, csw)) < 1e-13
+    inv = torch.empty_like(C)
+    q.qcdw_clover_invert(ctx, lat, C, kappa, csw, inv)
+    inv_o, bad = oracle.clover_invert(L, Cn, kappa, csw)
+    assert bad == 0
+    assert rel(host(inv), inv_o) < 1e-13
+
+
+def test_clover_invert_reports_not_positive_definite(ctx):
+    L = (4, 4, 4, 4)
+    U = _gauge(L, 1.5, 4)
+    Cn = oracle.clover_build(L, U)
+    inv = torch.empty(Cn.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(q.QcdwError) as e:
+        q.qcdw_clover_invert(ctx, q.make_lattice(L), dev(Cn), 1.0, 50.0, inv)
+    assert e.value.status == q.QCDW_ENOTPD
+
+
+@pytest.mark.parametrize("L", SMALL)
+@pytest.mark.parametrize("t_bc", [1, -1])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_hop_parity_matches_oracle(ctx, L, t_bc, parity):
+    U = _gauge(L, 0.3, 5)
+    psi = li.gaussian_source(L, 6)
+    out = torch.empty(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    q.qcdw_hop(ctx, q.make_lattice(L, t_bc), dev(U), dev(psi), out, parity)
+    # oracle: H_{p,1-p} psi = hop of psi restricted to the other parity, on parity p
+    V = int(np.prod(L))
+    src = psi.reshape(V, 4, 3).copy()
+    src[parity * V // 2:(parity + 1) * V // 2] = 0
+    expect = oracle.hop(L, U, src.reshape(psi.shape), t_bc, out_parity=parity)
+    assert rel(host(out), expect) < 1e-13
+
+
+@pytest.mark.parametrize("L", SMALL)
+@pytest.mark.parametrize("t_bc", [1, -1])
+def test_dslash_full_operator_matches_oracle(ctx, L, t_bc):
+    U = _gauge(L, 0.3, 7)
+    kappa, csw = 0.124, 1.0
+    psi = li.gaussian_source(L, 8)
+    lat = q.make_lattice(L, t_bc)
+    out = torch.empty(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    q.qcdw_dslash(ctx, lat, dev(U), None, dev(psi), out, kappa, csw)
+    Cn = oracle.clover_build(L, U)
+    expect = oracle.dirac(L, U, Cn, psi, kappa, csw, t_bc)
+    assert rel(host(out), expect) < 1e-13
+    # with a caller-provided clover field
+    out2 = torch.empty_like(out)
+    q.qcdw_dslash(ctx, lat, dev(U), dev(Cn), dev(psi), out2, kappa, csw)
+    assert rel(host(out2), expect) < 1e-13
+
+
+@pytest.mark.parametrize("L", SMALL)
+@pytest.mark.parametrize("recon", [12, 18])
+def test_matpc_matches_oracle_schur(ctx, L, recon):
+    U = _gauge(L, 0.3, 9)
+    kappa, csw = 0.124, 1.0
+    lat = q.make_lattice(L)
+    op = q.Operator(ctx, lat, dev(U), kappa, csw, "f64", recon)
+    Vh = int(np.prod(L)) // 2
+    xe = li.gaussian_source(L, 10).reshape(-1, 4, 3)[:Vh].copy()
+    out = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_op_matpc(op, "f64", dev(xe), out)
+    Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), kappa, csw)
+    expect = oracle.schur_matpc(L, U, Ainv, xe, kappa)
+    assert rel(host(out), expect) < 1e-13
+    op.close()
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 2e-2), ("f16", 4e-3)])
+def test_matpc_low_precision_error_bounded(ctx, prec, bound):
+    """16-bit / FP32 storage with FP32 arithmetic against the FP64 oracle."""
+    L = (8, 8, 8, 16)
+    U = _gauge(L, 0.2, 11)
+    kappa, csw = 0.124, 1.0
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, prec, 12)
+    Vh = int(np.prod(L)) // 2
+    xe = li.gaussian_source(L, 12).reshape(-1, 4, 3)[:Vh].copy()
+    out = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_op_matpc(op, prec, dev(xe), out)
+    Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), kappa, csw)
+    expect = oracle.schur_matpc(L, U, Ainv, xe, kappa)
+    err = np.linalg.norm(host(out) - expect) / np.linalg.norm(expect)
+    print(f"matpc {prec} relative error {err:.3e}")
+    assert err < bound
+    op.close()
+
+
+# ---------------------------------------------------------------------------
+# solver
+# ---------------------------------------------------------------------------
+
+
+def _oracle_true_res(L, U, x, b, kappa, csw, t_bc=1):
+    Cn = oracle.clover_build(L, U)
+    r = b - oracle.dirac(L, U, Cn, x, kappa, csw, t_bc)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def test_invert_dense_lu_4444(ctx):
+    """4^4, kappa 0.12, csw 1, eps 0.3, point source: GPU solve vs LAPACK dense LU."""
+    w = li.WORKLOADS["dense4"]
+    L = w["L"]
+    U = li.random_gauge(L, w["eps"], w["seed"])
+    b = li.point_source(L)
+    Cn = oracle.clover_build(L, U)
+    M = oracle.dense_matrix(L, U, Cn, w["kappa"], w["csw"])
+    x_lu = np.linalg.solve(M, b.ravel())
+    cond = np.linalg.cond(M)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), w["kappa"], w["csw"])
+    x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(tol=1e-10))
+    print(info)
+    assert info.status == q.QCDW_OK
+    xh = host(x)
+    assert info.true_res <= 1e-10
+    assert _oracle_true_res(L, U, xh, b, w["kappa"], w["csw"]) <= 1e-10
+    assert np.linalg.norm(xh.ravel() - x_lu) / np.linalg.norm(x_lu) <= cond * 1e-10
+    assert info.res_hist[0] == pytest.approx(np.linalg.norm(
+        oracle.schur_source(L, U, oracle.clover_invert(L, Cn, w["kappa"], w["csw"])[0], b, w["kappa"]))
+        / np.linalg.norm(b), rel=1e-12)
+    op.close()
+
+
+@pytest.mark.parametrize("L,t_bc", [((6, 4, 2, 6), 1), ((10, 6, 4, 6), -1), ((8, 8, 8, 16), 1)])
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16", "f16"])
+def test_invert_reaches_tolerance(ctx, L, t_bc, inner):
+    U = _gauge(L, 0.25, 13)
+    kappa, csw = 0.122, 1.0
+    b = li.gaussian_source(L, 14)
+    op = q.Operator(ctx, q.make_lattice(L, t_bc), dev(U), kappa, csw, inner)
+    x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(tol=1e-10, inner=inner, delta=0.1 if inner == "f32" else 0.2))
+    print(inner, info)
+    assert info.status == q.QCDW_OK
+    tr = _oracle_true_res(L, U, host(x), b, kappa, csw, t_bc)
+    print(f"oracle true residual {tr:.3e}")
+    assert tr <= 1e-10
+    ref = oracle.bicgstab(L, U, oracle.clover_build(L, U), b, kappa, csw, tol=1e-12, maxiter=5000, t_bc=t_bc)
+    assert ref.status == 0
+    err = np.linalg.norm(host(x) - ref.x) / np.linalg.norm(ref.x)
+    print(f"solution error vs oracle {err:.3e}")
+    assert err < 1e-8
+    op.close()
+
+
+def test_invert_statuses_and_restarts(ctx):
+    L = (8, 8, 8, 16)
+    U = _gauge(L, 0.25, 15)
+    kappa, csw = 0.122, 1.0
+    b = li.gaussian_source(L, 16)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw)
+    x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(maxiter=3))
+    assert info.status == q.QCDW_ENOCONV and info.iters == 3 and info.true_res > 1e-10
+    bn = b.copy()
+    bn.ravel()[5] = np.nan
+    x.zero_()
+    info = q.qcdw_invert(op, dev(bn), x, q.make_params())
+    assert info.status == q.QCDW_ENAN
+    x.fill_(1.0)
+    info = q.qcdw_invert(op, torch.zeros_like(x), x, q.make_params())
+    assert info.status == q.QCDW_OK and float(x.abs().max()) == 0.0
+    x.zero_()
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(fault_inject=5))
+    assert info.status == q.QCDW_OK and info.n_restarts == 1
+    assert _oracle_true_res(L, U, host(x), b, kappa, csw) <= 1e-10
+    # resume from a good guess: converges in (almost) no iterations
+    info2 = q.qcdw_invert(op, dev(b), x, q.make_params())
+    assert info2.status == q.QCDW_OK and info2.iters <= 2
+    op.close()
+
+
+def test_invert_is_deterministic(ctx):
+    L = (10, 6, 4, 6)
+    U = _gauge(L, 0.25, 17)
+    b = li.gaussian_source(L, 18)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), 0.122, 1.0)
+    xs, its = [], []
+    for _ in range(3):
+        x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+        info = q.qcdw_invert(op, dev(b), x, q.make_params())
+        xs.append(host(x))
+        its.append(info.iters)
+    assert its[0] == its[1] == its[2]
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    op.close()
+
+
+# ---------------------------------------------------------------------------
+# invariants checked on the GPU operator itself
+# ---------------------------------------------------------------------------
+
+
+def test_gpu_free_field_plane_wave(ctx):
+    L = (8, 4, 6, 8)
+    kappa = 0.11
+    U = li.unit_gauge(L)
+    c = oracle.coords_table(L)
+    g = [oracle.gamma(m) for m in range(4)]
+    rng = np.random.default_rng(3)
+    n = np.array([1, 3, 2, 5])
+    p = 2 * np.pi * n / np.asarray(L)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    phase = np.exp(1j * (c @ p))
+    psi = (phase[:, None, None] * u[None]).reshape(li.fermion_shape(L))
+    out = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    q.qcdw_dslash(ctx, q.make_lattice(L), dev(U), None, dev(psi), out, kappa, 1.7)
+    K = (1 - 2 * kappa * np.cos(p).sum()) * np.eye(4) + 2j * kappa * sum(g[m] * np.sin(p[m]) for m in range(4))
+    expect = (phase[:, None, None] * (K @ u)[None]).reshape(psi.shape)
+    assert rel(host(out), expect) < 1e-14
+
+
+def test_gpu_gamma5_hermiticity(ctx):
+    L = (6, 4, 2, 6)
+    U = _gauge(L, 0.4, 19)
+    kappa, csw = 0.124, 1.2
+    chi = li.gaussian_source(L, 20)
+    psi = li.gaussian_source(L, 21)
+    g5 = np.array([1, 1, -1, -1])[:, None]
+    lat = q.make_lattice(L)
+
+    def M(v):
+        out = torch.empty(v.shape, dtype=torch.complex128, device="cuda")
+        q.qcdw_dslash(ctx, lat, dev(U), None, dev(v), out, kappa, csw)
+        return host(out)
+
+    lhs = np.vdot(chi, g5 * M(g5 * psi))
+    rhs = np.vdot(M(chi), psi)
+    assert abs(lhs - rhs) / abs(rhs) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# workload sizes of the benchmark
+# ---------------------------------------------------------------------------
+
+
+@pytest.fixture(scope="module")
+def wc16():
+    w = li.WORKLOADS["wc16x32"]
+    L = w["L"]
+    U = li.random_gauge(L, w["eps"], w["seed"])
+    b = li.z2_source(L, w["source_seed"])
+    return L, U, b, w
+
+
+def test_wc16x32_matpc_full_size(ctx, wc16):
+    """16^3x32: the benchmark's FP64 reconstruct-12 M_hat against the oracle on every site."""
+    L, U, b, w = wc16
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), w["kappa"], w["csw"])
+    Vh = int(np.prod(L)) // 2
+    xe = b.reshape(-1, 4, 3)[:Vh].copy()
+    out = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_op_matpc(op, "f64", dev(xe), out)
+    Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), w["kappa"], w["csw"])
+    expect = oracle.schur_matpc(L, U, Ainv, xe, w["kappa"])
+    assert rel(host(out), expect) < 1e-13
+    op.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16", "f16"])
+def test_wc16x32_solve(ctx, wc16, inner):
+    """16^3x32, kappa 0.124, Z2 source: every precision reaches the FP64 true residual 1e-10."""
+    L, U, b, w = wc16
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), w["kappa"], w["csw"], inner)
+    x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(tol=1e-10, inner=inner, delta=0.1 if inner != "f16" else 0.2))
+    print(inner, info)
+    assert info.status == q.QCDW_OK
+    tr = _oracle_true_res(L, U, host(x), b, w["kappa"], w["csw"])
+    print(f"oracle true residual {tr:.3e}")
+    assert tr <= 1e-10
+    op.close()
