@@ -62,14 +62,49 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--inner", default="bf16", choices=["f32", "bf16", "f16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--eager", action="store_true", help="launch the iteration kernels eagerly instead of "
+                    "replaying captured hipGraphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-lattice", default="24,24,24,64",
                     help="also time the hop kernel on this lattice (empty to skip)")
+    ap.add_argument("--matpc-only", default="",
+                    help="profiling mode: a 256 MiB device copy (counter calibration), then a few M_hat "
+                         "applications in FP64 and BF16 on this lattice, e.g. 24,24,24,64; prints nothing else")
     return ap.parse_args()
+
+
+def matpc_only(L):
+    import numpy as np
+    import torch
+
+    import lattice_inputs as li
+    import paper_2411_08461_amd as q
+
+    src = torch.empty(32 * 2 ** 20, dtype=torch.float64, device="cuda")  # 256 MiB
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    Vh = int(np.prod(L)) // 2
+    U = torch.from_numpy(li.random_gauge(L, 0.2, 0)).cuda()
+    xe = torch.from_numpy(li.z2_source(L, 1000).reshape(-1, 4, 3)[:Vh].copy()).cuda()
+    out = torch.empty_like(xe)
+    ctx = q.Context(0)
+    op = q.Operator(ctx, q.make_lattice(L), U, 0.125, 1.1, "bf16", 12)
+    for prec in ("f64", "bf16"):
+        for _ in range(3):
+            q.qcdw_op_matpc(op, prec, xe, out)
+    torch.cuda.synchronize()
+    op.close()
+    ctx.close()
+    print(json.dumps({"matpc_only": list(L), "copy_bytes": 2 * src.numel() * 8}))
 
 
 def main():
     args = parse()
+    if args.matpc_only:
+        matpc_only([int(v) for v in args.matpc_only.split(",")])
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
               "decomposition is a design note, not part of this build)", file=sys.stderr)
@@ -94,9 +129,9 @@ def main():
     xlo = torch.zeros_like(bd)
     torch.cuda.synchronize()
 
-    p64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True)
+    p64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", use_graph=not args.eager)
     plo = q.make_params(tol=1e-10, maxiter=20000, inner=args.inner, delta=0.1 if args.inner != "f16" else 0.2,
-                        collect_timing=True)
+                        use_graph=not args.eager)
 
     def step():
         op = q.Operator(ctx, lat, Ud, kappa, csw, args.inner, 12)
@@ -120,15 +155,30 @@ def main():
                       for i64, ilo in infos)
     value = total_bytes / elapsed / 1e9
 
-    # dominant kernel: the FP64 hop into odd sites with fused A^-1 (two launches per iteration)
-    ms_a = sum(i64.hop_ms[0] for i64, _ in infos)
-    n_a = sum(i64.n_hop[0] for i64, _ in infos)
+    # roofline of the dominant kernel, the FP64 hop into odd sites with fused A_oo^-1 (two launches
+    # per iteration): the same solves again, launched eagerly, every hop dispatch timed by HIP events
+    # that the dispatch itself records on the library's stream
+    t64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True)
+    tlo = q.make_params(tol=1e-10, maxiter=20000, inner=args.inner, delta=plo.delta, collect_timing=True)
+    op = q.Operator(ctx, lat, Ud, kappa, csw, args.inner, 12)
+    timed = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        x64.zero_()
+        xlo.zero_()
+        timed.append((q.qcdw_invert(op, bd, x64, t64, raise_on_error=True),
+                      q.qcdw_invert(op, bd, xlo, tlo, raise_on_error=True)))
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    op.close()
+    ms_a = sum(i64.hop_ms[0] for i64, _ in timed)
+    n_a = sum(i64.n_hop[0] for i64, _ in timed)
     avg_a_ms = ms_a / max(n_a, 1)
     achieved = hop_a_bytes("f64") * Vh / (avg_a_ms * 1e-3) / 1e9
-    ms_b = sum(i64.hop_ms[1] + i64.hop_ms[2] for i64, _ in infos)
-    n_b = sum(i64.n_hop[1] + i64.n_hop[2] for i64, _ in infos)
-    ms_alo = sum(ilo.hop_ms[0] for _, ilo in infos)
-    n_alo = sum(ilo.n_hop[0] for _, ilo in infos)
+    ms_b = sum(i64.hop_ms[1] + i64.hop_ms[2] for i64, _ in timed)
+    n_b = sum(i64.n_hop[1] + i64.n_hop[2] for i64, _ in timed)
+    ms_alo = sum(ilo.hop_ms[0] for _, ilo in timed)
+    n_alo = sum(ilo.n_hop[0] for _, ilo in timed)
     lo_gbs = hop_a_bytes(args.inner) * Vh / (ms_alo / max(n_alo, 1) * 1e-3) / 1e9
 
     i64, ilo = infos[-1]
@@ -149,7 +199,7 @@ def main():
                    "lattice": list(L), "kappa": kappa, "csw": csw, "tol": 1e-10, "inner": args.inner},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "hop_kernel<P64, r12, EPI_CLOV, RED_NONE>",
+                     "kernel": "hop_kernel<P64, r12, EPI_CLOV, RED_NONE>", "launches_timed": n_a,
                      "bytes_per_launch": hop_a_bytes("f64") * Vh, "avg_launch_us": round(avg_a_ms * 1e3, 2)},
         "solve": {
             "f64": {"iters": i64.iters, "true_res": i64.true_res, "time_ms": round(i64.time_ms, 3),
@@ -157,6 +207,8 @@ def main():
             args.inner: {"iters": ilo.iters, "true_res": ilo.true_res, "time_ms": round(ilo.time_ms, 3),
                          "reliable": ilo.n_reliable},
             "speedup_mixed": round(i64.time_ms / ilo.time_ms, 3),
+            "graph": not args.eager,
+            "eager_instrumented_ms_per_step": round(eager_ms, 3),
         },
         "hop_gbs": {"f64_into_odd": round(achieved, 1),
                     "f64_into_even_xpay": round((hop_b_bytes("f64") + SPINOR["f64"] / 2) * Vh /
@@ -164,6 +216,7 @@ def main():
                     f"{args.inner}_into_odd": round(lo_gbs, 1)},
     }
 
+    result["stream_gbs"] = stream_probe(torch)
     if args.extra_lattice:
         result["hop_gbs_large"] = time_large_hop(q, li, np, torch, ctx, [int(v) for v in args.extra_lattice.split(",")])
 
@@ -173,6 +226,27 @@ def main():
     print(json.dumps(result))
     sys.stdout.flush()
     ctx.close()
+
+
+def stream_probe(torch):
+    """Context only: what plain torch copy / sum kernels reach on this GPU (1 GiB operands)."""
+    a = torch.empty(128 * 2 ** 20, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * a.numel() * 8),
+                             ("read_sum", lambda: a.sum(), a.numel() * 8)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(10 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_large_hop(q, li, np, torch, ctx, L):

@@ -78,8 +78,13 @@ typedef struct {
                               iterated residual has fallen by this factor (mixed precision) */
     int32_t check_every;   /* host polls convergence every this many iterations (>= 1) */
     int32_t max_restarts;  /* restarts allowed after a breakdown */
-    int32_t collect_timing;/* 1: time every hop launch with HIP events (eager path) */
+    int32_t collect_timing;/* 1: time every hop launch of the iteration with HIP events recorded by
+                              the dispatch itself; forces eager launches (use_graph ignored) */
     int32_t fault_inject;  /* tests only: > 0 forces a breakdown at that iteration */
+    int32_t use_graph;     /* 1: each chunk of check_every iterations is captured once into a
+                              hipGraph (cached on the operator) and replayed; 0: eager launches.
+                              Both run the same kernels in the same order (bitwise equal x). */
+    int32_t pad_;
 } qcdw_solver_params;
 
 typedef struct {
@@ -101,7 +106,7 @@ typedef struct {
 } qcdw_solve_info;
 
 /* Defaults: tol 1e-10, maxiter 10000, inner F64, delta 0.1, check_every 8,
-   max_restarts 8, collect_timing 0, fault_inject 0. */
+   max_restarts 8, collect_timing 0, fault_inject 0, use_graph 1. */
 void qcdw_solver_params_default(qcdw_solver_params *p);
 
 /* Context bound to one device and one HIP stream (hipStream_t, may be NULL for

@@ -57,6 +57,8 @@ class qcdw_solver_params(ctypes.Structure):
         ("max_restarts", ctypes.c_int32),
         ("collect_timing", ctypes.c_int32),
         ("fault_inject", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -307,7 +309,7 @@ class SolveInfo:
 
 
 def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8, max_restarts=8,
-                collect_timing=False, fault_inject=0) -> qcdw_solver_params:
+                collect_timing=False, fault_inject=0, use_graph=True) -> qcdw_solver_params:
     prm = qcdw_solver_params_default()
     prm.tol = float(tol)
     prm.maxiter = int(maxiter)
@@ -317,6 +319,7 @@ def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8,
     prm.max_restarts = int(max_restarts)
     prm.collect_timing = 1 if collect_timing else 0
     prm.fault_inject = int(fault_inject)
+    prm.use_graph = 1 if use_graph else 0
     return prm
 
 

@@ -21,6 +21,7 @@ using namespace qcdw;
 struct qcdw_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
     std::string err;
     Scal* host_scal = nullptr;  // pinned
     double* host_d = nullptr;   // pinned, 64 doubles
@@ -144,6 +145,23 @@ struct qcdw_op {
     DevBuf xlo;    // FP32 correction (mixed precision)
     DevBuf partials, scal, dres, hist;
     int kr_prec = -1;
+    int ws_gen = 0;  // bumped whenever a workspace buffer is (re)allocated
+    // captured iteration chunks, replayed by the solver
+    struct Graph {
+        int kprec, chunk, gen;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    void drop_graphs()
+    {
+        for (auto& gr : graphs) {
+            if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+            if (gr.graph) (void)hipGraphDestroy(gr.graph);
+        }
+        graphs.clear();
+    }
+    ~qcdw_op() { drop_graphs(); }
 };
 
 namespace {
@@ -221,6 +239,8 @@ void qcdw_solver_params_default(qcdw_solver_params* p)
     p->max_restarts = 8;
     p->collect_timing = 0;
     p->fault_inject = 0;
+    p->use_graph = 1;
+    p->pad_ = 0;
 }
 
 qcdw_status qcdw_ctx_create(qcdw_ctx** ctx, int device, void* hip_stream)
@@ -236,7 +256,8 @@ qcdw_status qcdw_ctx_create(qcdw_ctx** ctx, int device, void* hip_stream)
     c->stream = (hipStream_t)hip_stream;
     if (hipHostMalloc((void**)&c->host_scal, sizeof(Scal)) != hipSuccess ||
         hipHostMalloc((void**)&c->host_d, 64 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&c->dev_int, 64 * sizeof(int)) != hipSuccess) {
+        hipMalloc((void**)&c->dev_int, 64 * sizeof(int)) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         qcdw_ctx_destroy(c);
         return QCDW_ENOMEM;
     }
@@ -252,6 +273,7 @@ void qcdw_ctx_destroy(qcdw_ctx* ctx)
     if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
     if (ctx->host_d) (void)hipHostFree(ctx->host_d);
     if (ctx->dev_int) (void)hipFree(ctx->dev_int);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -522,6 +544,8 @@ struct Timing {
             if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) == hipSuccess) {
                 ms[kind[k]] += t;
                 launches[kind[k]]++;
+            } else {
+                (void)hipGetLastError();
             }
         }
         used = 0;
@@ -537,18 +561,17 @@ struct Solver {
     int nb_hop, nb_blas;
     Timing tm;
 
-    hipError_t timed_hop(int prec, int recon, int epi, int red, const HopArgs& a)
+    hipError_t timed_hop(hipStream_t st, int prec, int recon, int epi, int red, const HopArgs& a)
     {
-        if (!tm.on) return launch_hop(s, prec, recon, epi, red, a);
-        tm.kind.push_back(epi == EPI_CLOV ? 0 : (red == RED_WDOT ? 1 : 2));
-        (void)hipEventRecord(tm.get(), s);
-        hipError_t e = launch_hop(s, prec, recon, epi, red, a);
-        (void)hipEventRecord(tm.get(), s);
-        return e;
+        const int kind = epi == EPI_CLOV ? 0 : (red == RED_WDOT ? 1 : 2);
+        if (!tm.on) return launch_hop(st, prec, recon, epi, red, a);
+        tm.kind.push_back(kind);
+        hipEvent_t e0 = tm.get(), e1 = tm.get();
+        return launch_hop(st, prec, recon, epi, red, a, e0, e1);
     }
 
-    hipError_t matpc_t(const PrecView& v, const void* in, void* out, void* tmp_o, int red, const void* w,
-                       double* partials, const int* stop)
+    hipError_t matpc_t(hipStream_t st, const PrecView& v, const void* in, void* out, void* tmp_o, int red,
+                       const void* w, double* partials, const int* stop)
     {
         HopArgs a = hop_args(op->g, 1);
         a.psi = in;
@@ -556,7 +579,7 @@ struct Solver {
         a.gauge = v.gauge;
         a.clov = v.Ainv[1];
         a.stop = stop;
-        hipError_t e = timed_hop(v.prec, v.recon, EPI_CLOV, RED_NONE, a);
+        hipError_t e = timed_hop(st, v.prec, v.recon, EPI_CLOV, RED_NONE, a);
         if (e != hipSuccess) return e;
         HopArgs b = hop_args(op->g, 0);
         b.psi = tmp_o;
@@ -568,7 +591,63 @@ struct Solver {
         b.a = op->kappa * op->kappa;
         b.partials = partials;
         b.stop = stop;
-        return timed_hop(v.prec, v.recon, EPI_CLOV_XPAY, red, b);
+        return timed_hop(st, v.prec, v.recon, EPI_CLOV_XPAY, red, b);
+    }
+
+    // one BiCGStab iteration on M_hat in the Krylov precision (van der Vorst 1992):
+    //   v = M p, alpha = rho / (r0, v), s = r - alpha v, t = M s, omega = (t, s) / (t, t),
+    //   x += alpha p + omega s, r = s - omega t, beta = (rho'/rho)(alpha/omega), p = r + beta (p - omega v)
+    hipError_t enqueue_iters(hipStream_t st, int nit, int kprec, int xprec, void* xk)
+    {
+        const PrecView vk = view(op, kprec);
+        void *r = op->kr[0].p, *r0 = op->kr[1].p, *p = op->kr[2].p, *vv = op->kr[3].p, *sv = op->kr[4].p,
+             *t = op->kr[5].p, *tmpo = op->kr[6].p;
+        Scal* dS = (Scal*)op->scal.p;
+        double* dpart = (double*)op->partials.p;
+        const int* stop = &dS->flags;
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < nit && e == hipSuccess; i++) {
+            e = matpc_t(st, vk, p, vv, tmpo, RED_WDOT, r0, dpart, stop);
+            if (e == hipSuccess) e = launch_fin_alpha(st, dS, dpart, nb_hop);
+            if (e == hipSuccess) e = launch_bicg_s(st, kprec, sv, r, vv, n, dS);
+            if (e == hipSuccess) e = matpc_t(st, vk, sv, t, tmpo, RED_TS, nullptr, dpart, stop);
+            if (e == hipSuccess) e = launch_fin_omega(st, dS, dpart, nb_hop);
+            if (e == hipSuccess) e = launch_bicg_xr(st, kprec, xprec, xk, p, sv, r, t, r0, n, dS, dpart);
+            if (e == hipSuccess) e = launch_fin_beta(st, dS, dpart, nb_blas, (double*)op->hist.p);
+            if (e == hipSuccess) e = launch_bicg_p(st, kprec, p, r, vv, n, dS);
+        }
+        return e;
+    }
+
+    // run nit iterations: eagerly, or by replaying a captured graph of exactly nit iterations
+    qcdw_status run_chunk(int nit, int kprec, int xprec, void* xk, bool graph)
+    {
+        if (!graph) {
+            HIPCHK(ctx, enqueue_iters(s, nit, kprec, xprec, xk));
+            return QCDW_OK;
+        }
+        qcdw_op::Graph* gr = nullptr;
+        for (auto& cand : op->graphs)
+            if (cand.kprec == kprec && cand.chunk == nit && cand.gen == op->ws_gen)
+                gr = &cand;
+        if (!gr) {
+            op->graphs.emplace_back();
+            gr = &op->graphs.back();
+            gr->kprec = kprec;
+            gr->chunk = nit;
+            gr->gen = op->ws_gen;
+            hipStream_t cs = ctx->cap_stream;
+            HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_iters(cs, nit, kprec, xprec, xk);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            HIPCHK(ctx, e);
+            HIPCHK(ctx, e2);
+            gr->graph = g;
+            HIPCHK(ctx, hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0));
+        }
+        HIPCHK(ctx, hipGraphLaunch(gr->exec, s));
+        return QCDW_OK;
     }
 
     // rhi = bhat - M_hat xhi in FP64; returns ||rhi||^2
@@ -587,6 +666,10 @@ qcdw_status ensure_workspace(qcdw_op* op, int kprec, int maxiter)
     qcdw_ctx* ctx = op->ctx;
     const long n = 12L * op->g.Vh;
     const size_t b64 = n * 16;
+    std::vector<void*> before;
+    DevBuf* all[] = {&op->kr[0], &op->kr[1], &op->kr[2], &op->kr[3], &op->kr[4], &op->kr[5], &op->kr[6], &op->xlo,
+                     &op->xhi, &op->partials, &op->scal, &op->dres, &op->hist};
+    for (DevBuf* b : all) before.push_back(b->p);
     DevBuf* f64bufs[] = {&op->be, &op->bo, &op->yo, &op->ye, &op->bhat, &op->xhi, &op->rhi, &op->tmp64, &op->tmpo64};
     for (DevBuf* b : f64bufs) HIPCHK(ctx, b->alloc(b64));
     for (auto& b : op->kr) HIPCHK(ctx, b.alloc(n * cplx_bytes(kprec)));
@@ -596,6 +679,12 @@ qcdw_status ensure_workspace(qcdw_op* op, int kprec, int maxiter)
     HIPCHK(ctx, op->dres.alloc(64 * sizeof(double)));
     HIPCHK(ctx, op->hist.alloc(((size_t)maxiter + 2) * sizeof(double)));
     op->kr_prec = kprec;
+    for (size_t i = 0; i < before.size(); i++)
+        if (all[i]->p != before[i]) {
+            op->ws_gen++;
+            op->drop_graphs();
+            break;
+        }
     return QCDW_OK;
 }
 
@@ -634,6 +723,7 @@ extern "C" qcdw_status qcdw_invert(qcdw_op* op, const void* b, void* x, const qc
 
     Solver S{op, ctx, ctx->stream, 12L * op->g.Vh, hop_blocks(op->g.Vh), blas_blocks(12L * op->g.Vh)};
     S.tm.on = prm.collect_timing != 0;
+    const bool use_graph = prm.use_graph != 0 && !S.tm.on;  // per-launch timing needs eager launches
     hipStream_t s = ctx->stream;
     const Geom& g = op->g;
     const long n = S.n;
@@ -734,11 +824,9 @@ extern "C" qcdw_status qcdw_invert(qcdw_op* op, const void* b, void* x, const qc
 
         // --- one Krylov cycle on M_hat c = rhi --------------------------
         const bool mixed = kprec != F64;
-        const PrecView vk = view(op, kprec);
         const double rhi_norm = std::sqrt(rr_hi);
         const double scale = mixed ? std::sqrt((double)n) / rhi_norm : 1.0;
-        void *r = op->kr[0].p, *r0 = op->kr[1].p, *p = op->kr[2].p, *vv = op->kr[3].p, *sv = op->kr[4].p,
-             *t = op->kr[5].p, *tmpo = op->kr[6].p;
+        void *r = op->kr[0].p, *r0 = op->kr[1].p, *p = op->kr[2].p;
         void* xk = mixed ? op->xlo.p : op->xhi.p;
         const int xprec = mixed ? F32 : F64;
         HIPCHK(ctx, launch_convert(s, F64, kprec, op->rhi.p, r, n, scale));
@@ -757,21 +845,11 @@ extern "C" qcdw_status qcdw_invert(qcdw_op* op, const void* b, void* x, const qc
         hs->hist_len = maxiter + 2;
         HIPCHK(ctx, hipMemcpyAsync(dS, hs, sizeof(Scal), hipMemcpyHostToDevice, s));
         HIPCHK(ctx, launch_bicg_init(s, dS, dres));
-        const int* stop = &dS->flags;
         int flags = 0;
         while (true) {
             const int chunk = std::min(prm.check_every, maxiter - iters);
             if (chunk <= 0) break;
-            for (int i = 0; i < chunk; i++) {
-                HIPCHK(ctx, S.matpc_t(vk, p, vv, tmpo, RED_WDOT, r0, dpart, stop));
-                HIPCHK(ctx, launch_fin_alpha(s, dS, dpart, S.nb_hop));
-                HIPCHK(ctx, launch_bicg_s(s, kprec, sv, r, vv, n, dS));
-                HIPCHK(ctx, S.matpc_t(vk, sv, t, tmpo, RED_TS, nullptr, dpart, stop));
-                HIPCHK(ctx, launch_fin_omega(s, dS, dpart, S.nb_hop));
-                HIPCHK(ctx, launch_bicg_xr(s, kprec, xprec, xk, p, sv, r, t, r0, n, dS, dpart));
-                HIPCHK(ctx, launch_fin_beta(s, dS, dpart, S.nb_blas, dhist));
-                HIPCHK(ctx, launch_bicg_p(s, kprec, p, r, vv, n, dS));
-            }
+            CHK(S.run_chunk(chunk, kprec, xprec, xk, use_graph));
             HIPCHK(ctx, hipMemcpyAsync(hs, dS, sizeof(Scal), hipMemcpyDeviceToHost, s));
             HIPCHK(ctx, hipStreamSynchronize(s));
             const int done_now = hs->iter - iters;

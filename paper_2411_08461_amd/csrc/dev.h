@@ -162,8 +162,14 @@ __device__ __forceinline__ void site_coords(const Geom& g, int i, int p, int& x,
 // block mapping: consecutive logical tiles on one XCD (workgroups are
 // dispatched round-robin over the 8 XCDs, each with its own L2)
 // ---------------------------------------------------------------------------
+#ifndef QCDW_XCD_REMAP
+#define QCDW_XCD_REMAP 1
+#endif
 __device__ __forceinline__ int xcd_tile(int b, int nblk)
 {
+#if !QCDW_XCD_REMAP
+    return b;
+#endif
     const int nx = 8;
     int per = nblk / nx, rem = nblk % nx;
     int xcd = b % nx, k = b / nx;

@@ -14,7 +14,21 @@
 // spins (6 complex) of each neighbour plus the link, and owns partial sums of
 // two output spins; one in-quad shuffle gives lane q the finished spin q.
 // That keeps register use low and gives 4 Vh threads per launch.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
+
+#ifndef QCDW_HOP_PREFETCH
+#define QCDW_HOP_PREFETCH 0
+#endif
+#ifndef QCDW_HOP_WAVES_PER_EU
+#define QCDW_HOP_WAVES_PER_EU 0
+#endif
+#if QCDW_HOP_WAVES_PER_EU > 0
+#define QCDW_HOP_ATTR __attribute__((amdgpu_waves_per_eu(QCDW_HOP_WAVES_PER_EU, QCDW_HOP_WAVES_PER_EU)))
+#else
+#define QCDW_HOP_ATTR
+#endif
 
 namespace qcdw {
 
@@ -99,7 +113,7 @@ __device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
 }
 
 template <class P, int R, int EPI, int RED>
-__global__ __launch_bounds__(256) void hop_kernel(HopArgs a)
+__global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
 {
     using T = typename P::real;
     if (a.stop && *a.stop) return;
@@ -122,12 +136,16 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs a)
         const int xh = site % g.Lxh;
         const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
         const int Sy = g.Lxh, Sz = g.Lxh * g.Ly, St = g.Lxh * g.Ly * g.Lz;
+        // the four hops of this lane: h = 2 j + dir, mu = 2 gq + j, dir 0 forward / 1 backward
+        int nbh[4];
+        long loff[4];
+        T cre[4], cim[4], fsg[4];
 #pragma unroll
         for (int j = 0; j < 2; j++) {
             const int mu = 2 * gq + j;
             int fwd, bwd;
             bool fcross = false, bcross = false;
-            T cre, cim;  // projection coefficient of the forward hop
+            T c_re, c_im;  // projection coefficient of the forward hop
             if (j == 0) {
                 if (gq == 0) {  // x: the neighbour lies in the same row of the other parity
                     const int row = site - xh;
@@ -135,62 +153,98 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs a)
                     const int xm = (x == 0) ? g.Lx - 1 : x - 1;
                     fwd = row + (xp >> 1);
                     bwd = row + (xm >> 1);
-                    cre = T(0);
-                    cim = T(-1);
+                    c_re = T(0);
+                    c_im = T(-1);
                 } else {  // z
                     fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
                     bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
-                    cre = T(0);
-                    cim = k == 0 ? T(-1) : T(1);
+                    c_re = T(0);
+                    c_im = k == 0 ? T(-1) : T(1);
                 }
             } else {
                 if (gq == 0) {  // y
                     fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
                     bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
-                    cre = k == 0 ? T(1) : T(-1);
-                    cim = T(0);
+                    c_re = k == 0 ? T(1) : T(-1);
+                    c_im = T(0);
                 } else {  // t
                     fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
                     bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
                     fcross = (t + 1 == g.Lt);
                     bcross = (t == 0);
-                    cre = T(-1);
-                    cim = T(0);
+                    c_re = T(-1);
+                    c_im = T(0);
                 }
             }
+            // forward: U_mu(x) psi(x+mu) with (1 - g_mu); backward: U_mu(x-mu)^+ psi(x-mu)
+            // with (1 + g_mu), which flips the projection coefficient
+            nbh[2 * j] = fwd;
+            nbh[2 * j + 1] = bwd;
+            loff[2 * j] = ((long)(mu * 2 + p) * Vh + site) * R;
+            loff[2 * j + 1] = ((long)(mu * 2 + (1 - p)) * Vh + bwd) * R;
+            cre[2 * j] = c_re;
+            cim[2 * j] = c_im;
+            cre[2 * j + 1] = -c_re;
+            cim[2 * j + 1] = -c_im;
+            fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
+            fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
+        }
+#if QCDW_HOP_PREFETCH
+        // issue every load of the four hops before any arithmetic
+        cx<T> ur[4][R], pu[4][3], pl[4][3];
 #pragma unroll
-            for (int dir = 0; dir < 2; dir++) {
-                const int nb = dir == 0 ? fwd : bwd;
-                const T sc = dir == 0 ? T(1) : T(-1);  // (1 + g) on the backward hop flips c
-                const cx<T> cc = {sc * cre, sc * cim};
-                const long loff = dir == 0 ? ((long)(mu * 2 + p) * Vh + site) * R
-                                           : ((long)(mu * 2 + (1 - p)) * Vh + nb) * R;
-                cx<T> u[9];
-                load_link<P, R>(a.gauge, loff, u);
-                cx<T> hv[3];
+        for (int h = 0; h < 4; h++) {
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const cx<T> pu = P::ld(a.psi, ((long)su * Vh + nb) * 3 + c);
-                    const cx<T> pl = P::ld(a.psi, ((long)sl * Vh + nb) * 3 + c);
-                    hv[c] = pu + cc * pl;
-                }
-                cx<T> w[3];
+            for (int e = 0; e < R; e++) ur[h][e] = P::ld(a.gauge, loff[h] + e);
 #pragma unroll
-                for (int r = 0; r < 3; r++) {
-                    cx<T> s = {T(0), T(0)};
+            for (int c = 0; c < 3; c++) {
+                pu[h][c] = P::ld(a.psi, ((long)su * Vh + nbh[h]) * 3 + c);
+                pl[h][c] = P::ld(a.psi, ((long)sl * Vh + nbh[h]) * 3 + c);
+            }
+        }
+#endif
 #pragma unroll
-                    for (int c = 0; c < 3; c++) s = dir == 0 ? s + u[3 * r + c] * hv[c] : s + cmul_conj(u[3 * c + r], hv[c]);
-                    w[r] = s;
-                }
-                const bool flip = g.t_bc < 0 && (dir == 0 ? fcross : bcross);
-                const T fs = flip ? T(-1) : T(1);
-                const cx<T> cd = conj(cc);
+        for (int h = 0; h < 4; h++) {
+            const int dir = h & 1;
+            const cx<T> cc = {cre[h], cim[h]};
+            cx<T> u[9];
+#if QCDW_HOP_PREFETCH
 #pragma unroll
-                for (int r = 0; r < 3; r++) {
-                    const cx<T> wr = fs * w[r];
-                    acc_u[r] = acc_u[r] + wr;
-                    acc_l[r] = acc_l[r] + cd * wr;
-                }
+            for (int e = 0; e < R; e++) u[e] = ur[h][e];
+            if constexpr (R == 6) {
+                u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+                u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+                u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+            }
+#else
+            load_link<P, R>(a.gauge, loff[h], u);
+#endif
+            cx<T> hv[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+#if QCDW_HOP_PREFETCH
+                hv[c] = pu[h][c] + cc * pl[h][c];
+#else
+                const cx<T> pu_ = P::ld(a.psi, ((long)su * Vh + nbh[h]) * 3 + c);
+                const cx<T> pl_ = P::ld(a.psi, ((long)sl * Vh + nbh[h]) * 3 + c);
+                hv[c] = pu_ + cc * pl_;
+#endif
+            }
+            cx<T> w[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                cx<T> sacc = {T(0), T(0)};
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    sacc = dir == 0 ? sacc + u[3 * r + c] * hv[c] : sacc + cmul_conj(u[3 * c + r], hv[c]);
+                w[r] = sacc;
+            }
+            const cx<T> cd = conj(cc);
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                const cx<T> wr = fsg[h] * w[r];
+                acc_u[r] = acc_u[r] + wr;
+                acc_l[r] = acc_l[r] + cd * wr;
             }
         }
     }
@@ -277,13 +331,17 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs a)
 }
 
 template <class P, int R>
-static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a)
+static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
     dim3 grid(hop_blocks(a.g.Vh)), block(256);
-#define QCDW_HOP_CASE(E, D)                                                   \
-    if (epi == E && red == D) {                                              \
-        hipLaunchKernelGGL((hop_kernel<P, R, E, D>), grid, block, 0, s, a);   \
-        return hipGetLastError();                                            \
+    // with events, they are recorded by the dispatch itself (exact kernel time)
+#define QCDW_HOP_CASE(E, D)                                                                          \
+    if (epi == E && red == D) {                                                                     \
+        if (e0)                                                                                     \
+            hipExtLaunchKernelGGL((hop_kernel<P, R, E, D>), grid, block, 0, s, e0, e1, 0, a);        \
+        else                                                                                        \
+            hipLaunchKernelGGL((hop_kernel<P, R, E, D>), grid, block, 0, s, a);                      \
+        return hipGetLastError();                                                                   \
     }
     QCDW_HOP_CASE(EPI_NONE, RED_NONE)
     QCDW_HOP_CASE(EPI_CLOV, RED_NONE)
@@ -295,19 +353,20 @@ static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a)
+hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a, hipEvent_t e0,
+                      hipEvent_t e1)
 {
     if (a.g.Vh <= 0) return hipSuccess;
     if (recon == 18) {
-        if (prec == F64) return launch_hop_pr<P64, 9>(s, epi, red, a);
-        if (prec == F32) return launch_hop_pr<P32, 9>(s, epi, red, a);
+        if (prec == F64) return launch_hop_pr<P64, 9>(s, epi, red, a, e0, e1);
+        if (prec == F32) return launch_hop_pr<P32, 9>(s, epi, red, a, e0, e1);
         return hipErrorInvalidValue;
     }
     switch (prec) {
-    case F64: return launch_hop_pr<P64, 6>(s, epi, red, a);
-    case F32: return launch_hop_pr<P32, 6>(s, epi, red, a);
-    case BF16: return launch_hop_pr<PBF16, 6>(s, epi, red, a);
-    case F16: return launch_hop_pr<PF16, 6>(s, epi, red, a);
+    case F64: return launch_hop_pr<P64, 6>(s, epi, red, a, e0, e1);
+    case F32: return launch_hop_pr<P32, 6>(s, epi, red, a, e0, e1);
+    case BF16: return launch_hop_pr<PBF16, 6>(s, epi, red, a, e0, e1);
+    case F16: return launch_hop_pr<PF16, 6>(s, epi, red, a, e0, e1);
     }
     return hipErrorInvalidValue;
 }

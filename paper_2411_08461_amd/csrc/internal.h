@@ -46,7 +46,9 @@ struct HopArgs {
 constexpr int HOP_SITES_PER_BLOCK = 64;  // 4 lanes per site, 256 threads
 inline int hop_blocks(int Vh) { return (Vh + HOP_SITES_PER_BLOCK - 1) / HOP_SITES_PER_BLOCK; }
 
-hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a);
+// e0/e1: optional events recorded by the kernel dispatch itself (timing)
+hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // BiCGStab scalars kept on the device (complex values as re, im pairs)
 struct Scal {

@@ -337,3 +337,32 @@ def test_wc16x32_solve(ctx, wc16, inner):
     print(f"oracle true residual {tr:.3e}")
     assert tr <= 1e-10
     op.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "bf16"])
+def test_graph_replay_matches_eager(ctx, inner):
+    """Graph-replayed iteration chunks give bitwise the same solve as eager launches.
+
+    Several solves alternate between the two paths (with the program's own eager
+    work and synchronisations in between), so every replay of the cached graphs
+    is checked against the eager result.
+    """
+    L = (8, 8, 8, 16)
+    U = _gauge(L, 0.25, 23)
+    b = li.gaussian_source(L, 24)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), 0.122, 1.0, inner)
+    ref = None
+    for rep in range(3):
+        for graph in (False, True):
+            x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+            info = q.qcdw_invert(op, dev(b), x, q.make_params(inner=inner, delta=0.2, check_every=5,
+                                                             use_graph=graph))
+            torch.cuda.synchronize()
+            assert info.status == q.QCDW_OK
+            xh = host(x)
+            if ref is None:
+                ref = (xh, info.iters, info.res_hist)
+            assert np.array_equal(xh, ref[0]) and info.iters == ref[1], (rep, graph)
+            assert info.res_hist == ref[2]
+            _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+    op.close()
