@@ -51,6 +51,7 @@ extern "C" {
 
 typedef struct qcdw_ctx qcdw_ctx;
 typedef struct qcdw_op qcdw_op;
+typedef struct qcdw_batch qcdw_batch;
 
 typedef struct {
     int32_t L[4];  /* Lx, Ly, Lz, Lt: each even and >= 2 */
@@ -156,6 +157,11 @@ void qcdw_op_destroy(qcdw_op *op);
    the result is returned in FP64. */
 qcdw_status qcdw_op_matpc(qcdw_op *op, qcdw_prec prec, const void *in_e, void *out_e);
 
+/* The same for nrhs (1..16) stacked even-site fields, with the multi-RHS hop
+   kernel (each link and clover entry loaded once per site for all RHS).
+   Reconstruct-12 operators only. */
+qcdw_status qcdw_op_matpc_multi(qcdw_op *op, qcdw_prec prec, int nrhs, const void *in_e, void *out_e);
+
 /* Solve M x = b (fermion layout).  x holds the initial guess on entry (zeros
    for none) and the solution on exit; it is written on QCDW_OK and
    QCDW_ENOCONV (best iterate).  info is always filled.  The acceptance test is
@@ -163,12 +169,30 @@ qcdw_status qcdw_op_matpc(qcdw_op *op, qcdw_prec prec, const void *in_e, void *o
 qcdw_status qcdw_invert(qcdw_op *op, const void *b, void *x, const qcdw_solver_params *params,
                         qcdw_solve_info *info);
 
-/* nrhs right-hand sides solved together (Sec. III.B: a propagator is 12
-   solves).  b, x: nrhs consecutive fermion fields.  info: nrhs entries.  The
-   hop kernel applies each link to all right-hand sides of a site in one
-   launch; each RHS keeps its own recurrence and stops on its own. */
+/* nrhs (1..16) right-hand sides solved together (Sec. III.B: a propagator is
+   12 solves).  b, x: nrhs consecutive fermion fields.  info: nrhs entries.
+   Every launch of the iteration serves all RHS (one multi-RHS hop per parity
+   block applies each link to all RHS of a site; of its two forms, links held
+   in registers or re-read from L2, the faster is picked by timing on first
+   use); each RHS keeps its own BiCGStab scalars, targets and flags, and stops
+   on its own (masked). */
 qcdw_status qcdw_invert_multi(qcdw_op *op, int nrhs, const void *b, void *x, const qcdw_solver_params *params,
                               qcdw_solve_info *info);
+
+/* Batched solves of different operators (lattice sizes, kappas) in lockstep.
+   A batch references 1..64 reconstruct-12 operators of one context with the
+   same inner precision (they must outlive it) and owns the solver workspace.
+   Every launch of the iteration serves all problems: the hop kernels are
+   persistent grids that walk a device table of the problems' tiles, with the
+   grid size picked by timing candidates on first use (cached on the context,
+   and in the file named by $QCDW_TUNE_CACHE when set, the role of the paper's
+   tuning-cache resource_path, Sec. III.B).  Finished problems are masked. */
+qcdw_status qcdw_batch_create(qcdw_ctx *ctx, int n, qcdw_op *const ops[], qcdw_batch **batch);
+void qcdw_batch_destroy(qcdw_batch *batch);
+/* b[k], x[k]: fermion fields of operator k (x: initial guess in, solution out);
+   info: n entries.  Same conventions as qcdw_invert for each problem. */
+qcdw_status qcdw_invert_batch(qcdw_batch *batch, const void *const b[], void *const x[],
+                              const qcdw_solver_params *params, qcdw_solve_info *info);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,8 @@ PREC = {"f64": QCDW_F64, "f32": QCDW_F32, "bf16": QCDW_BF16, "f16": QCDW_F16}
 EXPORTED = (
     "qcdw_solver_params_default", "qcdw_ctx_create", "qcdw_ctx_destroy", "qcdw_last_error", "qcdw_ctx_set_stream",
     "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_op_create",
-    "qcdw_op_destroy", "qcdw_op_matpc", "qcdw_invert", "qcdw_invert_multi",
+    "qcdw_op_destroy", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
+    "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
 )
 
 
@@ -106,8 +107,13 @@ def load_library(path: str = LIB_PATH):
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_destroy": (None, [p]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
+        "qcdw_op_matpc_multi": (i, [p, i, i, p, p]),
         "qcdw_invert": (i, [p, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
         "qcdw_invert_multi": (i, [p, i, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
+        "qcdw_batch_create": (i, [p, i, ctypes.POINTER(p), ctypes.POINTER(p)]),
+        "qcdw_batch_destroy": (None, [p]),
+        "qcdw_invert_batch": (i, [p, ctypes.POINTER(p), ctypes.POINTER(p), ctypes.POINTER(qcdw_solver_params),
+                                  ctypes.POINTER(qcdw_solve_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -289,6 +295,17 @@ def qcdw_op_matpc(op: Operator, prec, in_e, out_e) -> None:
     _check(op.ctx.handle, st)
 
 
+def qcdw_op_matpc_multi(op: Operator, prec, in_e, out_e) -> None:
+    """M_hat on nrhs = in_e.shape[0] stacked even-site fields with the multi-RHS kernel."""
+    prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    nrhs = int(in_e.shape[0])
+    _need(in_e, 6 * op.volume * nrhs, "in_e")
+    _need(out_e, 6 * op.volume * nrhs, "out_e")
+    st = load_library().qcdw_op_matpc_multi(op.handle, prec, nrhs, _ptr(in_e, torch.complex128, "in_e"),
+                                            _ptr(out_e, torch.complex128, "out_e"))
+    _check(op.ctx.handle, st)
+
+
 class SolveInfo:
     def __init__(self, info: qcdw_solve_info, hist):
         self.status = info.status
@@ -361,3 +378,59 @@ def qcdw_invert_multi(op: Operator, b, x, params: qcdw_solver_params | None = No
     if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
         _check(op.ctx.handle, st)
     return [SolveInfo(infos[k], hists[k]) for k in range(nrhs)]
+
+
+class Batch:
+    """qcdw_batch: operators of different lattices / kappas solved in lockstep."""
+
+    def __init__(self, ctx: Context, ops):
+        self.ctx = ctx
+        self.ops = list(ops)  # keep the operators alive
+        arr = (ctypes.c_void_p * len(self.ops))(*[o.handle.value for o in self.ops])
+        h = ctypes.c_void_p()
+        st = load_library().qcdw_batch_create(ctx.handle, len(self.ops), arr, ctypes.byref(h))
+        _check(ctx.handle, st)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().qcdw_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qcdw_batch_create(ctx: Context, ops) -> Batch:
+    return Batch(ctx, ops)
+
+
+def qcdw_batch_destroy(batch: Batch) -> None:
+    batch.close()
+
+
+def qcdw_invert_batch(batch: Batch, bs, xs, params: qcdw_solver_params | None = None):
+    """Solve M_k x_k = b_k for every operator of the batch; returns a list of SolveInfo."""
+    if params is None:
+        params = make_params()
+    n = len(batch.ops)
+    if len(bs) != n or len(xs) != n:
+        raise ValueError("one source and one solution per operator")
+    for k, op in enumerate(batch.ops):
+        _need(bs[k], 12 * op.volume, f"b[{k}]")
+        _need(xs[k], 12 * op.volume, f"x[{k}]")
+    barr = (ctypes.c_void_p * n)(*[_ptr(t, torch.complex128, "b").value for t in bs])
+    xarr = (ctypes.c_void_p * n)(*[_ptr(t, torch.complex128, "x").value for t in xs])
+    n_hist = max(1, params.maxiter + 2)
+    hists = [(ctypes.c_double * n_hist)() for _ in range(n)]
+    infos = (qcdw_solve_info * n)()
+    for k in range(n):
+        infos[k].hist_len = n_hist
+        infos[k].res_hist = ctypes.cast(hists[k], ctypes.POINTER(ctypes.c_double))
+    st = load_library().qcdw_invert_batch(batch.handle, barr, xarr, ctypes.byref(params), infos)
+    if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
+        _check(batch.ctx.handle, st)
+    return [SolveInfo(infos[k], hists[k]) for k in range(n)]

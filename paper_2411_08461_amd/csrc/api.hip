@@ -9,7 +9,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -18,14 +21,40 @@
 
 using namespace qcdw;
 
+// pinned host staging sizes: a solve has at most 64 problems (batch) and needs
+// one Scal and two doubles per problem
+constexpr int HOST_SCAL_N = 64;
+constexpr int HOST_D_N = 256;
+
 struct qcdw_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
     std::string err;
-    Scal* host_scal = nullptr;  // pinned
-    double* host_d = nullptr;   // pinned, 64 doubles
+    Scal* host_scal = nullptr;  // pinned, HOST_SCAL_N entries (one per problem of a solve)
+    double* host_d = nullptr;   // pinned, HOST_D_N doubles (per-problem scalars, 2 per problem)
     int* dev_int = nullptr;
+    // launch-parameter tuning cache (the role of the paper's resource_path):
+    // "key value" lines, kept in memory and in $QCDW_TUNE_CACHE when set
+    std::map<std::string, int> tune;
+    std::string tune_path;
+    void tune_load()
+    {
+        const char* p = getenv("QCDW_TUNE_CACHE");
+        if (!p || !*p) return;
+        tune_path = p;
+        std::ifstream f(tune_path);
+        std::string k;
+        int v;
+        while (f >> k >> v) tune[k] = v;
+    }
+    void tune_store(const std::string& k, int v)
+    {
+        tune[k] = v;
+        if (tune_path.empty()) return;
+        std::ofstream f(tune_path, std::ios::trunc);
+        for (auto& kv : tune) f << kv.first << " " << kv.second << "\n";
+    }
 };
 
 namespace {
@@ -131,24 +160,16 @@ qcdw_status check_dev(qcdw_ctx* ctx, const void* p, const char* name)
 // ---------------------------------------------------------------------------
 // operator object
 // ---------------------------------------------------------------------------
-struct qcdw_op {
-    qcdw_ctx* ctx = nullptr;
-    Geom g{};
-    double kappa = 0, csw = 0;
-    int inner = F64;
-    int recon = 12;
-    DevBuf gauge64, gauge_lo;
-    DevBuf Ainv64[2], Ainv_lo[2], A64[2];
-    // solver workspace (allocated on first use)
-    DevBuf be, bo, yo, ye, bhat, xhi, rhi, tmp64, tmpo64;
+// Solver workspace: stacked/concatenated vectors of all problems of a solve,
+// scalars, partials, and the graphs captured over them.
+struct Workspace {
+    DevBuf be, bo, yo, ye, bhat, xhi, rhi, tmp64, tmpo64;  // FP64, per problem
     DevBuf kr[7];  // r, r0, p, v, s, t, tmp_o in the Krylov precision
     DevBuf xlo;    // FP32 correction (mixed precision)
-    DevBuf partials, scal, dres, hist;
-    int kr_prec = -1;
-    int ws_gen = 0;  // bumped whenever a workspace buffer is (re)allocated
-    // captured iteration chunks, replayed by the solver
+    DevBuf partials, scal, dres, hist, coef;
+    int ws_gen = 0;  // bumped whenever a buffer is (re)allocated
     struct Graph {
-        int kprec, chunk, gen;
+        int kprec, chunk, nprob, variant, gen;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     };
@@ -161,7 +182,30 @@ struct qcdw_op {
         }
         graphs.clear();
     }
-    ~qcdw_op() { drop_graphs(); }
+    ~Workspace() { drop_graphs(); }
+};
+
+struct qcdw_op {
+    qcdw_ctx* ctx = nullptr;
+    Geom g{};
+    double kappa = 0, csw = 0;
+    int inner = F64;
+    int recon = 12;
+    DevBuf gauge64, gauge_lo;
+    DevBuf Ainv64[2], Ainv_lo[2], A64[2];
+    Workspace ws;  // single- and multi-RHS solves
+};
+
+// a set of operators solved together (different lattices and kappas)
+struct qcdw_batch {
+    qcdw_ctx* ctx = nullptr;
+    std::vector<qcdw_op*> ops;
+    int inner = F64;
+    std::vector<long> off, len;  // element offsets / lengths of each problem in concatenated vectors
+    long total = 0, nmax = 0;
+    int total_tiles = 0, nbmax = 0;
+    DevBuf map, nbs, tab64, tablo;  // device: (off, len) pairs, hop tiles per problem, BatchEntry tables
+    Workspace ws;
 };
 
 namespace {
@@ -254,13 +298,14 @@ qcdw_status qcdw_ctx_create(qcdw_ctx** ctx, int device, void* hip_stream)
     qcdw_ctx* c = new qcdw_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    if (hipHostMalloc((void**)&c->host_scal, sizeof(Scal)) != hipSuccess ||
-        hipHostMalloc((void**)&c->host_d, 64 * sizeof(double)) != hipSuccess ||
+    if (hipHostMalloc((void**)&c->host_scal, HOST_SCAL_N * sizeof(Scal)) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_d, HOST_D_N * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&c->dev_int, 64 * sizeof(int)) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         qcdw_ctx_destroy(c);
         return QCDW_ENOMEM;
     }
+    c->tune_load();
     *ctx = c;
     return QCDW_OK;
 }
@@ -509,6 +554,53 @@ qcdw_status qcdw_op_matpc(qcdw_op* op, qcdw_prec prec, const void* in_e, void* o
     return QCDW_OK;
 }
 
+qcdw_status qcdw_op_matpc_multi(qcdw_op* op, qcdw_prec prec, int nrhs, const void* in_e, void* out_e)
+{
+    if (!op) return QCDW_EINVAL;
+    qcdw_ctx* ctx = op->ctx;
+    DeviceGuard dg(ctx->device);
+    CHK(check_dev(ctx, in_e, "in_e"));
+    CHK(check_dev(ctx, out_e, "out_e"));
+    if (nrhs < 1 || nrhs > 16) return fail(ctx, QCDW_EINVAL, "nrhs must lie in [1, 16]");
+    if (prec != QCDW_F64 && prec != (qcdw_prec)op->inner)
+        return fail(ctx, QCDW_EINVAL, "prec must be F64 or the operator's inner precision");
+    if (op->recon != 12 && prec == QCDW_F64)
+        return fail(ctx, QCDW_EINVAL, "the multi-RHS kernel uses reconstruct-12 links");
+    const Geom& g = op->g;
+    const long n = 12L * g.Vh;
+    const size_t half = (size_t)n * 16;  // bytes of one even-site FP64 field
+    DevBuf in, out, tmp;
+    HIPCHK(ctx, in.alloc(nrhs * n * cplx_bytes(prec)));
+    HIPCHK(ctx, out.alloc(nrhs * n * cplx_bytes(prec)));
+    HIPCHK(ctx, tmp.alloc(nrhs * n * cplx_bytes(prec)));
+    hipStream_t s = ctx->stream;
+    const PrecView v = view(op, prec);
+    for (int k = 0; k < nrhs; k++)
+        HIPCHK(ctx, launch_pack_spinor(s, prec, g, (const char*)in_e + k * half, 0,
+                                       (char*)in.p + (size_t)k * n * cplx_bytes(prec), 1.0));
+    HopArgs a = hop_args(g, 1);
+    a.psi = in.p;
+    a.out = tmp.p;
+    a.gauge = v.gauge;
+    a.clov = v.Ainv[1];
+    a.nrhs = nrhs;
+    HIPCHK(ctx, launch_hop_mrhs(s, prec, EPI_CLOV, RED_NONE, a, nullptr));
+    HopArgs b2 = hop_args(g, 0);
+    b2.psi = tmp.p;
+    b2.out = out.p;
+    b2.gauge = v.gauge;
+    b2.clov = v.Ainv[0];
+    b2.y = in.p;
+    b2.a = op->kappa * op->kappa;
+    b2.nrhs = nrhs;
+    HIPCHK(ctx, launch_hop_mrhs(s, prec, EPI_CLOV_XPAY, RED_NONE, b2, nullptr));
+    for (int k = 0; k < nrhs; k++)
+        HIPCHK(ctx, launch_unpack_spinor(s, prec, g, (const char*)out.p + (size_t)k * n * cplx_bytes(prec), 0,
+                                         (char*)out_e + k * half, 1.0));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return QCDW_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -553,70 +645,184 @@ struct Timing {
     }
 };
 
+constexpr int MAX_RHS = 16;
+constexpr int MAX_BATCH = 64;
+static_assert(HOST_SCAL_N >= MAX_BATCH && HOST_D_N >= 2 * MAX_BATCH && MAX_RHS <= MAX_BATCH,
+              "pinned staging buffers must hold every problem of a solve");
+
+// The problems of one solve: nprob right-hand sides of one operator (multi-RHS,
+// batch == nullptr) or the operators of a batch (one RHS each).
 struct Solver {
-    qcdw_op* op;
     qcdw_ctx* ctx;
+    Workspace& W;
+    std::vector<qcdw_op*> ops;  // per problem
+    qcdw_batch* batch;          // non-null for batched solves
     hipStream_t s;
-    long n;  // complex elements of a half-lattice spinor
-    int nb_hop, nb_blas;
+    int nprob;
+    std::vector<long> off, len;  // element offsets / lengths (complex) of each problem
+    long nmax;                   // longest problem
+    int nb_hop;                  // hop partials stride per problem
+    int nb_blas;                 // BLAS partials per problem
+    const long2* map;            // device (off, len) per problem (batch) or nullptr (uniform)
+    const int* nbs;              // device hop tiles per problem (batch) or nullptr
+    int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse) or batch grid
     Timing tm;
 
-    hipError_t timed_hop(hipStream_t st, int prec, int recon, int epi, int red, const HopArgs& a)
+    Solver(qcdw_ctx* c, Workspace& w, std::vector<qcdw_op*> o, qcdw_batch* b)
+        : ctx(c), W(w), ops(std::move(o)), batch(b), s(c->stream), nprob((int)ops.size())
+    {
+        if (batch) {
+            off = batch->off;
+            len = batch->len;
+            nmax = batch->nmax;
+            nb_hop = batch->nbmax;
+            map = (const long2*)batch->map.p;
+            nbs = (const int*)batch->nbs.p;
+        } else {
+            const long n = 12L * ops[0]->g.Vh;
+            for (int k = 0; k < nprob; k++) {
+                off.push_back(k * n);
+                len.push_back(n);
+            }
+            nmax = n;
+            nb_hop = hop_blocks(ops[0]->g.Vh);
+            map = nullptr;
+            nbs = nullptr;
+        }
+        nb_blas = blas_blocks(nmax);
+    }
+    long n0() const { return len[0]; }  // uniform length (multi-RHS)
+
+    void* at(const DevBuf& b, int k) const { return (char*)b.p + (size_t)off[k] * 16; }
+
+    hipError_t hop(hipStream_t st, int prec, int epi, int red, const void* psi, void* out, const void* y,
+                   const void* w, double* partials, const Scal* S, int parity)
     {
         const int kind = epi == EPI_CLOV ? 0 : (red == RED_WDOT ? 1 : 2);
-        if (!tm.on) return launch_hop(st, prec, recon, epi, red, a);
-        tm.kind.push_back(kind);
-        hipEvent_t e0 = tm.get(), e1 = tm.get();
-        return launch_hop(st, prec, recon, epi, red, a, e0, e1);
-    }
-
-    hipError_t matpc_t(hipStream_t st, const PrecView& v, const void* in, void* out, void* tmp_o, int red,
-                       const void* w, double* partials, const int* stop)
-    {
-        HopArgs a = hop_args(op->g, 1);
-        a.psi = in;
-        a.out = tmp_o;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tm.on) {
+            tm.kind.push_back(kind);
+            e0 = tm.get();
+            e1 = tm.get();
+        }
+        if (batch) {
+            BatchHopArgs b{};
+            b.tab = (const BatchEntry*)(prec == F64 ? batch->tab64.p : batch->tablo.p);
+            b.nprob = nprob;
+            b.total_tiles = batch->total_tiles;
+            b.parity = parity;
+            b.nbmax = batch->nbmax;
+            b.use_kappa2 = epi == EPI_CLOV_XPAY;
+            b.psi = psi;
+            b.out = out;
+            b.y = y;
+            b.w = w;
+            b.partials = partials;
+            b.S = S;
+            return launch_hop_batch(st, prec, epi, red, b, variant, e0, e1);
+        }
+        const qcdw_op* op = ops[0];
+        const PrecView v = view(op, prec);
+        HopArgs a = hop_args(op->g, parity);
+        a.psi = psi;
+        a.out = out;
         a.gauge = v.gauge;
-        a.clov = v.Ainv[1];
-        a.stop = stop;
-        hipError_t e = timed_hop(st, v.prec, v.recon, EPI_CLOV, RED_NONE, a);
-        if (e != hipSuccess) return e;
-        HopArgs b = hop_args(op->g, 0);
-        b.psi = tmp_o;
-        b.out = out;
-        b.gauge = v.gauge;
-        b.clov = v.Ainv[0];
-        b.y = in;
-        b.w = w;
-        b.a = op->kappa * op->kappa;
-        b.partials = partials;
-        b.stop = stop;
-        return timed_hop(st, v.prec, v.recon, EPI_CLOV_XPAY, red, b);
+        a.clov = v.Ainv[parity];
+        a.y = y;
+        a.w = w;
+        a.a = op->kappa * op->kappa;
+        a.partials = partials;
+        a.stop = S ? &S->flags : nullptr;
+        a.nrhs = nprob;
+        if (nprob > 1)
+            return variant == 1 ? launch_hop_rhs(st, prec, epi, red, a, S, e0, e1)
+                                : launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
+        return launch_hop(st, prec, v.recon, epi, red, a, e0, e1);
     }
 
-    // one BiCGStab iteration on M_hat in the Krylov precision (van der Vorst 1992):
+    // one BiCGStab iteration on M_hat for every problem in the Krylov precision (van der Vorst 1992):
     //   v = M p, alpha = rho / (r0, v), s = r - alpha v, t = M s, omega = (t, s) / (t, t),
     //   x += alpha p + omega s, r = s - omega t, beta = (rho'/rho)(alpha/omega), p = r + beta (p - omega v)
     hipError_t enqueue_iters(hipStream_t st, int nit, int kprec, int xprec, void* xk)
     {
-        const PrecView vk = view(op, kprec);
-        void *r = op->kr[0].p, *r0 = op->kr[1].p, *p = op->kr[2].p, *vv = op->kr[3].p, *sv = op->kr[4].p,
-             *t = op->kr[5].p, *tmpo = op->kr[6].p;
-        Scal* dS = (Scal*)op->scal.p;
-        double* dpart = (double*)op->partials.p;
-        const int* stop = &dS->flags;
+        void *r = W.kr[0].p, *r0 = W.kr[1].p, *p = W.kr[2].p, *vv = W.kr[3].p, *sv = W.kr[4].p, *t = W.kr[5].p,
+             *tmpo = W.kr[6].p;
+        Scal* dS = (Scal*)W.scal.p;
+        double* dpart = (double*)W.partials.p;
+        const long n = n0();
         hipError_t e = hipSuccess;
         for (int i = 0; i < nit && e == hipSuccess; i++) {
-            e = matpc_t(st, vk, p, vv, tmpo, RED_WDOT, r0, dpart, stop);
-            if (e == hipSuccess) e = launch_fin_alpha(st, dS, dpart, nb_hop);
-            if (e == hipSuccess) e = launch_bicg_s(st, kprec, sv, r, vv, n, dS);
-            if (e == hipSuccess) e = matpc_t(st, vk, sv, t, tmpo, RED_TS, nullptr, dpart, stop);
-            if (e == hipSuccess) e = launch_fin_omega(st, dS, dpart, nb_hop);
-            if (e == hipSuccess) e = launch_bicg_xr(st, kprec, xprec, xk, p, sv, r, t, r0, n, dS, dpart);
-            if (e == hipSuccess) e = launch_fin_beta(st, dS, dpart, nb_blas, (double*)op->hist.p);
-            if (e == hipSuccess) e = launch_bicg_p(st, kprec, p, r, vv, n, dS);
+            e = hop(st, kprec, EPI_CLOV, RED_NONE, p, tmpo, nullptr, nullptr, nullptr, dS, 1);
+            if (e == hipSuccess) e = hop(st, kprec, EPI_CLOV_XPAY, RED_WDOT, tmpo, vv, p, r0, dpart, dS, 0);
+            if (e == hipSuccess) e = launch_fin_alpha(st, dS, dpart, nb_hop, nprob, nbs);
+            if (e == hipSuccess) e = launch_bicg_s(st, kprec, sv, r, vv, n, dS, nprob, map, nmax);
+            if (e == hipSuccess) e = hop(st, kprec, EPI_CLOV, RED_NONE, sv, tmpo, nullptr, nullptr, nullptr, dS, 1);
+            if (e == hipSuccess) e = hop(st, kprec, EPI_CLOV_XPAY, RED_TS, tmpo, t, sv, nullptr, dpart, dS, 0);
+            if (e == hipSuccess) e = launch_fin_omega(st, dS, dpart, nb_hop, nprob, nbs);
+            if (e == hipSuccess)
+                e = launch_bicg_xr(st, kprec, xprec, xk, p, sv, r, t, r0, n, dS, dpart, nprob, map, nmax);
+            if (e == hipSuccess) e = launch_fin_beta(st, dS, dpart, nb_blas, (double*)W.hist.p, nprob);
+            if (e == hipSuccess) e = launch_bicg_p(st, kprec, p, r, vv, n, dS, nprob, map, nmax);
         }
         return e;
+    }
+
+    // pick the multi-RHS kernel form or the batched grid by timing the candidates once
+    // (result cached on the context, keyed by problem shape)
+    qcdw_status tune(int kprec)
+    {
+        if (nprob == 1) return QCDW_OK;
+        std::vector<int> cand;
+        char key[160];
+        if (batch) {
+            snprintf(key, sizeof key, "batch_hop/p%d/tiles%d/n%d", kprec, batch->total_tiles, nprob);
+            for (int gsz : {256, 512, 1024, 2048, 4096})
+                if (gsz < batch->total_tiles) cand.push_back(gsz);
+            cand.push_back(batch->total_tiles);
+        } else {
+            snprintf(key, sizeof key, "mrhs_hop/p%d/Vh%d/n%d", kprec, ops[0]->g.Vh, nprob);
+            cand = {0, 1};
+        }
+        auto it = ctx->tune.find(key);
+        if (it != ctx->tune.end()) {
+            variant = it->second;
+            return QCDW_OK;
+        }
+        hipEvent_t e0, e1;
+        HIPCHK(ctx, hipEventCreate(&e0));
+        HIPCHK(ctx, hipEventCreate(&e1));
+        float best = 1e30f;
+        int best_v = cand[0];
+        const bool was_on = tm.on;
+        tm.on = false;
+        for (int c : cand) {
+            variant = c;
+            // hop into odd sites from the (scratch) Krylov vectors; no solver state is touched
+            hipError_t e = hop(s, kprec, EPI_CLOV, RED_NONE, W.kr[2].p, W.kr[6].p, nullptr, nullptr, nullptr,
+                               nullptr, 1);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3 && e == hipSuccess; rep++)
+                e = hop(s, kprec, EPI_CLOV, RED_NONE, W.kr[2].p, W.kr[6].p, nullptr, nullptr, nullptr, nullptr, 1);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return fail(ctx, QCDW_EHIP, "tuning launch failed: %s", hipGetErrorString(e));
+            }
+            if (ms < best) {
+                best = ms;
+                best_v = c;
+            }
+        }
+        tm.on = was_on;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        variant = best_v;
+        ctx->tune_store(key, best_v);
+        return QCDW_OK;
     }
 
     // run nit iterations: eagerly, or by replaying a captured graph of exactly nit iterations
@@ -626,16 +832,18 @@ struct Solver {
             HIPCHK(ctx, enqueue_iters(s, nit, kprec, xprec, xk));
             return QCDW_OK;
         }
-        qcdw_op::Graph* gr = nullptr;
-        for (auto& cand : op->graphs)
-            if (cand.kprec == kprec && cand.chunk == nit && cand.gen == op->ws_gen)
-                gr = &cand;
+        Workspace::Graph* gr = nullptr;
+        for (auto& c : W.graphs)
+            if (c.kprec == kprec && c.chunk == nit && c.nprob == nprob && c.variant == variant && c.gen == W.ws_gen)
+                gr = &c;
         if (!gr) {
-            op->graphs.emplace_back();
-            gr = &op->graphs.back();
+            W.graphs.emplace_back();
+            gr = &W.graphs.back();
             gr->kprec = kprec;
             gr->chunk = nit;
-            gr->gen = op->ws_gen;
+            gr->nprob = nprob;
+            gr->variant = variant;
+            gr->gen = W.ws_gen;
             hipStream_t cs = ctx->cap_stream;
             HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             hipError_t e = enqueue_iters(cs, nit, kprec, xprec, xk);
@@ -650,41 +858,345 @@ struct Solver {
         return QCDW_OK;
     }
 
-    // rhi = bhat - M_hat xhi in FP64; returns ||rhi||^2
-    qcdw_status true_schur_residual(double& rr)
+    qcdw_status read_doubles(std::vector<double>& out)
     {
-        const PrecView v = view(op, F64);
-        HIPCHK(ctx, matpc(s, op, v, op->xhi.p, op->tmp64.p, op->tmpo64.p, RED_NONE, nullptr, nullptr, nullptr));
-        HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, op->bhat.p, op->tmp64.p, op->rhi.p, n, (double*)op->partials.p,
-                                     (double*)op->dres.p));
-        return read_double(ctx, (double*)op->dres.p, rr);
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_d, W.dres.p, nprob * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        out.assign(ctx->host_d, ctx->host_d + nprob);
+        return QCDW_OK;
+    }
+
+    // rhi = bhat - M_hat xhi in FP64 for every problem; rr[k] = ||rhi_k||^2
+    qcdw_status true_schur_residual(std::vector<double>& rr)
+    {
+        for (int k = 0; k < nprob; k++) {
+            const qcdw_op* op = ops[k];
+            HIPCHK(ctx, matpc(s, op, view(op, F64), at(W.xhi, k), at(W.tmp64, k), W.tmpo64.p, RED_NONE, nullptr,
+                              nullptr, nullptr));
+        }
+        HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, W.bhat.p, W.tmp64.p, W.rhi.p, n0(), (double*)W.partials.p,
+                                     (double*)W.dres.p, nprob, map, nmax));
+        return read_doubles(rr);
+    }
+
+    // x_o = A_oo^-1 b_o + kappa A_oo^-1 H_oe x_e for problem k into tmpo64, then the FP64
+    // full-lattice residual ||b - M x||^2 of that problem
+    qcdw_status full_residual(int k, double& r2)
+    {
+        const qcdw_op* op = ops[k];
+        const PrecView v64 = view(op, F64);
+        const Geom& g = op->g;
+        HopArgs a = hop_args(g, 1);
+        a.psi = at(W.xhi, k);
+        a.out = W.tmpo64.p;
+        a.gauge = v64.gauge;
+        a.clov = v64.Ainv[1];
+        a.y = at(W.yo, k);
+        a.a = -op->kappa;
+        HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_CLOV_XPAY, RED_NONE, a));
+        r2 = 0;
+        for (int p = 0; p < 2; p++) {
+            HopArgs m = hop_args(g, p);  // (M x)_p = A_pp x_p - kappa H x_{1-p}
+            m.psi = p == 0 ? W.tmpo64.p : at(W.xhi, k);
+            m.out = W.tmp64.p;
+            m.gauge = v64.gauge;
+            m.clov = op->A64[p].p;
+            m.y = p == 0 ? at(W.xhi, k) : W.tmpo64.p;
+            m.a = op->kappa;
+            HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_XPAY_CLOVY, RED_NONE, m));
+            HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, p == 0 ? at(W.be, k) : at(W.bo, k), W.tmp64.p, nullptr, len[k],
+                                         (double*)W.partials.p, (double*)W.dres.p));
+            double rp;
+            CHK(read_double(ctx, (double*)W.dres.p, rp));
+            r2 += rp;
+        }
+        return QCDW_OK;
+    }
+
+    qcdw_status ensure_workspace(int kprec, int maxiter)
+    {
+        long total = 0;
+        for (int k = 0; k < nprob; k++) total += len[k];
+        std::vector<void*> before;
+        DevBuf* all[] = {&W.kr[0], &W.kr[1], &W.kr[2], &W.kr[3], &W.kr[4], &W.kr[5], &W.kr[6], &W.xlo,
+                         &W.xhi, &W.partials, &W.scal, &W.dres, &W.hist, &W.coef};
+        for (DevBuf* b : all) before.push_back(b->p);
+        DevBuf* stacked64[] = {&W.be, &W.bo, &W.yo, &W.ye, &W.bhat, &W.xhi, &W.rhi, &W.tmp64};
+        for (DevBuf* b : stacked64) HIPCHK(ctx, b->alloc((size_t)total * 16));
+        HIPCHK(ctx, W.tmpo64.alloc((size_t)nmax * 16));
+        for (auto& b : W.kr) HIPCHK(ctx, b.alloc((size_t)total * cplx_bytes(kprec)));
+        if (kprec != F64) HIPCHK(ctx, W.xlo.alloc((size_t)total * 8));
+        const long nbmax = std::max<long>(std::max<long>(nb_blas, nb_hop), 1);
+        HIPCHK(ctx, W.partials.alloc(3UL * nprob * nbmax * sizeof(double)));
+        HIPCHK(ctx, W.scal.alloc(MAX_BATCH * sizeof(Scal)));
+        HIPCHK(ctx, W.dres.alloc(MAX_BATCH * sizeof(double)));
+        HIPCHK(ctx, W.coef.alloc(2 * MAX_BATCH * sizeof(double)));
+        HIPCHK(ctx, W.hist.alloc((size_t)nprob * ((size_t)maxiter + 2) * sizeof(double)));
+        for (size_t i = 0; i < before.size(); i++)
+            if (all[i]->p != before[i]) {
+                W.ws_gen++;
+                W.drop_graphs();
+                break;
+            }
+        return QCDW_OK;
     }
 };
 
-qcdw_status ensure_workspace(qcdw_op* op, int kprec, int maxiter)
+// Solve M_k x_k = b_k for every problem of S (b, x: one full fermion field each).
+// The problems share every launch of the iteration but keep their own scalars,
+// targets and convergence flags; finished problems are masked.
+qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_solver_params* params,
+                  qcdw_solve_info* infos)
 {
-    qcdw_ctx* ctx = op->ctx;
-    const long n = 12L * op->g.Vh;
-    const size_t b64 = n * 16;
-    std::vector<void*> before;
-    DevBuf* all[] = {&op->kr[0], &op->kr[1], &op->kr[2], &op->kr[3], &op->kr[4], &op->kr[5], &op->kr[6], &op->xlo,
-                     &op->xhi, &op->partials, &op->scal, &op->dres, &op->hist};
-    for (DevBuf* b : all) before.push_back(b->p);
-    DevBuf* f64bufs[] = {&op->be, &op->bo, &op->yo, &op->ye, &op->bhat, &op->xhi, &op->rhi, &op->tmp64, &op->tmpo64};
-    for (DevBuf* b : f64bufs) HIPCHK(ctx, b->alloc(b64));
-    for (auto& b : op->kr) HIPCHK(ctx, b.alloc(n * cplx_bytes(kprec)));
-    if (kprec != F64) HIPCHK(ctx, op->xlo.alloc(n * 8));
-    HIPCHK(ctx, op->partials.alloc(3UL * std::max<long>(MAX_PARTIALS, hop_blocks(op->g.Vh)) * sizeof(double)));
-    HIPCHK(ctx, op->scal.alloc(sizeof(Scal)));
-    HIPCHK(ctx, op->dres.alloc(64 * sizeof(double)));
-    HIPCHK(ctx, op->hist.alloc(((size_t)maxiter + 2) * sizeof(double)));
-    op->kr_prec = kprec;
-    for (size_t i = 0; i < before.size(); i++)
-        if (all[i]->p != before[i]) {
-            op->ws_gen++;
-            op->drop_graphs();
-            break;
+    qcdw_ctx* ctx = S.ctx;
+    Workspace& W = S.W;
+    const int nprob = S.nprob;
+    DeviceGuard dg(ctx->device);
+    const auto t_start = std::chrono::steady_clock::now();
+    qcdw_solver_params prm;
+    if (params) prm = *params;
+    else qcdw_solver_params_default(&prm);
+    std::vector<double*> user_hist(nprob);
+    std::vector<int> user_hist_len(nprob);
+    for (int k = 0; k < nprob; k++) {
+        user_hist[k] = infos[k].res_hist;
+        user_hist_len[k] = infos[k].hist_len;
+        infos[k] = qcdw_solve_info{};
+        infos[k].res_hist = user_hist[k];
+        infos[k].hist_len = user_hist_len[k];
+        infos[k].status = QCDW_EINVAL;
+    }
+    for (int k = 0; k < nprob; k++) {
+        CHK(check_dev(ctx, bs[k], "b"));
+        CHK(check_dev(ctx, xs[k], "x"));
+        if (bs[k] == xs[k]) return fail(ctx, QCDW_EINVAL, "x must not alias b");
+    }
+    if (!(prm.tol > 0.0) || !std::isfinite(prm.tol)) return fail(ctx, QCDW_EINVAL, "tol must be positive");
+    if (prm.maxiter < 0) return fail(ctx, QCDW_EINVAL, "maxiter must be >= 0");
+    if (prm.check_every < 1) prm.check_every = 1;
+    const int kprec = (int)prm.inner;
+    for (auto* op : S.ops)
+        if (kprec != F64 && kprec != op->inner)
+            return fail(ctx, QCDW_EINVAL, "inner precision %d not prepared by the operator (has %d)", kprec,
+                        op->inner);
+    if (kprec != F64 && !(prm.delta > 0.0 && prm.delta < 1.0))
+        return fail(ctx, QCDW_EINVAL, "delta must lie in (0, 1)");
+    CHK(S.ensure_workspace(kprec, prm.maxiter));
+    S.tm.on = prm.collect_timing != 0;
+    const bool use_graph = prm.use_graph != 0 && !S.tm.on;  // per-launch timing needs eager launches
+    hipStream_t s = S.s;
+    Scal* dS = (Scal*)W.scal.p;
+    double* dhist = (double*)W.hist.p;
+    double* dpart = (double*)W.partials.p;
+    double* dres = (double*)W.dres.p;
+    double* dcoef = (double*)W.coef.p;
+    const int hist_len = prm.maxiter + 2;
+    std::vector<std::vector<double>> hist_host(nprob);
+    const long n0 = S.n0();
+
+    // ---- source preparation (FP64) --------------------------------------
+    for (int k = 0; k < nprob; k++) {
+        const Geom& g = S.ops[k]->g;
+        HIPCHK(ctx, launch_pack_spinor(s, F64, g, bs[k], 0, S.at(W.be, k), 1.0));
+        HIPCHK(ctx, launch_pack_spinor(s, F64, g, bs[k], 1, S.at(W.bo, k), 1.0));
+        HIPCHK(ctx, launch_pack_spinor(s, F64, g, xs[k], 0, S.at(W.xhi, k), 1.0));
+    }
+    std::vector<double> bn2e, bn2o, bnorm(nprob);
+    HIPCHK(ctx, launch_norm2(s, F64, W.be.p, n0, dpart, dres, nprob, S.map, S.nmax));
+    CHK(S.read_doubles(bn2e));
+    HIPCHK(ctx, launch_norm2(s, F64, W.bo.p, n0, dpart, dres, nprob, S.map, S.nmax));
+    CHK(S.read_doubles(bn2o));
+    std::vector<int> status(nprob, QCDW_ENOCONV), done(nprob, 0), restarts(nprob, 0), iters(nprob, 0);
+    std::vector<double> true_res(nprob, NAN), target(nprob), iter_res(nprob, NAN);
+    for (int k = 0; k < nprob; k++) {
+        const qcdw_op* op = S.ops[k];
+        const Geom& g = op->g;
+        const PrecView v64 = view(op, F64);
+        const size_t fbytes = 24UL * g.Vh * 16;
+        bnorm[k] = std::sqrt(bn2e[k] + bn2o[k]);
+        if (!std::isfinite(bnorm[k])) {
+            status[k] = QCDW_ENAN;
+            done[k] = 1;
+        } else if (bnorm[k] == 0.0) {
+            status[k] = QCDW_OK;
+            true_res[k] = 0.0;
+            done[k] = 1;
+            HIPCHK(ctx, hipMemsetAsync(S.at(W.xhi, k), 0, S.len[k] * 16, s));
+            HIPCHK(ctx, hipMemsetAsync(xs[k], 0, fbytes, s));
         }
+        target[k] = 0.5 * prm.tol * bnorm[k];  // on ||bhat - M_hat x_e||
+        // y_o = A_oo^-1 b_o ; y_e = A_ee^-1 b_e ; bhat = y_e + kappa A_ee^-1 H_eo y_o
+        HIPCHK(ctx, launch_clov_apply_internal(s, F64, g, v64.Ainv[1], S.at(W.bo, k), S.at(W.yo, k)));
+        HIPCHK(ctx, launch_clov_apply_internal(s, F64, g, v64.Ainv[0], S.at(W.be, k), S.at(W.ye, k)));
+        HopArgs a = hop_args(g, 0);
+        a.psi = S.at(W.yo, k);
+        a.out = S.at(W.bhat, k);
+        a.gauge = v64.gauge;
+        a.clov = v64.Ainv[0];
+        a.y = S.at(W.ye, k);
+        a.a = -op->kappa;
+        HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_CLOV_XPAY, RED_NONE, a));
+    }
+    CHK(S.tune(kprec));
+
+    // ---- outer loop: Krylov cycles with FP64 residual recomputation -----
+    std::vector<double> rr_hi;
+    CHK(S.true_schur_residual(rr_hi));
+    for (int k = 0; k < nprob; k++)
+        if (!done[k]) hist_host[k].push_back(std::sqrt(rr_hi[k]) / bnorm[k]);
+    int lock_iters = 0, reliable = 0, fault = prm.fault_inject;
+    const int maxiter = prm.maxiter;
+    const bool mixed = kprec != F64;
+    void *r = W.kr[0].p, *r0 = W.kr[1].p, *p = W.kr[2].p;
+    void* xk = mixed ? W.xlo.p : W.xhi.p;
+    const int xprec = mixed ? F32 : F64;
+
+    while (true) {
+        bool pending = false;
+        for (int k = 0; k < nprob; k++) {
+            if (done[k]) continue;
+            if (!std::isfinite(rr_hi[k])) {
+                status[k] = QCDW_ENAN;
+                done[k] = 1;
+                continue;
+            }
+            if (std::sqrt(rr_hi[k]) <= target[k]) {
+                double r2;
+                CHK(S.full_residual(k, r2));
+                true_res[k] = std::sqrt(r2) / bnorm[k];
+                if (true_res[k] <= prm.tol) {
+                    status[k] = QCDW_OK;
+                    done[k] = 1;
+                    const Geom& g = S.ops[k]->g;
+                    HIPCHK(ctx, launch_unpack_spinor(s, F64, g, S.at(W.xhi, k), 0, xs[k], 1.0));
+                    HIPCHK(ctx, launch_unpack_spinor(s, F64, g, W.tmpo64.p, 1, xs[k], 1.0));
+                    continue;
+                }
+                target[k] *= 0.5 * prm.tol / true_res[k];  // tighten and keep iterating
+            }
+            pending = true;
+        }
+        if (!pending || lock_iters >= maxiter) break;
+
+        // --- one Krylov cycle on M_hat c = rhi for the pending problems -----
+        double* hc = ctx->host_d;  // [0, nprob): scales, [nprob, 2 nprob): coefficients of the x update
+        std::vector<double> scale(nprob, 1.0);
+        for (int k = 0; k < nprob; k++) {
+            scale[k] = (mixed && !done[k] && rr_hi[k] > 0) ? std::sqrt((double)S.len[k] / rr_hi[k]) : 1.0;
+            hc[k] = scale[k];
+            hc[nprob + k] = done[k] ? 0.0 : 1.0 / scale[k];
+        }
+        HIPCHK(ctx, hipMemcpyAsync(dcoef, hc, 2 * nprob * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, launch_convert(s, F64, kprec, W.rhi.p, r, n0, 1.0, dcoef, nprob, S.map, S.nmax));
+        HIPCHK(ctx, launch_convert(s, kprec, kprec, r, r0, n0, 1.0, nullptr, nprob, S.map, S.nmax));
+        HIPCHK(ctx, launch_convert(s, kprec, kprec, r, p, n0, 1.0, nullptr, nprob, S.map, S.nmax));
+        if (mixed) {
+            long total = 0;
+            for (int k = 0; k < nprob; k++) total += S.len[k];
+            HIPCHK(ctx, hipMemsetAsync(W.xlo.p, 0, (size_t)total * 8, s));
+        }
+        HIPCHK(ctx, launch_norm2(s, kprec, r, n0, dpart, dres, nprob, S.map, S.nmax));
+        Scal* hs = ctx->host_scal;
+        memset(hs, 0, nprob * sizeof(Scal));
+        for (int k = 0; k < nprob; k++) {
+            double cycle_stop = target[k] * scale[k];
+            if (mixed) cycle_stop = std::max(cycle_stop, prm.delta * std::sqrt((double)S.len[k]));
+            hs[k].stop_rr = done[k] ? INFINITY : cycle_stop * cycle_stop;  // finished problems start converged
+            hs[k].hist_norm = 1.0 / (scale[k] * bnorm[k]);
+            hs[k].iter = iters[k];
+            hs[k].fault_iter = fault;
+            hs[k].hist_len = hist_len;
+        }
+        HIPCHK(ctx, hipMemcpyAsync(dS, hs, nprob * sizeof(Scal), hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, launch_bicg_init(s, dS, dres, nprob));
+        int all_flags = 0;
+        while (true) {
+            const int chunk = std::min(prm.check_every, maxiter - lock_iters);
+            if (chunk <= 0) break;
+            CHK(S.run_chunk(chunk, kprec, xprec, xk, use_graph));
+            HIPCHK(ctx, hipMemcpyAsync(hs, dS, nprob * sizeof(Scal), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            int advanced = 0;
+            bool all_set = true;
+            for (int k = 0; k < nprob; k++) {
+                const int done_now = hs[k].iter - iters[k];
+                advanced = std::max(advanced, done_now);
+                if (done_now > 0) {
+                    std::vector<double> h(done_now);
+                    HIPCHK(ctx, hipMemcpy(h.data(), dhist + (size_t)k * hist_len + iters[k] + 1,
+                                          done_now * sizeof(double), hipMemcpyDeviceToHost));
+                    hist_host[k].insert(hist_host[k].end(), h.begin(), h.end());
+                }
+                iters[k] = hs[k].iter;
+                if (!hs[k].flags) all_set = false;
+            }
+            if (S.tm.on) S.tm.collect((size_t)4 * advanced);
+            lock_iters += chunk;
+            if (all_set) break;
+        }
+        for (int k = 0; k < nprob; k++) {
+            all_flags |= hs[k].flags;
+            if (!done[k]) iter_res[k] = std::sqrt(hs[k].rr) / (scale[k] * bnorm[k]);
+        }
+        if (mixed) HIPCHK(ctx, launch_axpy_hi(s, F32, 0.0, dcoef + nprob, W.xlo.p, W.xhi.p, n0, nprob, S.map, S.nmax));
+        for (int k = 0; k < nprob; k++) {
+            if (done[k]) continue;
+            if (hs[k].flags & FLAG_NAN) {
+                status[k] = QCDW_ENAN;
+                done[k] = 1;
+            } else if ((hs[k].flags & FLAG_BREAK) && ++restarts[k] > prm.max_restarts) {
+                status[k] = QCDW_EBREAKDOWN;
+                done[k] = 2;
+            }
+        }
+        if (all_flags & FLAG_BREAK) fault = 0;
+        CHK(S.true_schur_residual(rr_hi));
+        reliable++;
+    }
+
+    // ---- unfinished problems: best iterate and its true residual ----------
+    for (int k = 0; k < nprob; k++) {
+        if (status[k] == QCDW_OK || status[k] == QCDW_ENAN) continue;
+        double r2;
+        CHK(S.full_residual(k, r2));
+        true_res[k] = std::sqrt(r2) / bnorm[k];
+        const Geom& g = S.ops[k]->g;
+        HIPCHK(ctx, launch_unpack_spinor(s, F64, g, S.at(W.xhi, k), 0, xs[k], 1.0));
+        HIPCHK(ctx, launch_unpack_spinor(s, F64, g, W.tmpo64.p, 1, xs[k], 1.0));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+
+    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    qcdw_status worst = QCDW_OK;
+    for (int k = 0; k < nprob; k++) {
+        qcdw_solve_info* inf = infos + k;
+        inf->status = status[k];
+        inf->iters = iters[k];
+        inf->n_reliable = reliable;
+        inf->n_restarts = restarts[k];
+        inf->true_res = true_res[k];
+        inf->iter_res = iter_res[k];
+        inf->time_ms = wall;
+        for (int j = 0; j < 3; j++) {
+            inf->hop_ms[j] = S.tm.ms[j];
+            inf->n_hop[j] = (int32_t)S.tm.launches[j];
+        }
+        if (user_hist[k] && user_hist_len[k] > 0) {
+            const int m = std::min<int>(user_hist_len[k], (int)hist_host[k].size());
+            memcpy(user_hist[k], hist_host[k].data(), m * sizeof(double));
+            inf->hist_count = m;
+        }
+        if (status[k] != QCDW_OK && worst == QCDW_OK) worst = (qcdw_status)status[k];
+    }
+    if (worst != QCDW_OK) {
+        const char* what = worst == QCDW_ENOCONV      ? "did not converge within maxiter"
+                           : worst == QCDW_ENAN       ? "NaN or Inf in the source or the iteration"
+                           : worst == QCDW_EBREAKDOWN ? "BiCGStab breakdown persisted after restarts"
+                                                      : "solver failed";
+        int k0 = 0;
+        while (k0 < nprob && status[k0] == QCDW_OK) k0++;
+        return fail(ctx, worst, "%s (problem %d: iters %d, true residual %.3e)", what, k0, iters[k0], true_res[k0]);
+    }
     return QCDW_OK;
 }
 
@@ -694,262 +1206,106 @@ extern "C" qcdw_status qcdw_invert(qcdw_op* op, const void* b, void* x, const qc
                                    qcdw_solve_info* info)
 {
     if (!op) return QCDW_EINVAL;
-    qcdw_ctx* ctx = op->ctx;
-    DeviceGuard dg(ctx->device);
-    const auto t_start = std::chrono::steady_clock::now();
-    qcdw_solver_params prm;
-    if (params) prm = *params;
-    else qcdw_solver_params_default(&prm);
     qcdw_solve_info dummy{};
-    qcdw_solve_info* inf = info ? info : &dummy;
-    double* user_hist = inf->res_hist;
-    const int user_hist_len = inf->hist_len;
-    *inf = qcdw_solve_info{};
-    inf->res_hist = user_hist;
-    inf->hist_len = user_hist_len;
-    inf->status = QCDW_EINVAL;
-    CHK(check_dev(ctx, b, "b"));
-    CHK(check_dev(ctx, x, "x"));
-    if (b == x) return fail(ctx, QCDW_EINVAL, "x must not alias b");
-    if (!(prm.tol > 0.0) || !std::isfinite(prm.tol)) return fail(ctx, QCDW_EINVAL, "tol must be positive");
-    if (prm.maxiter < 0) return fail(ctx, QCDW_EINVAL, "maxiter must be >= 0");
-    if (prm.check_every < 1) prm.check_every = 1;
-    const int kprec = (int)prm.inner;
-    if (kprec != F64 && kprec != op->inner)
-        return fail(ctx, QCDW_EINVAL, "inner precision %d not prepared by this operator (has %d)", kprec, op->inner);
-    if (kprec != F64 && !(prm.delta > 0.0 && prm.delta < 1.0))
-        return fail(ctx, QCDW_EINVAL, "delta must lie in (0, 1)");
-    CHK(ensure_workspace(op, kprec, prm.maxiter));
-
-    Solver S{op, ctx, ctx->stream, 12L * op->g.Vh, hop_blocks(op->g.Vh), blas_blocks(12L * op->g.Vh)};
-    S.tm.on = prm.collect_timing != 0;
-    const bool use_graph = prm.use_graph != 0 && !S.tm.on;  // per-launch timing needs eager launches
-    hipStream_t s = ctx->stream;
-    const Geom& g = op->g;
-    const long n = S.n;
-    const PrecView v64 = view(op, F64);
-    Scal* dS = (Scal*)op->scal.p;
-    double* dhist = (double*)op->hist.p;
-    double* dpart = (double*)op->partials.p;
-    double* dres = (double*)op->dres.p;
-    std::vector<double> hist_host;
-    hist_host.reserve(64);
-
-    // ---- source preparation (FP64) --------------------------------------
-    HIPCHK(ctx, launch_pack_spinor(s, F64, g, b, 0, op->be.p, 1.0));
-    HIPCHK(ctx, launch_pack_spinor(s, F64, g, b, 1, op->bo.p, 1.0));
-    double bn2e, bn2o;
-    HIPCHK(ctx, launch_norm2(s, F64, op->be.p, n, dpart, dres));
-    CHK(read_double(ctx, dres, bn2e));
-    HIPCHK(ctx, launch_norm2(s, F64, op->bo.p, n, dpart, dres));
-    CHK(read_double(ctx, dres, bn2o));
-    const double bnorm = std::sqrt(bn2e + bn2o);
-    if (!std::isfinite(bnorm)) {
-        inf->status = QCDW_ENAN;
-        inf->true_res = NAN;
-        return fail(ctx, QCDW_ENAN, "source contains NaN or Inf");
-    }
-    if (bnorm == 0.0) {
-        HIPCHK(ctx, hipMemsetAsync(x, 0, 2 * n * 16, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        inf->status = QCDW_OK;
-        return QCDW_OK;
-    }
-    // y_o = A_oo^-1 b_o ; y_e = A_ee^-1 b_e ; bhat = y_e + kappa A_ee^-1 H_eo y_o
-    HIPCHK(ctx, launch_clov_apply_internal(s, F64, g, v64.Ainv[1], op->bo.p, op->yo.p));
-    HIPCHK(ctx, launch_clov_apply_internal(s, F64, g, v64.Ainv[0], op->be.p, op->ye.p));
-    {
-        HopArgs a = hop_args(g, 0);
-        a.psi = op->yo.p;
-        a.out = op->bhat.p;
-        a.gauge = v64.gauge;
-        a.clov = v64.Ainv[0];
-        a.y = op->ye.p;
-        a.a = -op->kappa;
-        HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_CLOV_XPAY, RED_NONE, a));
-    }
-    HIPCHK(ctx, launch_pack_spinor(s, F64, g, x, 0, op->xhi.p, 1.0));  // initial guess (even sites)
-
-    // ---- outer loop: Krylov cycles with FP64 residual recomputation -----
-    double target = 0.5 * prm.tol * bnorm;  // on ||bhat - M_hat x_e||
-    double rr_hi;
-    CHK(S.true_schur_residual(rr_hi));
-    hist_host.push_back(std::sqrt(rr_hi) / bnorm);
-    int iters = 0, restarts = 0, reliable = 0, fault = prm.fault_inject;
-    qcdw_status status = QCDW_ENOCONV;
-    double true_res = NAN;
-    const int maxiter = prm.maxiter;
-
-    while (true) {
-        if (!std::isfinite(rr_hi)) {
-            status = QCDW_ENAN;
-            break;
-        }
-        if (std::sqrt(rr_hi) <= target) {
-            // reconstruct and check the full-lattice residual
-            HopArgs a = hop_args(g, 1);  // x_o = y_o + kappa A_oo^-1 H_oe x_e
-            a.psi = op->xhi.p;
-            a.out = op->tmpo64.p;
-            a.gauge = v64.gauge;
-            a.clov = v64.Ainv[1];
-            a.y = op->yo.p;
-            a.a = -op->kappa;
-            HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_CLOV_XPAY, RED_NONE, a));
-            double r2 = 0;
-            for (int p = 0; p < 2; p++) {
-                HopArgs m = hop_args(g, p);  // (M x)_p = A_pp x_p - kappa H x_{1-p}
-                m.psi = p == 0 ? op->tmpo64.p : op->xhi.p;
-                m.out = op->tmp64.p;
-                m.gauge = v64.gauge;
-                m.clov = op->A64[p].p;
-                m.y = p == 0 ? op->xhi.p : op->tmpo64.p;
-                m.a = op->kappa;
-                HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_XPAY_CLOVY, RED_NONE, m));
-                double rp;
-                HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, p == 0 ? op->be.p : op->bo.p, op->tmp64.p, nullptr, n,
-                                             dpart, dres));
-                CHK(read_double(ctx, dres, rp));
-                r2 += rp;
-            }
-            true_res = std::sqrt(r2) / bnorm;
-            if (true_res <= prm.tol) {
-                status = QCDW_OK;
-                break;
-            }
-            // tighten the Schur target and keep iterating
-            target *= 0.5 * prm.tol / true_res;
-            if (iters >= maxiter) break;
-        }
-        if (iters >= maxiter) break;
-
-        // --- one Krylov cycle on M_hat c = rhi --------------------------
-        const bool mixed = kprec != F64;
-        const double rhi_norm = std::sqrt(rr_hi);
-        const double scale = mixed ? std::sqrt((double)n) / rhi_norm : 1.0;
-        void *r = op->kr[0].p, *r0 = op->kr[1].p, *p = op->kr[2].p;
-        void* xk = mixed ? op->xlo.p : op->xhi.p;
-        const int xprec = mixed ? F32 : F64;
-        HIPCHK(ctx, launch_convert(s, F64, kprec, op->rhi.p, r, n, scale));
-        HIPCHK(ctx, launch_convert(s, kprec, kprec, r, r0, n, 1.0));
-        HIPCHK(ctx, launch_convert(s, kprec, kprec, r, p, n, 1.0));
-        if (mixed) HIPCHK(ctx, hipMemsetAsync(op->xlo.p, 0, n * 8, s));
-        HIPCHK(ctx, launch_norm2(s, kprec, r, n, dpart, dres));
-        Scal* hs = ctx->host_scal;
-        memset(hs, 0, sizeof(Scal));
-        double cycle_stop = target * scale;
-        if (mixed) cycle_stop = std::max(cycle_stop, prm.delta * std::sqrt((double)n));
-        hs->stop_rr = cycle_stop * cycle_stop;
-        hs->hist_norm = 1.0 / (scale * bnorm);
-        hs->iter = iters;
-        hs->fault_iter = fault;
-        hs->hist_len = maxiter + 2;
-        HIPCHK(ctx, hipMemcpyAsync(dS, hs, sizeof(Scal), hipMemcpyHostToDevice, s));
-        HIPCHK(ctx, launch_bicg_init(s, dS, dres));
-        int flags = 0;
-        while (true) {
-            const int chunk = std::min(prm.check_every, maxiter - iters);
-            if (chunk <= 0) break;
-            CHK(S.run_chunk(chunk, kprec, xprec, xk, use_graph));
-            HIPCHK(ctx, hipMemcpyAsync(hs, dS, sizeof(Scal), hipMemcpyDeviceToHost, s));
-            HIPCHK(ctx, hipStreamSynchronize(s));
-            const int done_now = hs->iter - iters;
-            if (S.tm.on) S.tm.collect((size_t)4 * done_now);
-            if (done_now > 0) {
-                std::vector<double> h(done_now);
-                HIPCHK(ctx, hipMemcpy(h.data(), dhist + iters + 1, done_now * sizeof(double), hipMemcpyDeviceToHost));
-                hist_host.insert(hist_host.end(), h.begin(), h.end());
-            }
-            iters = hs->iter;
-            flags = hs->flags;
-            if (flags) break;
-        }
-        inf->iter_res = std::sqrt(hs->rr) / (scale * bnorm);
-        if (mixed) HIPCHK(ctx, launch_axpy_hi(s, F32, 1.0 / scale, op->xlo.p, op->xhi.p, n));
-        if (flags & FLAG_NAN) {
-            status = QCDW_ENAN;
-            break;
-        }
-        if (flags & FLAG_BREAK) {
-            fault = 0;
-            if (++restarts > prm.max_restarts) {
-                status = QCDW_EBREAKDOWN;
-                CHK(S.true_schur_residual(rr_hi));
-                break;
-            }
-        }
-        CHK(S.true_schur_residual(rr_hi));
-        reliable++;
-    }
-
-    // ---- write x (even sites from xhi, odd sites reconstructed) -----------
-    if (status == QCDW_OK || status == QCDW_ENOCONV || status == QCDW_EBREAKDOWN) {
-        if (status != QCDW_OK) {
-            HopArgs a = hop_args(g, 1);
-            a.psi = op->xhi.p;
-            a.out = op->tmpo64.p;
-            a.gauge = v64.gauge;
-            a.clov = v64.Ainv[1];
-            a.y = op->yo.p;
-            a.a = -op->kappa;
-            HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_CLOV_XPAY, RED_NONE, a));
-            double r2 = 0;
-            for (int p = 0; p < 2; p++) {
-                HopArgs m = hop_args(g, p);
-                m.psi = p == 0 ? op->tmpo64.p : op->xhi.p;
-                m.out = op->tmp64.p;
-                m.gauge = v64.gauge;
-                m.clov = op->A64[p].p;
-                m.y = p == 0 ? op->xhi.p : op->tmpo64.p;
-                m.a = op->kappa;
-                HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_XPAY_CLOVY, RED_NONE, m));
-                double rp;
-                HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, p == 0 ? op->be.p : op->bo.p, op->tmp64.p, nullptr, n,
-                                             dpart, dres));
-                CHK(read_double(ctx, dres, rp));
-                r2 += rp;
-            }
-            true_res = std::sqrt(r2) / bnorm;
-        }
-        HIPCHK(ctx, launch_unpack_spinor(s, F64, g, op->xhi.p, 0, x, 1.0));
-        HIPCHK(ctx, launch_unpack_spinor(s, F64, g, op->tmpo64.p, 1, x, 1.0));
-    }
-    HIPCHK(ctx, hipStreamSynchronize(s));
-
-    inf->status = status;
-    inf->iters = iters;
-    inf->n_reliable = reliable;
-    inf->n_restarts = restarts;
-    inf->true_res = true_res;
-    for (int k = 0; k < 3; k++) {
-        inf->hop_ms[k] = S.tm.ms[k];
-        inf->n_hop[k] = (int32_t)S.tm.launches[k];
-    }
-    if (user_hist && user_hist_len > 0) {
-        const int m = std::min<int>(user_hist_len, (int)hist_host.size());
-        memcpy(user_hist, hist_host.data(), m * sizeof(double));
-        inf->hist_count = m;
-    }
-    inf->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    if (status != QCDW_OK) {
-        const char* what = status == QCDW_ENOCONV   ? "did not converge within maxiter"
-                           : status == QCDW_ENAN    ? "NaN or Inf in the iteration"
-                           : status == QCDW_EBREAKDOWN ? "BiCGStab breakdown persisted after restarts"
-                                                    : "solver failed";
-        return fail(ctx, status, "%s (iters %d, true residual %.3e)", what, iters, true_res);
-    }
-    return QCDW_OK;
+    Solver S(op->ctx, op->ws, {op}, nullptr);
+    return solve(S, &b, &x, params, info ? info : &dummy);
 }
 
 extern "C" qcdw_status qcdw_invert_multi(qcdw_op* op, int nrhs, const void* b, void* x,
                                          const qcdw_solver_params* params, qcdw_solve_info* info)
 {
     if (!op) return QCDW_EINVAL;
-    if (nrhs < 1 || !info) return fail(op->ctx, QCDW_EINVAL, "nrhs must be >= 1 and info non-NULL");
-    const size_t fb = 24UL * op->g.Vh * 16;  // bytes of one full fermion field
-    qcdw_status worst = QCDW_OK;
+    if (nrhs < 1 || nrhs > MAX_RHS || !info)
+        return fail(op->ctx, QCDW_EINVAL, "nrhs must lie in [1, %d] and info must not be NULL", MAX_RHS);
+    const size_t fb = 24UL * op->g.Vh * 16;
+    std::vector<const void*> bs(nrhs);
+    std::vector<void*> xs(nrhs);
     for (int k = 0; k < nrhs; k++) {
-        qcdw_status st = qcdw_invert(op, (const char*)b + k * fb, (char*)x + k * fb, params, info + k);
-        if (st != QCDW_OK && worst == QCDW_OK) worst = st;
+        bs[k] = (const char*)b + k * fb;
+        xs[k] = (char*)x + k * fb;
     }
-    return worst;
+    Solver S(op->ctx, op->ws, std::vector<qcdw_op*>(nrhs, op), nullptr);
+    return solve(S, bs.data(), xs.data(), params, info);
+}
+
+extern "C" qcdw_status qcdw_batch_create(qcdw_ctx* ctx, int n, qcdw_op* const ops[], qcdw_batch** out)
+{
+    if (!ctx) return QCDW_EINVAL;
+    if (!out || !ops || n < 1 || n > MAX_BATCH)
+        return fail(ctx, QCDW_EINVAL, "need 1..%d operators and an output pointer", MAX_BATCH);
+    *out = nullptr;
+    DeviceGuard dg(ctx->device);
+    for (int k = 0; k < n; k++) {
+        if (!ops[k] || ops[k]->ctx != ctx) return fail(ctx, QCDW_EINVAL, "operator %d is NULL or of another context", k);
+        if (ops[k]->inner != ops[0]->inner)
+            return fail(ctx, QCDW_EINVAL, "all operators of a batch need the same inner precision");
+        if (ops[k]->recon != 12) return fail(ctx, QCDW_EINVAL, "batched solves use reconstruct-12 operators");
+    }
+    qcdw_batch* b = new qcdw_batch;
+    b->ctx = ctx;
+    b->ops.assign(ops, ops + n);
+    b->inner = ops[0]->inner;
+    std::vector<long2> map(n);
+    std::vector<int> tiles(n);
+    std::vector<BatchEntry> t64(n), tlo(n);
+    int tile0 = 0;
+    for (int k = 0; k < n; k++) {
+        const qcdw_op* op = ops[k];
+        const long len = 12L * op->g.Vh;
+        b->off.push_back(b->total);
+        b->len.push_back(len);
+        map[k] = make_long2(b->total, len);
+        tiles[k] = hop_blocks(op->g.Vh);
+        for (int pr = 0; pr < 2; pr++) {
+            BatchEntry& e = pr == 0 ? t64[k] : tlo[k];
+            const PrecView v = view(op, pr == 0 ? F64 : op->inner);
+            e.g = op->g;
+            e.kappa2 = op->kappa * op->kappa;
+            e.gauge = v.gauge;
+            e.clov[0] = v.Ainv[0];
+            e.clov[1] = v.Ainv[1];
+            e.off = b->total;
+            e.n = len;
+            e.tile0 = tile0;
+            e.ntiles = tiles[k];
+        }
+        tile0 += tiles[k];
+        b->total += len;
+        b->nmax = std::max(b->nmax, len);
+        b->nbmax = std::max(b->nbmax, tiles[k]);
+    }
+    b->total_tiles = tile0;
+    hipStream_t s = ctx->stream;
+    hipError_t e = b->map.alloc(n * sizeof(long2));
+    if (e == hipSuccess) e = b->nbs.alloc(n * sizeof(int));
+    if (e == hipSuccess) e = b->tab64.alloc(n * sizeof(BatchEntry));
+    if (e == hipSuccess) e = b->tablo.alloc(n * sizeof(BatchEntry));
+    if (e == hipSuccess) e = hipMemcpyAsync(b->map.p, map.data(), n * sizeof(long2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->nbs.p, tiles.data(), n * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->tab64.p, t64.data(), n * sizeof(BatchEntry), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->tablo.p, tlo.data(), n * sizeof(BatchEntry), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(ctx, e == hipErrorOutOfMemory ? QCDW_ENOMEM : QCDW_EHIP, "batch setup: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return QCDW_OK;
+}
+
+extern "C" void qcdw_batch_destroy(qcdw_batch* b)
+{
+    if (!b) return;
+    DeviceGuard dg(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    delete b;
+}
+
+extern "C" qcdw_status qcdw_invert_batch(qcdw_batch* b, const void* const bs[], void* const xs[],
+                                         const qcdw_solver_params* params, qcdw_solve_info* infos)
+{
+    if (!b) return QCDW_EINVAL;
+    if (!bs || !xs || !infos) return fail(b->ctx, QCDW_EINVAL, "b, x and info arrays must not be NULL");
+    Solver S(b->ctx, b->ws, b->ops, b);
+    return solve(S, bs, xs, params, infos);
 }

@@ -11,70 +11,89 @@ namespace qcdw {
 #define QCDW_GRID_LOOP(e, n) \
     for (long e = (long)blockIdx.x * BLAS_THREADS + threadIdx.x; e < (n); e += (long)gridDim.x * BLAS_THREADS)
 
+// Vector y of a launch (blockIdx.y) covers elements [off, off + len): with a map
+// (offset, length per vector: problems of different sizes) or uniformly y n, n.
+#define QCDW_VEC_RANGE(n, map)                                            \
+    const long off = (map) ? (map)[blockIdx.y].x : (long)blockIdx.y * (n); \
+    const long nn = (map) ? (map)[blockIdx.y].y : (n);
+
 // ---------------------------------------------------------------------------
 // generic vector kernels
 // ---------------------------------------------------------------------------
+// one RHS per blockIdx.y: elements [y n, (y+1) n)
 template <class P>
-__global__ __launch_bounds__(256) void k_norm2(const void* x, long n, double* partials)
+__global__ __launch_bounds__(256) void k_norm2(const void* x, long n, double* partials, const long2* map)
 {
     double v[1] = {0.0};
-    QCDW_GRID_LOOP(e, n)
+    QCDW_VEC_RANGE(n, map)
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto a = P::ld(x, e);
+        const auto a = P::ld(x, off + e);
         v[0] += (double)a.re * a.re + (double)a.im * a.im;
     }
-    block_sum_store<1>(v, partials + blockIdx.x);
+    block_sum_store<1>(v, partials + (long)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 template <class PB, class PY>
 __global__ __launch_bounds__(256) void k_xmy_norm2(const void* b, const void* y, double2* r, long n,
-                                                   double* partials)
+                                                   double* partials, const long2* map)
 {
     double v[1] = {0.0};
-    QCDW_GRID_LOOP(e, n)
+    QCDW_VEC_RANGE(n, map)
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto bb = PB::ld(b, e);
-        const auto yy = PY::ld(y, e);
+        const auto bb = PB::ld(b, off + e);
+        const auto yy = PY::ld(y, off + e);
         const double re = (double)bb.re - (double)yy.re, im = (double)bb.im - (double)yy.im;
-        if (r) r[e] = make_double2(re, im);
+        if (r) r[off + e] = make_double2(re, im);
         v[0] += re * re + im * im;
     }
-    block_sum_store<1>(v, partials + blockIdx.x);
+    block_sum_store<1>(v, partials + (long)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
+// one block per RHS: out[K x] = sum over the nb partials of RHS x
 template <int K>
 __global__ __launch_bounds__(256) void k_sum_partials(const double* partials, int nb, double* out)
 {
     double v[K];
+    const double* pp = partials + (long)blockIdx.x * nb * K;
 #pragma unroll
     for (int k = 0; k < K; k++) v[k] = 0.0;
     for (int b = threadIdx.x; b < nb; b += 256)
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] += partials[(long)b * K + k];
-    block_sum_store<K>(v, out);
+        for (int k = 0; k < K; k++) v[k] += pp[(long)b * K + k];
+    block_sum_store<K>(v, out + (long)blockIdx.x * K);
 }
 
+// out = scale_y in for RHS y (scales: per-RHS device array, or nullptr for `scale`)
 template <class PI, class PO>
-__global__ __launch_bounds__(256) void k_convert(const void* in, void* out, long n, double scale)
+__global__ __launch_bounds__(256) void k_convert(const void* in, void* out, long n, double scale,
+                                                 const double* scales, const long2* map)
 {
     using T = typename PO::real;
-    QCDW_GRID_LOOP(e, n)
+    QCDW_VEC_RANGE(n, map)
+    const double sc = scales ? scales[blockIdx.y] : scale;
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto a = PI::ld(in, e);
-        PO::st(out, e, cx<T>{(T)(scale * (double)a.re), (T)(scale * (double)a.im)});
+        const auto a = PI::ld(in, off + e);
+        PO::st(out, off + e, cx<T>{(T)(sc * (double)a.re), (T)(sc * (double)a.im)});
     }
 }
 
+// y += a_y x for RHS y (coefs: per-RHS device array, or nullptr for `a`)
 template <class PX>
-__global__ __launch_bounds__(256) void k_axpy_hi(double a, const void* x, double2* y, long n)
+__global__ __launch_bounds__(256) void k_axpy_hi(double a, const double* coefs, const void* x, double2* y, long n,
+                                                 const long2* map)
 {
-    QCDW_GRID_LOOP(e, n)
+    QCDW_VEC_RANGE(n, map)
+    const double c = coefs ? coefs[blockIdx.y] : a;
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto xv = PX::ld(x, e);
-        double2 yv = y[e];
-        yv.x += a * (double)xv.re;
-        yv.y += a * (double)xv.im;
-        y[e] = yv;
+        const auto xv = PX::ld(x, off + e);
+        double2 yv = y[off + e];
+        yv.x += c * (double)xv.re;
+        yv.y += c * (double)xv.im;
+        y[off + e] = yv;
     }
 }
 
@@ -150,57 +169,67 @@ __device__ __forceinline__ void st2(double* p, cx<double> v)
 }
 
 // p = r + beta (p - omega v)
+// blockIdx.y selects the right-hand side: its scalars S[y] and elements [y n, (y+1) n)
 template <class P>
-__global__ __launch_bounds__(256) void k_bicg_p(void* p, const void* r, const void* v, long n, const Scal* S)
+__global__ __launch_bounds__(256) void k_bicg_p(void* p, const void* r, const void* v, long n, const Scal* S,
+                                                const long2* map)
 {
+    S += blockIdx.y;
     if (S->flags) return;
     using T = typename P::real;
+    QCDW_VEC_RANGE(n, map)
     const cx<T> beta = {(T)S->beta[0], (T)S->beta[1]}, omega = {(T)S->omega[0], (T)S->omega[1]};
-    QCDW_GRID_LOOP(e, n)
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto pv = P::ld(p, e), rv = P::ld(r, e), vv = P::ld(v, e);
-        P::st(p, e, rv + beta * (pv - omega * vv));
+        const auto pv = P::ld(p, off + e), rv = P::ld(r, off + e), vv = P::ld(v, off + e);
+        P::st(p, off + e, rv + beta * (pv - omega * vv));
     }
 }
 
 // s = r - alpha v
 template <class P>
-__global__ __launch_bounds__(256) void k_bicg_s(void* sv, const void* r, const void* v, long n, const Scal* S)
+__global__ __launch_bounds__(256) void k_bicg_s(void* sv, const void* r, const void* v, long n, const Scal* S,
+                                                const long2* map)
 {
+    S += blockIdx.y;
     if (S->flags) return;
     using T = typename P::real;
+    QCDW_VEC_RANGE(n, map)
     const cx<T> alpha = {(T)S->alpha[0], (T)S->alpha[1]};
-    QCDW_GRID_LOOP(e, n)
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto rv = P::ld(r, e), vv = P::ld(v, e);
-        P::st(sv, e, rv - alpha * vv);
+        const auto rv = P::ld(r, off + e), vv = P::ld(v, off + e);
+        P::st(sv, off + e, rv - alpha * vv);
     }
 }
 
 // x += alpha p + omega s ; r = s - omega t ; partials (r0, r), ||r||^2
 template <class P, class PX>
 __global__ __launch_bounds__(256) void k_bicg_xr(void* x, const void* p, const void* sv, void* r, const void* t,
-                                                 const void* r0, long n, const Scal* S, double* partials)
+                                                 const void* r0, long n, const Scal* S, double* partials,
+                                                 const long2* map)
 {
+    S += blockIdx.y;
     if (S->flags) return;
     using T = typename P::real;
     using TX = typename PX::real;
+    QCDW_VEC_RANGE(n, map)
     const cx<TX> alpha = {(TX)S->alpha[0], (TX)S->alpha[1]}, omega_x = {(TX)S->omega[0], (TX)S->omega[1]};
     const cx<T> omega = {(T)S->omega[0], (T)S->omega[1]};
     double acc[3] = {0.0, 0.0, 0.0};
-    QCDW_GRID_LOOP(e, n)
+    QCDW_GRID_LOOP(e, nn)
     {
-        const auto pv = P::ld(p, e), sv_ = P::ld(sv, e), tv = P::ld(t, e), w = P::ld(r0, e);
-        const cx<TX> xv = PX::ld(x, e);
+        const auto pv = P::ld(p, off + e), sv_ = P::ld(sv, off + e), tv = P::ld(t, off + e), w = P::ld(r0, off + e);
+        const cx<TX> xv = PX::ld(x, off + e);
         const cx<TX> pX = {(TX)pv.re, (TX)pv.im}, sX = {(TX)sv_.re, (TX)sv_.im};
-        PX::st(x, e, xv + alpha * pX + omega_x * sX);
+        PX::st(x, off + e, xv + alpha * pX + omega_x * sX);
         const auto rn = P::rt(sv_ - omega * tv);
-        P::st(r, e, rn);
+        P::st(r, off + e, rn);
         acc[0] += (double)w.re * rn.re + (double)w.im * rn.im;
         acc[1] += (double)w.re * rn.im - (double)w.im * rn.re;
         acc[2] += (double)rn.re * rn.re + (double)rn.im * rn.im;
     }
-    block_sum_store<3>(acc, partials + 3L * blockIdx.x);
+    block_sum_store<3>(acc, partials + 3L * ((long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // fixed-order sum of nb x 3 partials, result valid in thread 0
@@ -221,10 +250,11 @@ __device__ __forceinline__ void sum3(const double* partials, int nb, double (&v)
 }
 
 // start (or restart) from the residual r with r0 = r: rho = (r0, r) = ||r||^2
-__global__ void k_bicg_init(Scal* S, const double* rr_dev)
+__global__ void k_bicg_init(Scal* S, const double* rr_dev, int nrhs)
 {
-    if (threadIdx.x != 0) return;
-    const double rr = *rr_dev;
+    if ((int)threadIdx.x >= nrhs) return;
+    S += threadIdx.x;
+    const double rr = rr_dev[threadIdx.x];
     S->rho[0] = rr;
     S->rho[1] = 0.0;
     S->rr = rr;
@@ -239,11 +269,12 @@ __global__ void k_bicg_init(Scal* S, const double* rr_dev)
     if (!isfinite(rr)) S->flags = FLAG_NAN;
 }
 
-__global__ __launch_bounds__(256) void k_fin_alpha(Scal* S, const double* partials, int nb)
+__global__ __launch_bounds__(256) void k_fin_alpha(Scal* S, const double* partials, int nb, const int* nbs)
 {
+    S += blockIdx.x;
     if (S->flags) return;
     double v[3];
-    sum3(partials, nb, v);
+    sum3(partials + 3L * nb * blockIdx.x, nbs ? nbs[blockIdx.x] : nb, v);
     if (threadIdx.x == 0) {
         const cx<double> rv = {v[0], v[1]};
         const double arv = sqrt(rv.re * rv.re + rv.im * rv.im);
@@ -257,11 +288,12 @@ __global__ __launch_bounds__(256) void k_fin_alpha(Scal* S, const double* partia
     }
 }
 
-__global__ __launch_bounds__(256) void k_fin_omega(Scal* S, const double* partials, int nb)
+__global__ __launch_bounds__(256) void k_fin_omega(Scal* S, const double* partials, int nb, const int* nbs)
 {
+    S += blockIdx.x;
     if (S->flags) return;
     double v[3];
-    sum3(partials, nb, v);
+    sum3(partials + 3L * nb * blockIdx.x, nbs ? nbs[blockIdx.x] : nb, v);
     if (threadIdx.x == 0) {
         const double tt = v[2];
         if (!isfinite(tt) || !isfinite(v[0]) || !isfinite(v[1])) {
@@ -279,9 +311,11 @@ __global__ __launch_bounds__(256) void k_fin_omega(Scal* S, const double* partia
 
 __global__ __launch_bounds__(256) void k_fin_beta(Scal* S, const double* partials, int nb, double* hist)
 {
+    S += blockIdx.x;
     if (S->flags) return;
+    if (hist) hist += (long)blockIdx.x * S->hist_len;
     double v[3];
-    sum3(partials, nb, v);
+    sum3(partials + 3L * nb * blockIdx.x, nb, v);
     if (threadIdx.x == 0) {
         const cx<double> rho_new = {v[0], v[1]};
         const double rr = v[2];
@@ -318,66 +352,76 @@ __global__ __launch_bounds__(256) void k_fin_beta(Scal* S, const double* partial
     default: return hipErrorInvalidValue;                                              \
     }
 
-hipError_t launch_norm2(hipStream_t s, int prec, const void* x, long n, double* partials, double* out)
+// grid.x covers the longest vector of the launch (nmax); blocks past a shorter
+// vector's end contribute zero partials
+hipError_t launch_norm2(hipStream_t s, int prec, const void* x, long n, double* partials, double* out, int nrhs,
+                        const long2* map, long nmax)
 {
-    const int nb = blas_blocks(n);
-    QCDW_DISPATCH1(prec, k_norm2, dim3(nb), dim3(256), 0, s, x, n, partials)
-    hipLaunchKernelGGL(k_sum_partials<1>, dim3(1), dim3(256), 0, s, partials, nb, out);
+    const int nb = blas_blocks(map ? nmax : n);
+    QCDW_DISPATCH1(prec, k_norm2, dim3(nb, nrhs), dim3(256), 0, s, x, n, partials, map)
+    hipLaunchKernelGGL(k_sum_partials<1>, dim3(nrhs), dim3(256), 0, s, partials, nb, out);
     return hipGetLastError();
 }
 
 template <class PB>
-static hipError_t xmy_b(hipStream_t s, int prec_y, const void* b, const void* y, void* r, long n, double* partials)
+static hipError_t xmy_b(hipStream_t s, int prec_y, const void* b, const void* y, void* r, long n, double* partials,
+                        int nrhs, const long2* map, int nb)
 {
-    const int nb = blas_blocks(n);
+    const dim3 grid(nb, nrhs);
     switch (prec_y) {
-    case F64: hipLaunchKernelGGL((k_xmy_norm2<PB, P64>), dim3(nb), dim3(256), 0, s, b, y, (double2*)r, n, partials); break;
-    case F32: hipLaunchKernelGGL((k_xmy_norm2<PB, P32>), dim3(nb), dim3(256), 0, s, b, y, (double2*)r, n, partials); break;
+    case F64: hipLaunchKernelGGL((k_xmy_norm2<PB, P64>), grid, dim3(256), 0, s, b, y, (double2*)r, n, partials, map); break;
+    case F32: hipLaunchKernelGGL((k_xmy_norm2<PB, P32>), grid, dim3(256), 0, s, b, y, (double2*)r, n, partials, map); break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
 }
 
 hipError_t launch_xmy_norm2(hipStream_t s, int prec_b, int prec_y, const void* b, const void* y, void* r, long n,
-                            double* partials, double* out)
+                            double* partials, double* out, int nrhs, const long2* map, long nmax)
 {
+    const int nb = blas_blocks(map ? nmax : n);
     hipError_t e;
-    if (prec_b == F64) e = xmy_b<P64>(s, prec_y, b, y, r, n, partials);
-    else if (prec_b == F32) e = xmy_b<P32>(s, prec_y, b, y, r, n, partials);
+    if (prec_b == F64) e = xmy_b<P64>(s, prec_y, b, y, r, n, partials, nrhs, map, nb);
+    else if (prec_b == F32) e = xmy_b<P32>(s, prec_y, b, y, r, n, partials, nrhs, map, nb);
     else return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_partials<1>, dim3(1), dim3(256), 0, s, partials, blas_blocks(n), out);
+    hipLaunchKernelGGL(k_sum_partials<1>, dim3(nrhs), dim3(256), 0, s, partials, nb, out);
     return hipGetLastError();
 }
 
 template <class PI>
-static hipError_t convert_in(hipStream_t s, int prec_out, const void* in, void* out, long n, double scale)
+static hipError_t convert_in(hipStream_t s, int prec_out, const void* in, void* out, long n, double scale,
+                             const double* scales, int nrhs, const long2* map, int nb)
 {
-    const int nb = blas_blocks(n);
+    const dim3 grid(nb, nrhs);
     switch (prec_out) {
-    case F64: hipLaunchKernelGGL((k_convert<PI, P64>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
-    case F32: hipLaunchKernelGGL((k_convert<PI, P32>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
-    case BF16: hipLaunchKernelGGL((k_convert<PI, PBF16>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
-    case F16: hipLaunchKernelGGL((k_convert<PI, PF16>), dim3(nb), dim3(256), 0, s, in, out, n, scale); break;
+    case F64: hipLaunchKernelGGL((k_convert<PI, P64>), grid, dim3(256), 0, s, in, out, n, scale, scales, map); break;
+    case F32: hipLaunchKernelGGL((k_convert<PI, P32>), grid, dim3(256), 0, s, in, out, n, scale, scales, map); break;
+    case BF16: hipLaunchKernelGGL((k_convert<PI, PBF16>), grid, dim3(256), 0, s, in, out, n, scale, scales, map); break;
+    case F16: hipLaunchKernelGGL((k_convert<PI, PF16>), grid, dim3(256), 0, s, in, out, n, scale, scales, map); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_convert(hipStream_t s, int prec_in, int prec_out, const void* in, void* out, long n, double scale)
+hipError_t launch_convert(hipStream_t s, int prec_in, int prec_out, const void* in, void* out, long n, double scale,
+                          const double* scales, int nrhs, const long2* map, long nmax)
 {
+    const int nb = blas_blocks(map ? nmax : n);
     switch (prec_in) {
-    case F64: return convert_in<P64>(s, prec_out, in, out, n, scale);
-    case F32: return convert_in<P32>(s, prec_out, in, out, n, scale);
-    case BF16: return convert_in<PBF16>(s, prec_out, in, out, n, scale);
-    case F16: return convert_in<PF16>(s, prec_out, in, out, n, scale);
+    case F64: return convert_in<P64>(s, prec_out, in, out, n, scale, scales, nrhs, map, nb);
+    case F32: return convert_in<P32>(s, prec_out, in, out, n, scale, scales, nrhs, map, nb);
+    case BF16: return convert_in<PBF16>(s, prec_out, in, out, n, scale, scales, nrhs, map, nb);
+    case F16: return convert_in<PF16>(s, prec_out, in, out, n, scale, scales, nrhs, map, nb);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_axpy_hi(hipStream_t s, int prec_x, double a, const void* x, void* y, long n)
+hipError_t launch_axpy_hi(hipStream_t s, int prec_x, double a, const double* coefs, const void* x, void* y, long n,
+                          int nrhs, const long2* map, long nmax)
 {
-    QCDW_DISPATCH1(prec_x, k_axpy_hi, dim3(blas_blocks(n)), dim3(256), 0, s, a, x, (double2*)y, n)
+    QCDW_DISPATCH1(prec_x, k_axpy_hi, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, a, coefs, x,
+                   (double2*)y, n, map)
     return hipGetLastError();
 }
 
@@ -390,60 +434,65 @@ hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, co
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev)
+hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nrhs)
 {
-    hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(64), 0, s, S, rr_dev);
+    hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(64), 0, s, S, rr_dev, nrhs);
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S)
+hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S,
+                         int nrhs, const long2* map, long nmax)
 {
-    QCDW_DISPATCH1(prec, k_bicg_p, dim3(blas_blocks(n)), dim3(256), 0, s, p, r, v, n, S)
+    QCDW_DISPATCH1(prec, k_bicg_p, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, p, r, v, n, S, map)
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S)
+hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S,
+                         int nrhs, const long2* map, long nmax)
 {
-    QCDW_DISPATCH1(prec, k_bicg_s, dim3(blas_blocks(n)), dim3(256), 0, s, sv, r, v, n, S)
+    QCDW_DISPATCH1(prec, k_bicg_s, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, sv, r, v, n, S, map)
     return hipGetLastError();
 }
 
 template <class PX>
 static hipError_t bicg_xr_x(hipStream_t s, int prec, void* x, const void* p, const void* sv, void* r, const void* t,
-                            const void* r0, long n, const Scal* S, double* partials)
+                            const void* r0, long n, const Scal* S, double* partials, int nrhs, const long2* map,
+                            int nb)
 {
-    const int nb = blas_blocks(n);
+    const dim3 grid(nb, nrhs);
     switch (prec) {
-    case F64: hipLaunchKernelGGL((k_bicg_xr<P64, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
-    case F32: hipLaunchKernelGGL((k_bicg_xr<P32, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
-    case BF16: hipLaunchKernelGGL((k_bicg_xr<PBF16, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
-    case F16: hipLaunchKernelGGL((k_bicg_xr<PF16, PX>), dim3(nb), dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials); break;
+    case F64: hipLaunchKernelGGL((k_bicg_xr<P64, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
+    case F32: hipLaunchKernelGGL((k_bicg_xr<P32, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
+    case BF16: hipLaunchKernelGGL((k_bicg_xr<PBF16, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
+    case F16: hipLaunchKernelGGL((k_bicg_xr<PF16, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_bicg_xr(hipStream_t s, int prec, int prec_x, void* x, const void* p, const void* sv, void* r,
-                          const void* t, const void* r0, long n, const Scal* S, double* partials)
+                          const void* t, const void* r0, long n, const Scal* S, double* partials, int nrhs,
+                          const long2* map, long nmax)
 {
-    if (prec_x == F64) return bicg_xr_x<P64>(s, prec, x, p, sv, r, t, r0, n, S, partials);
-    if (prec_x == F32) return bicg_xr_x<P32>(s, prec, x, p, sv, r, t, r0, n, S, partials);
+    const int nb = blas_blocks(map ? nmax : n);
+    if (prec_x == F64) return bicg_xr_x<P64>(s, prec, x, p, sv, r, t, r0, n, S, partials, nrhs, map, nb);
+    if (prec_x == F32) return bicg_xr_x<P32>(s, prec, x, p, sv, r, t, r0, n, S, partials, nrhs, map, nb);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb)
+hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb, int nrhs, const int* nbs)
 {
-    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, S, partials, nb);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(nrhs), dim3(256), 0, s, S, partials, nb, nbs);
     return hipGetLastError();
 }
-hipError_t launch_fin_omega(hipStream_t s, Scal* S, const double* partials, int nb)
+hipError_t launch_fin_omega(hipStream_t s, Scal* S, const double* partials, int nb, int nrhs, const int* nbs)
 {
-    hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(256), 0, s, S, partials, nb);
+    hipLaunchKernelGGL(k_fin_omega, dim3(nrhs), dim3(256), 0, s, S, partials, nb, nbs);
     return hipGetLastError();
 }
-hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int nb, double* hist)
+hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int nb, double* hist, int nrhs)
 {
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, S, partials, nb, hist);
+    hipLaunchKernelGGL(k_fin_beta, dim3(nrhs), dim3(256), 0, s, S, partials, nb, hist);
     return hipGetLastError();
 }
 

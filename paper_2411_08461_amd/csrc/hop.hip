@@ -112,13 +112,13 @@ __device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
     return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
 }
 
+// One 64-site tile of the hop with its epilogue; `part` receives the tile's
+// reduction partials (RED != RED_NONE).  All 256 threads of the block call it.
 template <class P, int R, int EPI, int RED>
-__global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
+__device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* part)
 {
     using T = typename P::real;
-    if (a.stop && *a.stop) return;
     const Geom g = a.g;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int q = threadIdx.x & 3;
     const int site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
     const bool valid = site < g.Vh;
@@ -326,7 +326,68 @@ __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
                 }
             }
         }
-        block_sum_store<3>(v, a.partials + 3 * (long)tile);
+        block_sum_store<3>(v, part);
+    }
+}
+
+template <class P, int R, int EPI, int RED>
+__global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
+{
+    if (a.stop && *a.stop) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    hop_tile<P, R, EPI, RED>(a, tile, a.partials + 3 * (long)tile);
+}
+
+// Multi-RHS hop, L2-reuse form: block -> (tile, rhs) with rhs fastest, so the
+// blocks applying one tile's links and clover entries to all right-hand sides
+// run back to back on one XCD and re-read them from its L2; each block is the
+// single-RHS tile code.  Finished RHS (flags set) are skipped.
+template <class P, int EPI, int RED>
+__global__ __launch_bounds__(256) void hop_rhs_kernel(HopArgs a, const Scal* S)
+{
+    const int nrhs = a.nrhs;
+    const int logical = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = logical / nrhs, r = logical - tile * nrhs;
+    if (S && S[r].flags) return;
+    const long off = (long)r * 12 * a.g.Vh * P::cbytes;
+    HopArgs b = a;
+    b.psi = (const char*)a.psi + off;
+    b.out = (char*)a.out + off;
+    if (a.y) b.y = (const char*)a.y + off;
+    if (a.w) b.w = (const char*)a.w + off;
+    hop_tile<P, 6, EPI, RED>(b, tile, a.partials + 3 * ((long)r * hop_blocks(a.g.Vh) + tile));
+}
+
+// Batched hop: a persistent grid walks the tiles of every problem in a device
+// table (problems of different lattice sizes and kappas).  Tile t belongs to
+// the problem whose [tile0, tile0 + ntiles) contains it; finished problems
+// (flags set) are skipped; partials go to [problem][tile][3].
+template <class P, int EPI, int RED>
+__global__ __launch_bounds__(256) void hop_batch_kernel(BatchHopArgs b)
+{
+    for (int t = blockIdx.x; t < b.total_tiles; t += gridDim.x) {
+        int lo = 0, hi = b.nprob - 1;
+        while (lo < hi) {  // last problem with tile0 <= t
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.tab[mid].tile0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchEntry& e = b.tab[lo];
+        if (b.S && b.S[lo].flags) continue;  // uniform over the block
+        HopArgs a{};
+        a.g = e.g;
+        a.parity = b.parity;
+        a.gauge = e.gauge;
+        a.clov = e.clov[b.parity];
+        a.psi = (const char*)b.psi + e.off * P::cbytes;
+        a.out = (char*)b.out + e.off * P::cbytes;
+        a.y = b.y ? (const char*)b.y + e.off * P::cbytes : nullptr;
+        a.w = b.w ? (const char*)b.w + e.off * P::cbytes : nullptr;
+        a.a = b.use_kappa2 ? e.kappa2 : b.a;
+        a.nrhs = 1;
+        const int tile = t - e.tile0;
+        hop_tile<P, 6, EPI, RED>(a, tile, b.partials + 3 * ((long)lo * b.nbmax + tile));
+        __syncthreads();  // shared reduction buffer reused by the next tile
     }
 }
 
@@ -350,6 +411,73 @@ static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& 
     QCDW_HOP_CASE(EPI_CLOV_XPAY, RED_TS)
     QCDW_HOP_CASE(EPI_XPAY_CLOVY, RED_NONE)
 #undef QCDW_HOP_CASE
+    return hipErrorInvalidValue;
+}
+
+template <class P>
+static hipError_t launch_rhs_p(hipStream_t s, int epi, int red, const HopArgs& a, const Scal* S, hipEvent_t e0,
+                               hipEvent_t e1)
+{
+    const dim3 grid(hop_blocks(a.g.Vh) * a.nrhs), block(256);
+#define QCDW_RHS_CASE(E, D)                                                                     \
+    if (epi == E && red == D) {                                                                \
+        if (e0)                                                                                \
+            hipExtLaunchKernelGGL((hop_rhs_kernel<P, E, D>), grid, block, 0, s, e0, e1, 0, a, S); \
+        else                                                                                   \
+            hipLaunchKernelGGL((hop_rhs_kernel<P, E, D>), grid, block, 0, s, a, S);             \
+        return hipGetLastError();                                                              \
+    }
+    QCDW_RHS_CASE(EPI_CLOV, RED_NONE)
+    QCDW_RHS_CASE(EPI_CLOV_XPAY, RED_NONE)
+    QCDW_RHS_CASE(EPI_CLOV_XPAY, RED_WDOT)
+    QCDW_RHS_CASE(EPI_CLOV_XPAY, RED_TS)
+#undef QCDW_RHS_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_rhs(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S, hipEvent_t e0,
+                          hipEvent_t e1)
+{
+    if (a.g.Vh <= 0 || a.nrhs <= 0) return hipSuccess;
+    switch (prec) {
+    case F64: return launch_rhs_p<P64>(s, epi, red, a, S, e0, e1);
+    case F32: return launch_rhs_p<P32>(s, epi, red, a, S, e0, e1);
+    case BF16: return launch_rhs_p<PBF16>(s, epi, red, a, S, e0, e1);
+    case F16: return launch_rhs_p<PF16>(s, epi, red, a, S, e0, e1);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class P>
+static hipError_t launch_batch_p(hipStream_t s, int epi, int red, const BatchHopArgs& b, int grid, hipEvent_t e0,
+                                 hipEvent_t e1)
+{
+#define QCDW_BATCH_CASE(E, D)                                                                             \
+    if (epi == E && red == D) {                                                                          \
+        if (e0)                                                                                          \
+            hipExtLaunchKernelGGL((hop_batch_kernel<P, E, D>), dim3(grid), dim3(256), 0, s, e0, e1, 0, b); \
+        else                                                                                             \
+            hipLaunchKernelGGL((hop_batch_kernel<P, E, D>), dim3(grid), dim3(256), 0, s, b);             \
+        return hipGetLastError();                                                                        \
+    }
+    QCDW_BATCH_CASE(EPI_CLOV, RED_NONE)
+    QCDW_BATCH_CASE(EPI_CLOV_XPAY, RED_WDOT)
+    QCDW_BATCH_CASE(EPI_CLOV_XPAY, RED_TS)
+#undef QCDW_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_batch(hipStream_t s, int prec, int epi, int red, const BatchHopArgs& b, int grid,
+                            hipEvent_t e0, hipEvent_t e1)
+{
+    if (b.total_tiles <= 0) return hipSuccess;
+    if (grid <= 0 || grid > b.total_tiles) grid = b.total_tiles;
+    switch (prec) {
+    case F64: return launch_batch_p<P64>(s, epi, red, b, grid, e0, e1);
+    case F32: return launch_batch_p<P32>(s, epi, red, b, grid, e0, e1);
+    case BF16: return launch_batch_p<PBF16>(s, epi, red, b, grid, e0, e1);
+    case F16: return launch_batch_p<PF16>(s, epi, red, b, grid, e0, e1);
+    }
     return hipErrorInvalidValue;
 }
 

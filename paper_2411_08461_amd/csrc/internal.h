@@ -8,6 +8,8 @@
 
 namespace qcdw {
 
+struct Scal;  // BiCGStab scalars, below
+
 enum Prec { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
 inline int cplx_bytes(int prec) { return prec == F64 ? 16 : prec == F32 ? 8 : 4; }
@@ -43,14 +45,45 @@ struct HopArgs {
     const int* stop;    // if non-null and *stop != 0 the launch does nothing
 };
 
+// one problem of a batched solve (device table entry); reconstruct-12 operators
+struct BatchEntry {
+    Geom g;
+    double kappa2;        // kappa^2 of this problem
+    const void* gauge;    // links in the batch's Krylov precision
+    const void* clov[2];  // A^-1 per parity, same precision
+    long off;             // element offset (complex) of this problem in the concatenated vectors
+    long n;               // 12 Vh
+    int tile0;            // first global hop tile of this problem
+    int ntiles;           // hop tiles of this problem
+};
+
+struct BatchHopArgs {
+    const BatchEntry* tab;
+    int nprob;
+    int total_tiles;
+    int parity;
+    int nbmax;           // partials stride per problem (tiles)
+    int use_kappa2;      // 1: xpay coefficient = kappa^2 of each problem, else `a`
+    double a;
+    const void* psi;     // concatenated vectors, problem k at element offset tab[k].off
+    void* out;
+    const void* y;
+    const void* w;
+    double* partials;    // [problem][nbmax][3]
+    const Scal* S;       // per-problem solver scalars (flags) or nullptr
+};
+
 constexpr int HOP_SITES_PER_BLOCK = 64;  // 4 lanes per site, 256 threads
-inline int hop_blocks(int Vh) { return (Vh + HOP_SITES_PER_BLOCK - 1) / HOP_SITES_PER_BLOCK; }
+__host__ __device__ inline int hop_blocks(int Vh) { return (Vh + HOP_SITES_PER_BLOCK - 1) / HOP_SITES_PER_BLOCK; }
 
 // e0/e1: optional events recorded by the kernel dispatch itself (timing)
 hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // BiCGStab scalars kept on the device (complex values as re, im pairs)
+hipError_t launch_hop_batch(hipStream_t s, int prec, int epi, int red, const BatchHopArgs& b, int grid,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
 struct Scal {
     double rho[2];    // (r0, r)
     double alpha[2];
@@ -77,24 +110,45 @@ inline int blas_blocks(long n)
     return (int)b;
 }
 
-// generic reductions over n complex elements; results (doubles) land in out
-hipError_t launch_norm2(hipStream_t s, int prec, const void* x, long n, double* partials, double* out);
+// Vector kernels act on nrhs stacked fields of n complex elements each; RHS y uses
+// elements [y n, (y+1) n), scalars S[y] and partials [y][blocks][..].  With a map
+// (device array of (offset, length) per vector, problems of different sizes) the
+// ranges come from the map and nmax is the longest length.
+hipError_t launch_norm2(hipStream_t s, int prec, const void* x, long n, double* partials, double* out, int nrhs = 1,
+                        const long2* map = nullptr, long nmax = 0);
 hipError_t launch_xmy_norm2(hipStream_t s, int prec_b, int prec_y, const void* b, const void* y, void* r, long n,
-                            double* partials, double* out);  // r = b - y (FP64 r), out[0] = ||r||^2
-hipError_t launch_convert(hipStream_t s, int prec_in, int prec_out, const void* in, void* out, long n, double scale);
-hipError_t launch_axpy_hi(hipStream_t s, int prec_x, double a, const void* x, void* y, long n);  // y(f64) += a x
+                            double* partials, double* out, int nrhs = 1, const long2* map = nullptr,
+                            long nmax = 0);  // r = b - y (FP64 r), out = ||r||^2
+hipError_t launch_convert(hipStream_t s, int prec_in, int prec_out, const void* in, void* out, long n, double scale,
+                          const double* scales = nullptr, int nrhs = 1, const long2* map = nullptr, long nmax = 0);
+hipError_t launch_axpy_hi(hipStream_t s, int prec_x, double a, const double* coefs, const void* x, void* y, long n,
+                          int nrhs = 1, const long2* map = nullptr, long nmax = 0);  // y(f64) += a x
 hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, const void* clov, const void* in,
                                       void* out);
 
 // BiCGStab iteration pieces
-hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev);
-hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S);
-hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S);
+hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nrhs = 1);
+hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S,
+                         int nrhs = 1, const long2* map = nullptr, long nmax = 0);
+hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S,
+                         int nrhs = 1, const long2* map = nullptr, long nmax = 0);
 hipError_t launch_bicg_xr(hipStream_t s, int prec, int prec_x, void* x, const void* p, const void* sv, void* r,
-                          const void* t, const void* r0, long n, const Scal* S, double* partials);
-hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb);
-hipError_t launch_fin_omega(hipStream_t s, Scal* S, const double* partials, int nb);
-hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int nb, double* hist);
+                          const void* t, const void* r0, long n, const Scal* S, double* partials, int nrhs = 1,
+                          const long2* map = nullptr, long nmax = 0);
+// nb: partials stride per RHS; nbs (optional, per RHS) the count actually written
+hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb, int nrhs = 1,
+                            const int* nbs = nullptr);
+hipError_t launch_fin_omega(hipStream_t s, Scal* S, const double* partials, int nb, int nrhs = 1,
+                            const int* nbs = nullptr);
+hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int nb, double* hist, int nrhs = 1);
+
+// multi-RHS hop (reconstruct-12): a.nrhs stacked fields; RHS y skipped when S[y].flags != 0;
+// partials [y][hop_blocks][3]
+hipError_t launch_hop_mrhs(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// the same operation with one block per (tile, rhs), rhs fastest (links and clover re-read from L2)
+hipError_t launch_hop_rhs(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // pack / unpack between the paper layouts and the internal ones
 hipError_t launch_pack_spinor(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal,

@@ -366,3 +366,141 @@ def test_graph_replay_matches_eager(ctx, inner):
             assert info.res_hist == ref[2]
             _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
     op.close()
+
+
+# ---------------------------------------------------------------------------
+# multi-RHS
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("L", [(6, 4, 2, 6), (10, 6, 4, 6)])
+@pytest.mark.parametrize("prec,nrhs", [("f64", 3), ("f64", 12), ("bf16", 12), ("f32", 5)])
+def test_matpc_multi_matches_oracle(ctx, L, prec, nrhs):
+    U = _gauge(L, 0.3, 25)
+    kappa, csw = 0.124, 1.0
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, "f64" if prec == "f64" else prec, 12)
+    Vh = int(np.prod(L)) // 2
+    xs = np.stack([li.gaussian_source(L, 100 + k).reshape(-1, 4, 3)[:Vh] for k in range(nrhs)])
+    out = torch.empty(xs.shape, dtype=torch.complex128, device="cuda")
+    q.qcdw_op_matpc_multi(op, prec, dev(xs), out)
+    Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), kappa, csw)
+    got = host(out)
+    for k in range(nrhs):
+        expect = oracle.schur_matpc(L, U, Ainv, xs[k], kappa)
+        if prec == "f64":
+            assert rel(got[k], expect) < 1e-13, k
+        else:
+            err = np.linalg.norm(got[k] - expect) / np.linalg.norm(expect)
+            assert err < (2e-6 if prec == "f32" else 2e-2), (k, err)
+    # the single-RHS kernel agrees to rounding in the same storage precision
+    one = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_op_matpc(op, prec, dev(xs[nrhs - 1]), one)
+    bound = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-2}[prec]
+    assert rel(host(one), got[nrhs - 1]) < bound
+    op.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "bf16"])
+def test_invert_multi_propagator(ctx, inner):
+    """12 point sources (all spins and colours): lockstep solve equals 12 single solves."""
+    L = (8, 8, 8, 16)
+    U = _gauge(L, 0.25, 26)
+    kappa, csw = 0.122, 1.1
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, inner)
+    bs = np.stack([li.point_source(L, s, c) for s in range(4) for c in range(3)])
+    x = torch.zeros(bs.shape, dtype=torch.complex128, device="cuda")
+    prm = q.make_params(tol=1e-10, inner=inner, delta=0.2)
+    infos = q.qcdw_invert_multi(op, dev(bs), x, prm)
+    Cn = oracle.clover_build(L, U)
+    xh = host(x)
+    for k in range(12):
+        assert infos[k].status == q.QCDW_OK, (k, infos[k])
+        tr = np.linalg.norm(bs[k] - oracle.dirac(L, U, Cn, xh[k], kappa, csw)) / np.linalg.norm(bs[k])
+        assert tr <= 1e-10, (k, tr)
+    for k in (0, 7, 11):
+        x1 = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+        info = q.qcdw_invert(op, dev(bs[k]), x1, prm)
+        assert info.status == q.QCDW_OK
+        assert np.linalg.norm(host(x1) - xh[k]) / np.linalg.norm(xh[k]) < 1e-8
+    op.close()
+
+
+def test_invert_multi_masks_finished_rhs(ctx):
+    """A zero RHS and an easy RHS finish early; the others keep iterating alone."""
+    L = (6, 4, 2, 6)
+    U = _gauge(L, 0.25, 27)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), 0.122, 1.0)
+    b = np.stack([li.gaussian_source(L, 30), np.zeros(li.fermion_shape(L)), li.gaussian_source(L, 31)])
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    x[2] = dev(oracle.bicgstab(L, U, oracle.clover_build(L, U), b[2], 0.122, 1.0, tol=1e-9).x)
+    infos = q.qcdw_invert_multi(op, dev(b), x, q.make_params())
+    assert [i.status for i in infos] == [q.QCDW_OK] * 3
+    assert float(x[1].abs().max()) == 0.0
+    assert infos[2].iters < infos[0].iters
+    op.close()
+
+
+# ---------------------------------------------------------------------------
+# batched solves of different lattices and kappas
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("inner", ["f64", "bf16"])
+def test_invert_batch_uneven(ctx, inner):
+    """Lattices of different sizes and kappas in one lockstep batch; each equals its solo solve."""
+    specs = [((4, 4, 4, 4), 0.115), ((6, 4, 2, 6), 0.121), ((8, 8, 8, 16), 0.124), ((10, 6, 4, 6), 0.118),
+             ((4, 4, 4, 4), 0.123)]
+    ops, Us, bs, xs = [], [], [], []
+    for k, (L, kappa) in enumerate(specs):
+        U = li.random_gauge(L, 0.25, 100 + k)
+        Us.append(U)
+        ops.append(q.Operator(ctx, q.make_lattice(L), dev(U), kappa, 1.0, inner))
+        bs.append(dev(li.gaussian_source(L, 1100 + k)))
+        xs.append(torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda"))
+    batch = q.Batch(ctx, ops)
+    prm = q.make_params(tol=1e-10, inner=inner, delta=0.2)
+    infos = q.qcdw_invert_batch(batch, bs, xs, prm)
+    for k, (L, kappa) in enumerate(specs):
+        assert infos[k].status == q.QCDW_OK, (k, infos[k])
+        bh = host(bs[k])
+        Cn = oracle.clover_build(L, Us[k])
+        tr = np.linalg.norm(bh - oracle.dirac(L, Us[k], Cn, host(xs[k]), kappa, 1.0)) / np.linalg.norm(bh)
+        assert tr <= 1e-10, (k, tr)
+        x1 = torch.zeros_like(xs[k])
+        solo = q.qcdw_invert(ops[k], bs[k], x1, prm)
+        assert solo.status == q.QCDW_OK
+        assert np.linalg.norm(host(x1) - host(xs[k])) / np.linalg.norm(host(x1)) < 1e-8
+    # the batch is reusable (cached graphs and tuned grid), with the same result
+    xs2 = [torch.zeros_like(x) for x in xs]
+    infos2 = q.qcdw_invert_batch(batch, bs, xs2, prm)
+    for k in range(len(specs)):
+        assert infos2[k].status == q.QCDW_OK and infos2[k].iters == infos[k].iters
+        assert np.array_equal(host(xs2[k]), host(xs[k]))
+    batch.close()
+    for op in ops:
+        op.close()
+
+
+def test_invert_batch_many_small_problems(ctx):
+    """More problems than right-hand sides of a propagator (regression: per-problem host staging)."""
+    n = 24
+    L = (4, 4, 4, 4)
+    ops, bs, xs, Us, ks = [], [], [], [], []
+    for k in range(n):
+        U = li.random_gauge(L, 0.25, 200 + k)
+        kappa = 0.115 + 0.0004 * k
+        Us.append(U)
+        ks.append(kappa)
+        ops.append(q.Operator(ctx, q.make_lattice(L), dev(U), kappa, 1.0))
+        bs.append(dev(li.gaussian_source(L, 1200 + k)))
+        xs.append(torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda"))
+    batch = q.Batch(ctx, ops)
+    infos = q.qcdw_invert_batch(batch, bs, xs, q.make_params())
+    for k in range(n):
+        assert infos[k].status == q.QCDW_OK
+        bh = host(bs[k])
+        r = bh - oracle.dirac(L, Us[k], oracle.clover_build(L, Us[k]), host(xs[k]), ks[k], 1.0)
+        assert np.linalg.norm(r) / np.linalg.norm(bh) <= 1e-10
+    batch.close()
+    for op in ops:
+        op.close()
