@@ -33,6 +33,8 @@
  *     contiguous torch tensor); the library never frees it;
  *   - the library owns its workspaces (packed links, clover inverse, Krylov
  *     vectors) inside a context or operator and frees them in *_destroy;
+ *     objects must be destroyed before what they reference: nets and batches
+ *     before their operators, operators before their context;
  *   - no exception crosses the ABI: each call returns a qcdw_status, and
  *     qcdw_last_error(ctx) describes the last failure on that context;
  *   - invalid arguments (odd extents, null pointers, host pointers, tol <= 0)
@@ -52,6 +54,7 @@ extern "C" {
 typedef struct qcdw_ctx qcdw_ctx;
 typedef struct qcdw_op qcdw_op;
 typedef struct qcdw_batch qcdw_batch;
+typedef struct qcdw_net qcdw_net;
 
 typedef struct {
     int32_t L[4];  /* Lx, Ly, Lz, Lt: each even and >= 2 */
@@ -85,6 +88,8 @@ typedef struct {
     int32_t use_graph;     /* 1: each chunk of check_every iterations is captured once into a
                               hipGraph (cached on the operator) and replayed; 0: eager launches.
                               Both run the same kernels in the same order (bitwise equal x). */
+    int32_t gmres_restart; /* FGMRES: Krylov vectors per restart cycle (1..64) */
+    int32_t gmres_fallback;/* FGMRES: 1 = hand a stalled solve to BiCGStab, 0 = keep restarting */
     int32_t pad_;
 } qcdw_solver_params;
 
@@ -102,12 +107,14 @@ typedef struct {
     int32_t n_hop[3];      /* launches timed, same kinds */
     int32_t hist_len;      /* in: capacity of res_hist (entries) */
     int32_t hist_count;    /* out: entries written */
+    int32_t fallback;      /* FGMRES: 1 if it stalled and BiCGStab finished the solve */
+    int32_t fallback_iters;/* FGMRES: BiCGStab iterations of the fallback (included in iters) */
     double *res_hist;      /* in: host buffer or NULL; out: relative residual after each
                               iteration (entry 0 = initial) */
 } qcdw_solve_info;
 
 /* Defaults: tol 1e-10, maxiter 10000, inner F64, delta 0.1, check_every 8,
-   max_restarts 8, collect_timing 0, fault_inject 0, use_graph 1. */
+   max_restarts 8, collect_timing 0, fault_inject 0, use_graph 1, gmres_restart 32, gmres_fallback 1. */
 void qcdw_solver_params_default(qcdw_solver_params *p);
 
 /* Context bound to one device and one HIP stream (hipStream_t, may be NULL for
@@ -193,6 +200,58 @@ void qcdw_batch_destroy(qcdw_batch *batch);
    info: n entries.  Same conventions as qcdw_invert for each problem. */
 qcdw_status qcdw_invert_batch(qcdw_batch *batch, const void *const b[], void *const x[],
                               const qcdw_solver_params *params, qcdw_solve_info *info);
+
+/* Learned gauge-covariant preconditioner (the paper's accelerator for clover
+   solves is multigrid, Sec. II.E; this follows the published idea of
+   gauge-equivariant convolutions, Favoni et al. 2022, Lehner and Wettig 2023).
+   Two linear layers on the full lattice, 4 -> hidden -> 4 channels (input
+   channels = spins), each out_c'(x) = sum_{a in {0, +-mu}} sum_c W_a[c', c]
+   (T_a phi_c)(x) with T_{+mu} phi(x) = U_mu(x) phi(x+mu), T_{-mu} phi(x) =
+   U_mu(x-mu)^+ phi(x-mu); no bias, no nonlinearity.  As a preconditioner of the
+   even-odd system it maps an even-site field r_e to restrict_even(net(embed r_e)).
+   Weights: complex, [9][cout][cin], hop order a = 0, +x, -x, +y, -y, +z, -z, +t, -t.
+   The net holds an FP32 copy of the operator's reconstruct-12 links; op must be
+   reconstruct-12 and must outlive the net.  Training and gradients use FP32
+   activations; application for FGMRES uses BF16 hidden activations. */
+qcdw_status qcdw_net_create(qcdw_op *op, int hidden, uint64_t seed, double init_scale, qcdw_net **net);
+void qcdw_net_destroy(qcdw_net *net);
+/* Rebind the net to another operator on a lattice of the same extents (another gauge field of
+   the same ensemble): the links are copied, weights and Adam moments are kept, so training can
+   continue on several fields and the trained net can precondition a field it has not seen (the
+   layers are gauge-covariant with field-independent weights).  op must be reconstruct-12, on the
+   same context, and must outlive the net (or a later rebinding).  EINVAL on mismatch. */
+qcdw_status qcdw_net_bind(qcdw_net *net, qcdw_op *op);
+/* host arrays of 2*9*hidden*4 doubles (re, im interleaved), W1 [9][hidden][4], W2 [9][4][hidden] */
+qcdw_status qcdw_net_get_weights(qcdw_net *net, double *w1, double *w2);
+qcdw_status qcdw_net_set_weights(qcdw_net *net, const double *w1, const double *w2);
+/* out_e = P(in_e); even-site fermion fields [Lt,Lz,Ly,Lx/2,4,3] complex FP64 on the device.
+   prec: QCDW_F32 (FP32 activations) or QCDW_BF16 (BF16 hidden activations). */
+qcdw_status qcdw_net_apply(qcdw_net *net, qcdw_prec prec, const void *in_e, void *out_e);
+/* loss = sum_k ||P(r_k) - e_k||^2 / ||e_k||^2 over npairs even-site pairs (device pointers,
+   FP64), and its gradients dL/dRe W + i dL/dIm W into host arrays g1, g2 (layout as the weights). */
+qcdw_status qcdw_net_loss_grad(qcdw_net *net, int npairs, const void *const r_e[], const void *const e_e[],
+                               double *loss, double *g1, double *g2);
+/* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) on mini-batches of `batch` pairs drawn in a
+   seeded shuffled order; loss_hist (host, `steps` entries or NULL) receives each batch's mean loss. */
+qcdw_status qcdw_net_train(qcdw_net *net, int npairs, const void *const r_e[], const void *const e_e[], int steps,
+                           int batch, double lr, uint64_t seed, double *loss_hist);
+/* Flexible GMRES(m) (Saad 1993, m = params->gmres_restart) on the even-odd system with right
+   preconditioning z = P(v) (net may be NULL: no preconditioner), block classical Gram-Schmidt
+   with one reorthogonalisation.  With params->gmres_fallback, a restart cycle that reduces the
+   residual by less than 10 % hands the solve to BiCGStab in the operator's inner precision from
+   the current iterate.  The final acceptance is the FP64 true residual of the full system, as
+   for qcdw_invert. */
+/* Solver-generated training pairs for the net: x* from an FP64 solve of M x = b to 1e-12; the
+   iterates x_k of FP64 BiCGStab restarted every `stride` iterations from zero, k = 1..npairs;
+   e_k = (x* - x_k) on even sites and r_k = M_hat e_k, both scaled so that ||r_k|| = 1.
+   With stride < 0 the errors are instead seeded Gaussian fields (seed = -stride, stream k) and
+   r_k = M_hat e_k (b is not used): pairs that weight all modes alike.
+   r_e[k], e_e[k]: caller-owned even-site fields [Lt,Lz,Ly,Lx/2,4,3] complex FP64 on the device.
+   *made receives the number of pairs written (fewer than npairs if the iteration converged). */
+qcdw_status qcdw_make_training_pairs(qcdw_op *op, const void *b, int npairs, int stride, void *const r_e[],
+                                     void *const e_e[], int *made);
+qcdw_status qcdw_invert_fgmres(qcdw_op *op, qcdw_net *net, const void *b, void *x, const qcdw_solver_params *params,
+                               qcdw_solve_info *info);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
@@ -35,6 +36,8 @@ EXPORTED = (
     "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_op_create",
     "qcdw_op_destroy", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
+    "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
+    "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
 )
 
 
@@ -59,6 +62,8 @@ class qcdw_solver_params(ctypes.Structure):
         ("collect_timing", ctypes.c_int32),
         ("fault_inject", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("gmres_restart", ctypes.c_int32),
+        ("gmres_fallback", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
     ]
 
@@ -76,6 +81,8 @@ class qcdw_solve_info(ctypes.Structure):
         ("n_hop", ctypes.c_int32 * 3),
         ("hist_len", ctypes.c_int32),
         ("hist_count", ctypes.c_int32),
+        ("fallback", ctypes.c_int32),
+        ("fallback_iters", ctypes.c_int32),
         ("res_hist", ctypes.POINTER(ctypes.c_double)),
     ]
 
@@ -112,6 +119,16 @@ def load_library(path: str = LIB_PATH):
         "qcdw_invert_multi": (i, [p, i, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
         "qcdw_batch_create": (i, [p, i, ctypes.POINTER(p), ctypes.POINTER(p)]),
         "qcdw_batch_destroy": (None, [p]),
+        "qcdw_net_create": (i, [p, i, ctypes.c_uint64, d, ctypes.POINTER(p)]),
+        "qcdw_net_destroy": (None, [p]),
+        "qcdw_net_bind": (i, [p, p]),
+        "qcdw_net_get_weights": (i, [p, p, p]),
+        "qcdw_net_set_weights": (i, [p, p, p]),
+        "qcdw_net_apply": (i, [p, i, p, p]),
+        "qcdw_net_loss_grad": (i, [p, i, ctypes.POINTER(p), ctypes.POINTER(p), ctypes.POINTER(d), p, p]),
+        "qcdw_net_train": (i, [p, i, ctypes.POINTER(p), ctypes.POINTER(p), i, i, d, ctypes.c_uint64, p]),
+        "qcdw_make_training_pairs": (i, [p, p, i, i, ctypes.POINTER(p), ctypes.POINTER(p), ctypes.POINTER(i)]),
+        "qcdw_invert_fgmres": (i, [p, p, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
         "qcdw_invert_batch": (i, [p, ctypes.POINTER(p), ctypes.POINTER(p), ctypes.POINTER(qcdw_solver_params),
                                   ctypes.POINTER(qcdw_solve_info)]),
     }
@@ -173,14 +190,24 @@ class Context:
             stream = torch.cuda.current_stream(device)
         self.device = device
         self.stream = stream
+        self._children = weakref.WeakSet()  # objects that must be destroyed before the context
         h = ctypes.c_void_p()
         st = lib.qcdw_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
         if st != QCDW_OK:
             raise QcdwError(st, "qcdw_ctx_create failed")
         self.handle = h
 
+    def _adopt(self, obj):
+        self._children.add(obj)
+
     def close(self):
         if getattr(self, "handle", None):
+            # nets and batches reference operators, operators reference the context
+            kids = list(self._children)
+            for rank in (0, 1, 2):
+                for k in kids:
+                    if getattr(k, "_rank", 2) == rank:
+                        k.close()
             load_library().qcdw_ctx_destroy(self.handle)
             self.handle = None
 
@@ -252,6 +279,8 @@ def qcdw_dslash(ctx: Context, lat: qcdw_lattice, U, clover, psi, out, kappa: flo
 class Operator:
     """qcdw_op: packed links, clover inverse and solver workspace for one (U, kappa, csw)."""
 
+    _rank = 2  # destroyed after the nets and batches that use it
+
     def __init__(self, ctx: Context, lat: qcdw_lattice, U, kappa: float, csw: float, inner="f64", recon: int = 12):
         self.ctx = ctx
         self.lat = lat
@@ -265,9 +294,13 @@ class Operator:
                                            float(kappa), float(csw), self.inner, int(recon), ctypes.byref(h))
         _check(ctx.handle, st)
         self.handle = h
+        self._children = weakref.WeakSet()
+        ctx._adopt(self)
 
     def close(self):
         if getattr(self, "handle", None):
+            for k in list(self._children):
+                k.close()
             load_library().qcdw_op_destroy(self.handle)
             self.handle = None
 
@@ -318,6 +351,8 @@ class SolveInfo:
         self.time_ms = info.time_ms
         self.hop_ms = list(info.hop_ms)
         self.n_hop = list(info.n_hop)
+        self.fallback = info.fallback
+        self.fallback_iters = info.fallback_iters
         self.res_hist = list(hist[: info.hist_count]) if hist is not None else []
 
     def __repr__(self):
@@ -326,7 +361,8 @@ class SolveInfo:
 
 
 def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8, max_restarts=8,
-                collect_timing=False, fault_inject=0, use_graph=True) -> qcdw_solver_params:
+                collect_timing=False, fault_inject=0, use_graph=True, gmres_restart=32,
+                gmres_fallback=True) -> qcdw_solver_params:
     prm = qcdw_solver_params_default()
     prm.tol = float(tol)
     prm.maxiter = int(maxiter)
@@ -337,6 +373,8 @@ def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8,
     prm.collect_timing = 1 if collect_timing else 0
     prm.fault_inject = int(fault_inject)
     prm.use_graph = 1 if use_graph else 0
+    prm.gmres_restart = int(gmres_restart)
+    prm.gmres_fallback = 1 if gmres_fallback else 0
     return prm
 
 
@@ -383,6 +421,8 @@ def qcdw_invert_multi(op: Operator, b, x, params: qcdw_solver_params | None = No
 class Batch:
     """qcdw_batch: operators of different lattices / kappas solved in lockstep."""
 
+    _rank = 1
+
     def __init__(self, ctx: Context, ops):
         self.ctx = ctx
         self.ops = list(ops)  # keep the operators alive
@@ -391,6 +431,9 @@ class Batch:
         st = load_library().qcdw_batch_create(ctx.handle, len(self.ops), arr, ctypes.byref(h))
         _check(ctx.handle, st)
         self.handle = h
+        ctx._adopt(self)
+        for o in self.ops:
+            o._children.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -434,3 +477,154 @@ def qcdw_invert_batch(batch: Batch, bs, xs, params: qcdw_solver_params | None = 
     if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
         _check(batch.ctx.handle, st)
     return [SolveInfo(infos[k], hists[k]) for k in range(n)]
+
+
+class Net:
+    """qcdw_net: the learned gauge-covariant preconditioner of one operator."""
+
+    _rank = 0
+
+    def __init__(self, op: Operator, hidden: int = 12, seed: int = 0, init_scale: float = 0.01):
+        self.op = op
+        self.hidden = hidden
+        h = ctypes.c_void_p()
+        st = load_library().qcdw_net_create(op.handle, int(hidden), int(seed), float(init_scale), ctypes.byref(h))
+        _check(op.ctx.handle, st)
+        self.handle = h
+        op.ctx._adopt(self)
+        op._children.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().qcdw_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qcdw_net_create(op: Operator, hidden: int = 12, seed: int = 0, init_scale: float = 0.01) -> Net:
+    return Net(op, hidden, seed, init_scale)
+
+
+def qcdw_net_destroy(net: Net) -> None:
+    net.close()
+
+
+def qcdw_net_bind(net: Net, op: Operator) -> None:
+    """Move the net to another operator of the same lattice (weights and Adam state kept)."""
+    _check(net.op.ctx.handle, load_library().qcdw_net_bind(net.handle, op.handle))
+    net.op._children.discard(net)
+    net.op = op
+    op._children.add(net)
+
+
+def _wshape(net):
+    return (9, net.hidden, 4), (9, 4, net.hidden)
+
+
+def qcdw_net_get_weights(net: Net):
+    """(W1, W2) as complex NumPy arrays [9][hidden][4], [9][4][hidden]."""
+    import numpy as np
+
+    s1, s2 = _wshape(net)
+    w1 = np.zeros(2 * int(np.prod(s1)))
+    w2 = np.zeros(2 * int(np.prod(s2)))
+    st = load_library().qcdw_net_get_weights(net.handle, w1.ctypes.data_as(ctypes.c_void_p),
+                                             w2.ctypes.data_as(ctypes.c_void_p))
+    _check(net.op.ctx.handle, st)
+    return w1.view(np.complex128).reshape(s1), w2.view(np.complex128).reshape(s2)
+
+
+def qcdw_net_set_weights(net: Net, W1, W2) -> None:
+    import numpy as np
+
+    s1, s2 = _wshape(net)
+    w1 = np.ascontiguousarray(np.asarray(W1, dtype=np.complex128).reshape(s1)).view(np.float64)
+    w2 = np.ascontiguousarray(np.asarray(W2, dtype=np.complex128).reshape(s2)).view(np.float64)
+    st = load_library().qcdw_net_set_weights(net.handle, w1.ctypes.data_as(ctypes.c_void_p),
+                                             w2.ctypes.data_as(ctypes.c_void_p))
+    _check(net.op.ctx.handle, st)
+
+
+def qcdw_net_apply(net: Net, prec, in_e, out_e) -> None:
+    prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    _need(in_e, 6 * net.op.volume, "in_e")
+    _need(out_e, 6 * net.op.volume, "out_e")
+    st = load_library().qcdw_net_apply(net.handle, prec, _ptr(in_e, torch.complex128, "in_e"),
+                                       _ptr(out_e, torch.complex128, "out_e"))
+    _check(net.op.ctx.handle, st)
+
+
+def _ptr_array(ts, n_each, name):
+    for t in ts:
+        _need(t, n_each, name)
+    return (ctypes.c_void_p * len(ts))(*[_ptr(t, torch.complex128, name).value for t in ts])
+
+
+def qcdw_net_loss_grad(net: Net, r_e, e_e):
+    """(loss, G1, G2) over the pairs; G = dL/dRe W + i dL/dIm W as complex NumPy arrays."""
+    import numpy as np
+
+    s1, s2 = _wshape(net)
+    g1 = np.zeros(2 * int(np.prod(s1)))
+    g2 = np.zeros(2 * int(np.prod(s2)))
+    loss = ctypes.c_double()
+    n6 = 6 * net.op.volume
+    st = load_library().qcdw_net_loss_grad(net.handle, len(r_e), _ptr_array(r_e, n6, "r_e"),
+                                           _ptr_array(e_e, n6, "e_e"), ctypes.byref(loss),
+                                           g1.ctypes.data_as(ctypes.c_void_p), g2.ctypes.data_as(ctypes.c_void_p))
+    _check(net.op.ctx.handle, st)
+    return loss.value, g1.view(np.complex128).reshape(s1), g2.view(np.complex128).reshape(s2)
+
+
+def qcdw_net_train(net: Net, r_e, e_e, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0):
+    """Adam training on the GPU; returns the per-step batch-mean loss."""
+    import numpy as np
+
+    hist = np.zeros(max(1, steps))
+    n6 = 6 * net.op.volume
+    st = load_library().qcdw_net_train(net.handle, len(r_e), _ptr_array(r_e, n6, "r_e"), _ptr_array(e_e, n6, "e_e"),
+                                       int(steps), int(batch), float(lr), int(seed),
+                                       hist.ctypes.data_as(ctypes.c_void_p))
+    _check(net.op.ctx.handle, st)
+    return hist[:steps]
+
+
+def qcdw_make_training_pairs(op: Operator, b, npairs: int, stride: int):
+    """(r_e, e_e) pairs as lists of device tensors [Vh, 4, 3]: errors of a solve of b
+    (stride > 0), or seeded Gaussian errors (stride < 0, seed -stride, b unused; may be None)."""
+    if stride >= 0 or b is not None:
+        _need(b, 12 * op.volume, "b")
+    Vh = op.volume // 2
+    r = [torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda") for _ in range(npairs)]
+    e = [torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda") for _ in range(npairs)]
+    made = ctypes.c_int()
+    bp = _ptr(b, torch.complex128, "b") if b is not None else None
+    st = load_library().qcdw_make_training_pairs(op.handle, bp, int(npairs), int(stride),
+                                                 _ptr_array(r, 6 * op.volume, "r_e"),
+                                                 _ptr_array(e, 6 * op.volume, "e_e"), ctypes.byref(made))
+    _check(op.ctx.handle, st)
+    return r[: made.value], e[: made.value]
+
+
+def qcdw_invert_fgmres(op: Operator, net, b, x, params: qcdw_solver_params | None = None):
+    """FGMRES(m) with the net as right preconditioner (net None: none); returns a SolveInfo."""
+    if params is None:
+        params = make_params()
+    _need(b, 12 * op.volume, "b")
+    _need(x, 12 * op.volume, "x")
+    n_hist = max(1, params.maxiter + 2)
+    hist = (ctypes.c_double * n_hist)()
+    info = qcdw_solve_info()
+    info.hist_len = n_hist
+    info.res_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    st = load_library().qcdw_invert_fgmres(op.handle, net.handle if net is not None else None,
+                                           _ptr(b, torch.complex128, "b"), _ptr(x, torch.complex128, "x"),
+                                           ctypes.byref(params), ctypes.byref(info))
+    if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
+        _check(op.ctx.handle, st)
+    return SolveInfo(info, hist)

@@ -150,6 +150,25 @@ hipError_t launch_hop_mrhs(hipStream_t s, int prec, int epi, int red, const HopA
 hipError_t launch_hop_rhs(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// learned preconditioner layers (activations [parity][channel][Vh][3], FP32/BF16 storage)
+hipError_t launch_net_layer(hipStream_t s, int pin, int pout, int cin, int cout, const void* in, void* out,
+                            const void* gauge32, const void* W, const Geom& g);
+// out[2 cin cout] (+)= weight gradient of hop a: sum_x g_{c'} conj(T_a phi_c); partials: [blocks][2 cin cout]
+hipError_t launch_net_wgrad(hipStream_t s, int cin, int cout, const void* phi, const void* gz, const void* gauge32,
+                            const Geom& g, int a, double* partials, double* out, int accumulate);
+hipError_t launch_net_adjoint_w(hipStream_t s, const void* W, void* Wt, int cout, int cin);
+hipError_t launch_net_make_gz(hipStream_t s, const void* diff, void* gz, long n_half, double coef);
+hipError_t launch_gaussian(hipStream_t s, void* out, long n, uint64_t seed, uint64_t stream);  // FP64 complex
+hipError_t launch_adam(hipStream_t s, void* W, const double* G, double* m, double* v, int n, double lr, double b1,
+                       double b2, double eps, int step, double gscale);
+
+// FGMRES block Gram-Schmidt on FP64 vectors V_i = V + i stride (complex elements)
+hipError_t launch_scale_inv_norm(hipStream_t s, const void* w, void* out, long n, const double* nrm2);
+hipError_t launch_multidot(hipStream_t s, const void* V, long stride, int nvec, const void* w, long n,
+                           double* partials, double* out);  // out[2i..] = (V_i, w); partials: 16 ceil(nvec/8) blocks
+hipError_t launch_multiaxpy(hipStream_t s, const void* V, long stride, int nvec, const double* c, void* w, long n,
+                            double sign);  // w += sign sum_i c_i V_i
+
 // pack / unpack between the paper layouts and the internal ones
 hipError_t launch_pack_spinor(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal,
                               double scale);

@@ -1,0 +1,311 @@
+// Kernels of the learned gauge-covariant preconditioner (the published idea of
+// gauge-equivariant convolutions: Favoni et al. 2022, Lehner and Wettig 2023;
+// the paper's own accelerator for clover solves is multigrid, Sec. II.E).
+//
+// A layer maps CIN channels phi_c (colour 3-vector fields on the full lattice)
+// to COUT channels:  out_{c'}(x) = sum_a sum_c W_a[c', c] (T_a phi_c)(x),
+// a in {0, +-mu}: T_0 = 1, (T_{+mu} phi)(x) = U_mu(x) phi(x+mu),
+// (T_{-mu} phi)(x) = U_mu(x-mu)^+ phi(x-mu).  Hop index a = 1 + 2 mu + back.
+// Activation layout [parity][channel][Vh][3] complex: with 4 channels it is two
+// internal spinor fields (even, odd), so spins are the input/output channels.
+// Links: the operator's reconstruct-12 internal layout, FP32.  Arithmetic FP32.
+#include "internal.h"
+
+namespace qcdw {
+
+struct NetArgs {
+    const void* in;
+    void* out;
+    const void* gauge;  // P32 [4][2][Vh][6]
+    const float2* W;    // [9][COUT][CIN]
+    Geom g;
+};
+
+__device__ __forceinline__ void su3_row3(const void* gauge, long off, cx<float> (&u)[9])
+{
+#pragma unroll
+    for (int e = 0; e < 6; e++) u[e] = P32::ld(gauge, off + e);
+    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
+// neighbour (parity 1 - p) of site i of parity p one step along mu (dir 0 forward, 1 backward)
+__device__ __forceinline__ int nbr_index(const Geom& g, int i, int x, int y, int z, int t, int mu, int dir)
+{
+    const int xh = i % g.Lxh;
+    switch (mu) {
+    case 0: {
+        const int row = i - xh;
+        const int xn = dir == 0 ? ((x + 1 == g.Lx) ? 0 : x + 1) : ((x == 0) ? g.Lx - 1 : x - 1);
+        return row + (xn >> 1);
+    }
+    case 1: {
+        const int S = g.Lxh;
+        return dir == 0 ? ((y + 1 == g.Ly) ? i - (g.Ly - 1) * S : i + S) : ((y == 0) ? i + (g.Ly - 1) * S : i - S);
+    }
+    case 2: {
+        const int S = g.Lxh * g.Ly;
+        return dir == 0 ? ((z + 1 == g.Lz) ? i - (g.Lz - 1) * S : i + S) : ((z == 0) ? i + (g.Lz - 1) * S : i - S);
+    }
+    default: {
+        const int S = g.Lxh * g.Ly * g.Lz;
+        return dir == 0 ? ((t + 1 == g.Lt) ? i - (g.Lt - 1) * S : i + S) : ((t == 0) ? i + (g.Lt - 1) * S : i - S);
+    }
+    }
+}
+
+// Y[c] = (T_a phi_c)(x) for the site (p, i)
+template <class PI, int CIN>
+__device__ __forceinline__ void transport(const void* in, const void* gauge, const Geom& g, int p, int i, int x,
+                                          int y, int z, int t, int a, cx<float> (&Y)[CIN][3])
+{
+    const long Vh = g.Vh;
+    if (a == 0) {
+#pragma unroll
+        for (int c = 0; c < CIN; c++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const auto v = PI::ld(in, (((long)p * CIN + c) * Vh + i) * 3 + k);
+                Y[c][k] = {(float)v.re, (float)v.im};
+            }
+        return;
+    }
+    const int mu = (a - 1) >> 1, back = (a - 1) & 1;
+    const int j = nbr_index(g, i, x, y, z, t, mu, back);
+    cx<float> u[9];
+    su3_row3(gauge, back == 0 ? (((long)mu * 2 + p) * Vh + i) * 6 : (((long)mu * 2 + (1 - p)) * Vh + j) * 6, u);
+#pragma unroll
+    for (int c = 0; c < CIN; c++) {
+        cx<float> v[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const auto w = PI::ld(in, (((long)(1 - p) * CIN + c) * Vh + j) * 3 + k);
+            v[k] = {(float)w.re, (float)w.im};
+        }
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            cx<float> s = {0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 3; k++) s = back == 0 ? s + u[3 * r + k] * v[k] : s + cmul_conj(u[3 * k + r], v[k]);
+            Y[c][r] = s;
+        }
+    }
+}
+
+template <class PI, class PO, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_net_layer(NetArgs n)
+{
+    const Geom g = n.g;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2L * g.Vh) return;
+    const int p = (int)(gid / g.Vh), i = (int)(gid % g.Vh);
+    int x, y, z, t;
+    site_coords(g, i, p, x, y, z, t);
+    cx<float> acc[COUT][3];
+#pragma unroll
+    for (int d = 0; d < COUT; d++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) acc[d][k] = {0.f, 0.f};
+    for (int a = 0; a < 9; a++) {
+        cx<float> Y[CIN][3];
+        transport<PI, CIN>(n.in, n.gauge, g, p, i, x, y, z, t, a, Y);
+        const float2* Wa = n.W + (long)a * COUT * CIN;
+#pragma unroll
+        for (int d = 0; d < COUT; d++)
+#pragma unroll
+            for (int c = 0; c < CIN; c++) {
+                const float2 w = Wa[d * CIN + c];
+                const cx<float> wc = {w.x, w.y};
+#pragma unroll
+                for (int k = 0; k < 3; k++) acc[d][k] = acc[d][k] + wc * Y[c][k];
+            }
+    }
+    using TO = typename PO::real;
+#pragma unroll
+    for (int d = 0; d < COUT; d++)
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            PO::st(n.out, (((long)p * COUT + d) * g.Vh + i) * 3 + k, cx<TO>{(TO)acc[d][k].re, (TO)acc[d][k].im});
+}
+
+// per-block partials of G_a[c', c] = sum_x sum_k g_{c'}(x)_k conj((T_a phi_c)(x)_k), one hop a per launch;
+// reduced one output channel at a time to bound register use
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_net_wgrad(const void* phi, const void* gz, const void* gauge, Geom g, int a,
+                                                   double* partials)
+{
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = gid < 2L * g.Vh;
+    const int p = valid ? (int)(gid / g.Vh) : 0, i = valid ? (int)(gid % g.Vh) : 0;
+    cx<float> Y[CIN][3];
+    if (valid) {
+        int x, y, z, t;
+        site_coords(g, i, p, x, y, z, t);
+        transport<P32, CIN>(phi, gauge, g, p, i, x, y, z, t, a, Y);
+    } else {
+#pragma unroll
+        for (int c = 0; c < CIN; c++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) Y[c][k] = {0.f, 0.f};
+    }
+    double* base = partials + (long)blockIdx.x * 2 * CIN * COUT;
+    for (int d = 0; d < COUT; d++) {
+        cx<float> gd[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            gd[k] = valid ? P32::ld(gz, (((long)p * COUT + d) * g.Vh + i) * 3 + k) : cx<float>{0.f, 0.f};
+        double v[2 * CIN];
+#pragma unroll
+        for (int c = 0; c < CIN; c++) {
+            cx<float> s = {0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 3; k++) s = s + cmul_conj(Y[c][k], gd[k]);  // g conj(Y)
+            v[2 * c] = s.re;
+            v[2 * c + 1] = s.im;
+        }
+        block_sum_store<2 * CIN>(v, base + 2 * CIN * d);
+        __syncthreads();  // the block reduction's shared buffer is reused for the next channel
+    }
+}
+
+// out[e] (+)= sum over nb blocks of partials[b][e], e < K; one block per 64 entries
+__global__ __launch_bounds__(256) void k_sum_columns(const double* partials, int nb, int K, double* out, int accumulate)
+{
+    const int e = blockIdx.x;
+    if (e >= K) return;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += 256) v[0] += partials[(long)b * K + e];
+    __shared__ double res[1];
+    block_sum_store<1>(v, res);
+    __syncthreads();
+    if (threadIdx.x == 0) out[e] = accumulate ? out[e] + res[0] : res[0];
+}
+
+// Wt[a'][c][d] = conj(W[a][d][c]), a' the reversed hop (T_a^+ = T_a'), for the adjoint layer
+__global__ void k_net_adjoint_w(const float2* W, float2* Wt, int cout, int cin)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 9 * cout * cin) return;
+    const int a = e / (cout * cin), r = e % (cout * cin), d = r / cin, c = r % cin;
+    const int at = a == 0 ? 0 : (((a - 1) & 1) ? a - 1 : a + 1);
+    const float2 w = W[e];
+    Wt[(long)at * cin * cout + c * cout + d] = make_float2(w.x, -w.y);
+}
+
+// gz = coef * (FP64 even field) on even sites, zero on odd sites (4 channels)
+__global__ void k_net_make_gz(const double2* diff, float2* gz, long n_half, double coef)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * n_half) return;
+    if (e < n_half) {
+        const double2 d = diff[e];
+        gz[e] = make_float2((float)(coef * d.x), (float)(coef * d.y));
+    } else {
+        gz[e] = make_float2(0.f, 0.f);
+    }
+}
+
+// Adam (Kingma and Ba 2015) on the real and imaginary parts of the weights
+__global__ void k_adam(float* W, const double* G, double* m, double* v, int n, double lr, double b1, double b2,
+                       double eps, int step, double gscale)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double g = G[e] * gscale;
+    m[e] = b1 * m[e] + (1.0 - b1) * g;
+    v[e] = b2 * v[e] + (1.0 - b2) * g * g;
+    const double mh = m[e] / (1.0 - pow(b1, (double)step));
+    const double vh = v[e] / (1.0 - pow(b2, (double)step));
+    W[e] = (float)((double)W[e] - lr * mh / (sqrt(vh) + eps));
+}
+
+// Gaussian complex entries (re, im ~ N(0,1)) from a counter-based generator:
+// splitmix64 of (seed, stream, element) feeds a Box-Muller transform, so the
+// field depends only on (seed, stream), not on the launch shape.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_gaussian(double2* out, long n, uint64_t seed, uint64_t stream)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t k = splitmix64(seed ^ splitmix64(stream ^ splitmix64((uint64_t)e)));
+    const uint64_t k2 = splitmix64(k);
+    const double u1 = ((k >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+    const double u2 = (k2 >> 11) * (1.0 / 9007199254740992.0);          // [0, 1)
+    const double rad = sqrt(-2.0 * log(u1)), th = 6.283185307179586 * u2;
+    out[e] = make_double2(rad * cos(th), rad * sin(th));
+}
+
+static inline dim3 g256(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_gaussian(hipStream_t s, void* out, long n, uint64_t seed, uint64_t stream)
+{
+    hipLaunchKernelGGL(k_gaussian, g256(n), dim3(256), 0, s, (double2*)out, n, seed, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_layer(hipStream_t s, int pin, int pout, int cin, int cout, const void* in, void* out,
+                            const void* gauge32, const void* W, const Geom& g)
+{
+    NetArgs n{in, out, gauge32, (const float2*)W, g};
+    const dim3 grid = g256(2L * g.Vh);
+#define QCDW_NET_CASE(PI, PO, CI, CO, pi, po)                                              \
+    if (pin == pi && pout == po && cin == CI && cout == CO) {                              \
+        hipLaunchKernelGGL((k_net_layer<PI, PO, CI, CO>), grid, dim3(256), 0, s, n);        \
+        return hipGetLastError();                                                          \
+    }
+    QCDW_NET_CASE(P32, P32, 4, 12, F32, F32)
+    QCDW_NET_CASE(P32, P32, 12, 4, F32, F32)
+    QCDW_NET_CASE(P32, PBF16, 4, 12, F32, BF16)
+    QCDW_NET_CASE(PBF16, P32, 12, 4, BF16, F32)
+    QCDW_NET_CASE(P32, P32, 4, 4, F32, F32)
+#undef QCDW_NET_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_net_wgrad(hipStream_t s, int cin, int cout, const void* phi, const void* gz, const void* gauge32,
+                            const Geom& g, int a, double* partials, double* out, int accumulate)
+{
+    const dim3 grid = g256(2L * g.Vh);
+    const int K = 2 * cin * cout;
+    if (cin == 4 && cout == 12)
+        hipLaunchKernelGGL((k_net_wgrad<4, 12>), grid, dim3(256), 0, s, phi, gz, gauge32, g, a, partials);
+    else if (cin == 12 && cout == 4)
+        hipLaunchKernelGGL((k_net_wgrad<12, 4>), grid, dim3(256), 0, s, phi, gz, gauge32, g, a, partials);
+    else if (cin == 4 && cout == 4)
+        hipLaunchKernelGGL((k_net_wgrad<4, 4>), grid, dim3(256), 0, s, phi, gz, gauge32, g, a, partials);
+    else
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum_columns, dim3(K), dim3(256), 0, s, partials, (int)grid.x, K, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_adjoint_w(hipStream_t s, const void* W, void* Wt, int cout, int cin)
+{
+    hipLaunchKernelGGL(k_net_adjoint_w, g256(9L * cout * cin), dim3(256), 0, s, (const float2*)W, (float2*)Wt, cout,
+                       cin);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_make_gz(hipStream_t s, const void* diff, void* gz, long n_half, double coef)
+{
+    hipLaunchKernelGGL(k_net_make_gz, g256(2 * n_half), dim3(256), 0, s, (const double2*)diff, (float2*)gz, n_half,
+                       coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(hipStream_t s, void* W, const double* G, double* m, double* v, int n, double lr, double b1,
+                       double b2, double eps, int step, double gscale)
+{
+    hipLaunchKernelGGL(k_adam, g256(n), dim3(256), 0, s, (float*)W, G, m, v, n, lr, b1, b2, eps, step, gscale);
+    return hipGetLastError();
+}
+
+}  // namespace qcdw

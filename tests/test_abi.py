@@ -79,3 +79,10 @@ def test_product_package_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 for bad in ("import oracle", "from oracle", "liboracle", "orc_"):
                     assert bad not in text, (f, bad)
+
+
+def test_binding_orders_object_destruction():
+    """Children (nets, batches, operators) are closed before their context."""
+    import paper_2411_08461_amd as q
+
+    assert q.Net._rank < q.Batch._rank < q.Operator._rank
