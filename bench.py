@@ -10,6 +10,14 @@ Workload: 16^3 x 32 lattice, kappa 0.124, csw 1.0, links exp(i 0.2 H), Z2
 source (seed 1000).  Inputs are generated on the host and copied to HBM
 before the timed region.
 
+Beside the timed steps (not part of them) the line carries the other
+workloads of the same metric: "propagator" (24^3 x 64, 12 point sources solved
+together with the multi-RHS hop in BF16 against 12 separate FP64 solves),
+"batch" (48 uneven problems in one persistent batched solve against a loop of
+single solves, solves/s) and "learned" (32^3 x 64 near the critical kappa:
+FGMRES(32) with the trained gauge-covariant preconditioner against plain FP64
+and mixed BiCGStab).  ``--bisect-kappa`` finds that kappa.
+
 Printed line (rank 0): metric/value = algorithmic bytes of the Krylov
 iterations (byte model per iteration and precision, counted with the actual
 iteration numbers) divided by the step's wall time; roofline = the dominant
@@ -48,6 +56,11 @@ def hop_b_bytes(prec):
     return hop_a_bytes(prec) + SPINOR[prec]
 
 
+def hop_a_bytes_multi(prec, nrhs):
+    """One multi-RHS hop into odd sites with A_oo^-1: links and clover once, nrhs spinors in and out."""
+    return 8 * LINK_R12[prec] + CLOVER[prec] + nrhs * 2 * SPINOR[prec]
+
+
 def iter_bytes(prec):
     s = SPINOR[prec]
     xs = SPINOR["f64"] if prec == "f64" else SPINOR["f32"]  # x is kept in FP64 / FP32
@@ -67,6 +80,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-lattice", default="24,24,24,64",
                     help="also time the hop kernel on this lattice (empty to skip)")
+    ap.add_argument("--sections", default="propagator,batch,learned",
+                    help="comma-separated extra workloads to run after the timed steps (empty: none)")
+    ap.add_argument("--bisect-kappa", action="store_true",
+                    help="find the 32^3x64 kappa at which FP64 BiCGStab first needs >= 2000 iterations, then exit")
     ap.add_argument("--matpc-only", default="",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then a few M_hat "
                          "applications in FP64 and BF16 on this lattice, e.g. 24,24,24,64; prints nothing else")
@@ -115,10 +132,31 @@ def main():
     import lattice_inputs as li
     import paper_2411_08461_amd as q
 
+    if args.bisect_kappa:
+        print(json.dumps(bisect_kappa(q, li, np, torch)))
+        return
+    sections = [v for v in args.sections.split(",") if v]
+    for sec in sections:
+        if sec not in SECTIONS:
+            raise SystemExit(f"unknown section {sec}; choose from {', '.join(SECTIONS)}")
+
+    # every host input is drawn before the GPU is initialised (the field generator forks workers)
     w = li.WORKLOADS["wc16x32"]
     L, kappa, csw = w["L"], w["kappa"], w["csw"]
     Vh = int(np.prod(L)) // 2
-    U = li.random_gauge(L, w["eps"], w["seed"])
+    jobs = {"main": [(L, w["eps"], w["seed"])]}
+    for sec in sections:
+        jobs[sec] = SECTIONS[sec][0](li)
+    flat = [j for js in jobs.values() for j in js]
+    t_gen = time.perf_counter()
+    fields = li.random_gauges(flat)
+    t_gen = time.perf_counter() - t_gen
+    host_fields, k = {}, 0
+    for name, js in jobs.items():
+        host_fields[name] = fields[k:k + len(js)]
+        k += len(js)
+    del fields
+    U = host_fields.pop("main")[0]
     b = li.z2_source(L, w["source_seed"])
 
     ctx = q.Context(0)
@@ -220,6 +258,11 @@ def main():
     if args.extra_lattice:
         result["hop_gbs_large"] = time_large_hop(q, li, np, torch, ctx, [int(v) for v in args.extra_lattice.split(",")])
 
+    for sec in sections:
+        result[sec] = SECTIONS[sec][1](q, li, np, torch, ctx, host_fields.pop(sec), args)
+        host_fields[sec] = None
+    result["input_generation_s"] = round(t_gen, 1)
+
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(li, np, L, U, b, kappa, csw, args.cpu_seconds)
 
@@ -273,6 +316,230 @@ def time_large_hop(q, li, np, torch, ctx, L):
         out[prec] = {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(ms * 1e3, 2)}
     op.close()
     return out
+
+
+def _solve_summary(infos):
+    return {"iters_max": max(i.iters for i in infos), "iters_sum": sum(i.iters for i in infos),
+            "max_true_res": max(i.true_res for i in infos),
+            "all_ok": all(i.status == 0 for i in infos)}
+
+
+def propagator_jobs(li):
+    w = li.WORKLOADS["wc24x64"]
+    return [(w["L"], w["eps"], w["seed"])]
+
+
+def propagator(q, li, np, torch, ctx, fields, args):
+    """12 point sources (all spins and colours) at 24^3x64: one lockstep multi-RHS solve with BF16
+    storage against 12 separate FP64 solves; both to an FP64 true residual of 1e-10."""
+    w = li.WORKLOADS["wc24x64"]
+    L, kappa, csw = w["L"], w["kappa"], w["csw"]
+    Vh = int(np.prod(L)) // 2
+    Ud = torch.from_numpy(fields[0]).cuda()
+    bs = torch.zeros((12,) + li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    for s in range(4):
+        for c in range(3):
+            bs[3 * s + c][0, 0, 0, 0, 0, s, c] = 1.0
+    op = q.Operator(ctx, q.make_lattice(L), Ud, kappa, csw, "bf16", 12)
+    del Ud
+    torch.cuda.empty_cache()
+    x = torch.zeros_like(bs)
+    pm = q.make_params(tol=1e-10, maxiter=20000, inner="bf16", delta=0.1)
+    q.qcdw_invert_multi(op, bs, x, pm)  # warm-up: autotuner choice and graph capture
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    multi = q.qcdw_invert_multi(op, bs, x, pm)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t0
+    p64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64")
+    x64 = torch.zeros_like(bs)
+    q.qcdw_invert(op, bs[0], x64[0], p64)  # warm-up
+    x64.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sep = [q.qcdw_invert(op, bs[k], x64[k], p64) for k in range(12)]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    diff = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+    # hop bandwidth of the multi-RHS kernel: a capped solve with every hop dispatch timed
+    pt = q.make_params(tol=1e-10, maxiter=16, inner="bf16", collect_timing=True, check_every=8)
+    xt = torch.zeros_like(bs)
+    ti = q.qcdw_invert_multi(op, bs, xt, pt)[0]
+    ms = ti.hop_ms[0] / max(ti.n_hop[0], 1)
+    gbs = hop_a_bytes_multi("bf16", 12) * Vh / (ms * 1e-3) / 1e9
+    op.close()
+    del bs, x, x64, xt
+    torch.cuda.empty_cache()
+    return {"workload": "24^3x64, kappa 0.125, csw 1.1, eps 0.2, 12 point sources",
+            "multi_bf16": dict(_solve_summary(multi), time_ms=round(1e3 * t_multi, 1)),
+            "separate_f64": dict(_solve_summary(sep), time_ms=round(1e3 * t_sep, 1)),
+            "speedup": round(t_sep / t_multi, 3), "rel_diff_multi_vs_f64": diff,
+            "multi_hop": {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "avg_launch_us": round(ms * 1e3, 1), "bytes_per_site_12rhs": hop_a_bytes_multi("bf16", 12)}}
+
+
+def batch_jobs(li):
+    return [(p["L"], p["eps"], p["seed"]) for p in li.batch48()]
+
+
+def batch(q, li, np, torch, ctx, fields, args):
+    """48 uneven problems: one persistent batched solve against a loop of single solves (solves/s)."""
+    specs = li.batch48()
+    ops, bs = [], []
+    for p, U in zip(specs, fields):
+        ops.append(q.Operator(ctx, q.make_lattice(p["L"]), torch.from_numpy(U).cuda(), p["kappa"], p["csw"],
+                              "bf16", 12))
+        bs.append(torch.from_numpy(li.gaussian_source(p["L"], p["source_seed"])).cuda())
+    xs = [torch.zeros_like(t) for t in bs]
+    bt = q.Batch(ctx, ops)
+    out = {"workload": "48 problems: 16 each of 8^3x16, 12^3x24, 16^3x32; kappa in [0.115, 0.124], eps 0.25"}
+    for prec in ("f64", "bf16"):
+        prm = q.make_params(tol=1e-10, maxiter=20000, inner=prec, delta=0.1)
+        q.qcdw_invert_batch(bt, bs, xs, prm)  # warm-up: autotuner and graph capture
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = q.qcdw_invert_batch(bt, bs, xs, prm)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        for x in xs:
+            x.zero_()
+        q.qcdw_invert(ops[0], bs[0], xs[0], prm)
+        xs[0].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        single = [q.qcdw_invert(op, bb, xx, prm) for op, bb, xx in zip(ops, bs, xs)]
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        out[prec] = {"batched": dict(_solve_summary(infos), time_ms=round(1e3 * t_b, 1),
+                                     solves_per_s=round(48 / t_b, 1)),
+                     "sequential": dict(_solve_summary(single), time_ms=round(1e3 * t_s, 1),
+                                        solves_per_s=round(48 / t_s, 1)),
+                     "speedup": round(t_s / t_b, 3)}
+    bt.close()
+    for op in ops:
+        op.close()
+    del bs, xs
+    torch.cuda.empty_cache()
+    return out
+
+
+LEARNED_TRAIN_SEEDS = range(1, 9)
+
+
+def learned_jobs(li):
+    w = li.WORKLOADS["wc32x64"]
+    if w["kappa"] is None:
+        return []
+    return [(w["L"], w["eps"], s) for s in [w["seed"], *LEARNED_TRAIN_SEEDS]]
+
+
+def learned(q, li, np, torch, ctx, fields, args):
+    """32^3x64 near the critical kappa: train the gauge-covariant net on 8 other fields of the ensemble
+    (32 random-error pairs each, 256 in all), then FGMRES(32)+net against plain FP64 and mixed BiCGStab
+    and FGMRES(32) without the net, all to an FP64 true residual of 1e-10 from the Gaussian source."""
+    w = li.WORKLOADS["wc32x64"]
+    if w["kappa"] is None:
+        return {"skipped": "kappa not set; run bench.py --bisect-kappa"}
+    L, kappa, csw = w["L"], w["kappa"], w["csw"]
+    lat = q.make_lattice(L)
+    out = {"workload": f"32^3x64, kappa {kappa} (bisected), csw 1.0, eps 0.15, Gaussian source"}
+    # training on fields 1..8
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net, losses, prev = None, [], None
+    for k, U in zip(LEARNED_TRAIN_SEEDS, fields[1:]):
+        op = q.Operator(ctx, lat, torch.from_numpy(U).cuda(), kappa, csw, "bf16", 12)
+        if net is None:
+            net = q.Net(op, 12, seed=5, init_scale=0.01)
+        else:
+            q.qcdw_net_bind(net, op)
+        if prev is not None:
+            prev.close()
+        prev = op
+        r, e = q.qcdw_make_training_pairs(op, None, 32, -(1000 + k))
+        h = q.qcdw_net_train(net, r, e, steps=40, batch=4, lr=2e-3, seed=k)
+        losses.append((float(np.mean(h[:4])), float(np.mean(h[-4:]))))
+        del r, e
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    op = q.Operator(ctx, lat, torch.from_numpy(fields[0]).cuda(), kappa, csw, "bf16", 12)
+    q.qcdw_net_bind(net, op)
+    prev.close()
+    torch.cuda.empty_cache()
+    b = torch.from_numpy(li.gaussian_source(L, w["source_seed"])).cuda()
+    out["training"] = {"fields": len(losses), "pairs": 32 * len(losses), "steps": 40 * len(losses),
+                       "time_s": round(t_train, 2), "loss_first_field": [round(v, 4) for v in losses[0]],
+                       "loss_last_field": [round(v, 4) for v in losses[-1]]}
+    runs = {
+        "bicgstab_f64": lambda x: q.qcdw_invert(op, b, x, q.make_params(tol=1e-10, maxiter=40000, inner="f64")),
+        "bicgstab_bf16": lambda x: q.qcdw_invert(op, b, x, q.make_params(tol=1e-10, maxiter=40000, inner="bf16")),
+        "fgmres32_net": lambda x: q.qcdw_invert_fgmres(op, net, b, x, q.make_params(tol=1e-10, maxiter=12000,
+                                                                                      inner="bf16")),
+        "fgmres32_plain": lambda x: q.qcdw_invert_fgmres(op, None, b, x, q.make_params(tol=1e-10, maxiter=12000,
+                                                                                         inner="bf16")),
+    }
+    for name, fn in runs.items():
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fn(x)
+        torch.cuda.synchronize()
+        out[name] = {"status": info.status_name, "iters": info.iters, "true_res": info.true_res,
+                     "time_ms": round(1e3 * (time.perf_counter() - t0), 1)}
+        if name.startswith("fgmres"):
+            out[name].update(fallback=info.fallback, fallback_iters=info.fallback_iters, cycles=info.n_restarts)
+        print(f"[learned] {name}: {out[name]}", file=sys.stderr, flush=True)
+    out["speedup_net_vs_f64"] = round(out["bicgstab_f64"]["time_ms"] / out["fgmres32_net"]["time_ms"], 3)
+    net.close()
+    op.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
+SECTIONS = {"propagator": (propagator_jobs, propagator), "batch": (batch_jobs, batch),
+            "learned": (learned_jobs, learned)}
+
+
+def bisect_kappa(q, li, np, torch):
+    """Smallest kappa on a 1e-5 grid in [0.120, 0.135] at which FP64 even-odd BiCGStab on the 32^3x64
+    field (eps 0.15, seed 0, Gaussian source seed 1000) does not converge to 1e-10 within 2000
+    iterations (counting divergence and breakdown as 'too far'); then the converged iteration count
+    there with maxiter 20000."""
+    w = li.WORKLOADS["wc32x64"]
+    L, csw = w["L"], w["csw"]
+    U = li.random_gauge(L, w["eps"], w["seed"])
+    b = torch.from_numpy(li.gaussian_source(L, w["source_seed"])).cuda()
+    Ud = torch.from_numpy(U).cuda()
+    del U
+    ctx = q.Context(0)
+    lat = q.make_lattice(L)
+    lo, hi = 12000, 13500  # kappa in units of 1e-5
+    trail = []
+
+    def run(kap, maxiter):
+        op = q.Operator(ctx, lat, Ud, kap * 1e-5, csw, "bf16", 12)
+        x = torch.zeros_like(b)
+        info = q.qcdw_invert(op, b, x, q.make_params(tol=1e-10, maxiter=maxiter, inner="f64"))
+        op.close()
+        trail.append((kap * 1e-5, info.status_name, info.iters))
+        print(f"[bisect] kappa {kap * 1e-5:.5f}: {info.status_name} after {info.iters}", file=sys.stderr, flush=True)
+        return info
+
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        info = run(mid, 2000)
+        if info.status == 0 and info.iters < 2000:
+            lo = mid
+        else:
+            hi = mid
+    final = run(hi, 20000)
+    ctx.close()
+    return {"kappa": hi * 1e-5, "status": final.status_name, "iters": final.iters, "true_res": final.true_res,
+            "trail": trail}
 
 
 def cpu_baseline(li, np, L, U, b, kappa, csw, seconds):

@@ -63,6 +63,29 @@ def random_gauge(L, eps: float, seed: int) -> np.ndarray:
     return _su3_exp(eps, rng, n).reshape(gauge_shape(L))
 
 
+def _gauge_job(job):
+    L, eps, seed = job
+    return random_gauge(L, eps, seed)
+
+
+def random_gauges(jobs, workers: int | None = None):
+    """random_gauge(L, eps, seed) for each (L, eps, seed) in jobs, one worker process per field.
+
+    The fields are independent streams, so the result equals the serial calls.  Workers are
+    forked: call this before the process has initialised a GPU.
+    """
+    import multiprocessing as mp
+    import os
+
+    jobs = [tuple(j) for j in jobs]
+    if workers is None:
+        workers = min(len(jobs), os.cpu_count() or 1, 16)
+    if workers <= 1 or len(jobs) <= 1:
+        return [_gauge_job(j) for j in jobs]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_gauge_job, jobs, chunksize=1)
+
+
 def unit_gauge(L) -> np.ndarray:
     check_lattice(L)
     U = np.zeros(gauge_shape(L), dtype=np.complex128)
@@ -118,8 +141,22 @@ WORKLOADS = {
     "dense4": dict(L=(4, 4, 4, 4), kappa=0.12, csw=1.0, eps=0.3, seed=0, source="point"),
     "wc16x32": dict(L=(16, 16, 16, 32), kappa=0.124, csw=1.0, eps=0.2, seed=0, source="z2", source_seed=1000),
     "wc24x64": dict(L=(24, 24, 24, 64), kappa=0.125, csw=1.1, eps=0.2, seed=0, source="point12"),
-    "wc32x64": dict(L=(32, 32, 32, 64), kappa=None, csw=1.0, eps=0.15, seed=0, source="gaussian", source_seed=1000),
+    # kappa: the smallest value on a 1e-5 grid at which FP64 even-odd BiCGStab from the Gaussian
+    # source needs at least 2000 iterations to reach 1e-10 (2729 at 0.12781, 1857 at 0.12780),
+    # found by bisection on the GPU solver (bench.py --bisect-kappa)
+    "wc32x64": dict(L=(32, 32, 32, 64), kappa=0.12781, csw=1.0, eps=0.15, seed=0, source="gaussian",
+                    source_seed=1000),
 }
+
+
+# the 48 uneven problems solved as one batch: 16 each of 8^3x16, 12^3x24, 16^3x32, kappa uniform in
+# [0.115, 0.124] (seed 4000), csw 1.0, independent eps = 0.25 fields (seeds 100..147), Gaussian sources
+# (seeds 1100..1147)
+def batch48():
+    kap = np.random.default_rng(4000).uniform(0.115, 0.124, 48)
+    Ls = [(8, 8, 8, 16)] * 16 + [(12, 12, 12, 24)] * 16 + [(16, 16, 16, 32)] * 16
+    return [dict(L=Ls[k], kappa=float(kap[k]), csw=1.0, eps=0.25, seed=100 + k, source_seed=1100 + k)
+            for k in range(48)]
 
 
 def make_source(kind: str, L, seed: int = 0, spin: int = 0, colour: int = 0) -> np.ndarray:
