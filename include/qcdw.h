@@ -84,7 +84,8 @@ typedef struct {
     int32_t max_restarts;  /* restarts allowed after a breakdown */
     int32_t collect_timing;/* 1: time every hop launch of the iteration with HIP events recorded by
                               the dispatch itself; forces eager launches (use_graph ignored) */
-    int32_t fault_inject;  /* tests only: > 0 forces a breakdown at that iteration */
+    int32_t fault_inject;  /* tests only: > 0 forces a breakdown at that iteration, < 0 flags an
+                              overflow (as a NaN would) at iteration -fault_inject */
     int32_t use_graph;     /* 1: each chunk of check_every iterations is captured once into a
                               hipGraph (cached on the operator) and replayed; 0: eager launches.
                               Both run the same kernels in the same order (bitwise equal x). */
@@ -107,8 +108,11 @@ typedef struct {
     int32_t n_hop[3];      /* launches timed, same kinds */
     int32_t hist_len;      /* in: capacity of res_hist (entries) */
     int32_t hist_count;    /* out: entries written */
-    int32_t fallback;      /* FGMRES: 1 if it stalled and BiCGStab finished the solve */
-    int32_t fallback_iters;/* FGMRES: BiCGStab iterations of the fallback (included in iters) */
+    int32_t fallback;      /* FGMRES: 1 if it stalled and BiCGStab finished the solve.
+                              BiCGStab with a low inner precision: 1 if the cycles stopped reducing the
+                              FP64 residual (3 cycles in a row without halving it, an overflow, or
+                              breakdowns beyond max_restarts) and the rest of the solve ran in FP64 */
+    int32_t fallback_iters;/* iterations after that switch (included in iters) */
     double *res_hist;      /* in: host buffer or NULL; out: relative residual after each
                               iteration (entry 0 = initial) */
 } qcdw_solve_info;

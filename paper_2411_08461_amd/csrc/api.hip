@@ -710,7 +710,7 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
     if (!(prm.tol > 0.0) || !std::isfinite(prm.tol)) return fail(ctx, QCDW_EINVAL, "tol must be positive");
     if (prm.maxiter < 0) return fail(ctx, QCDW_EINVAL, "maxiter must be >= 0");
     if (prm.check_every < 1) prm.check_every = 1;
-    const int kprec = (int)prm.inner;
+    int kprec = (int)prm.inner;  // raised to F64 if the low-precision cycles stop reducing the residual
     for (auto* op : S.ops)
         if (kprec != F64 && kprec != op->inner)
             return fail(ctx, QCDW_EINVAL, "inner precision %d not prepared by the operator (has %d)", kprec,
@@ -782,10 +782,35 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         if (!done[k]) hist_host[k].push_back(std::sqrt(rr_hi[k]) / bnorm[k]);
     int lock_iters = 0, reliable = 0, fault = prm.fault_inject;
     const int maxiter = prm.maxiter;
-    const bool mixed = kprec != F64;
+    bool mixed = kprec != F64;
     void *r = W.kr[0].p, *r0 = W.kr[1].p, *p = W.kr[2].p;
     void* xk = mixed ? W.xlo.p : W.xhi.p;
-    const int xprec = mixed ? F32 : F64;
+    int xprec = mixed ? F32 : F64;
+    // precision escalation: a healthy low-precision cycle cuts the FP64 residual by about delta; when
+    // ESCALATE_CYCLES cycles in a row fail to halve it (the rounded operator is too far from the true
+    // one, as near the critical kappa), or the inner iteration overflows, the remaining cycles run
+    // in FP64
+    constexpr int ESCALATE_CYCLES = 3;
+    std::vector<double> progress_rr(rr_hi);
+    std::vector<int> stalls(nprob, 0), iters_at_escalation(nprob, -1);
+    auto escalate = [&]() -> qcdw_status {
+        kprec = F64;
+        mixed = false;
+        xprec = F64;
+        CHK(S.ensure_workspace(F64, prm.maxiter));
+        CHK(S.tune(F64));
+        dS = (Scal*)W.scal.p;
+        dhist = (double*)W.hist.p;
+        dpart = (double*)W.partials.p;
+        dres = (double*)W.dres.p;
+        dcoef = (double*)W.coef.p;
+        r = W.kr[0].p;
+        r0 = W.kr[1].p;
+        p = W.kr[2].p;
+        xk = W.xhi.p;
+        for (int k = 0; k < nprob; k++) iters_at_escalation[k] = iters[k];
+        return QCDW_OK;
+    };
 
     while (true) {
         bool pending = false;
@@ -846,6 +871,11 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         HIPCHK(ctx, hipMemcpyAsync(dS, hs, nprob * sizeof(Scal), hipMemcpyHostToDevice, s));
         HIPCHK(ctx, launch_bicg_init(s, dS, dres, nprob));
         int all_flags = 0;
+        // stagnation of a low-precision cycle: no new minimum of the iterated residual for
+        // STAG_ITERS iterations ends the cycle (a reliable update follows)
+        constexpr int STAG_ITERS = 96;
+        std::vector<double> cyc_min(nprob, INFINITY);
+        std::vector<int> cyc_min_it(iters);
         while (true) {
             const int chunk = std::min(prm.check_every, maxiter - lock_iters);
             if (chunk <= 0) break;
@@ -864,6 +894,15 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
                     hist_host[k].insert(hist_host[k].end(), h.begin(), h.end());
                 }
                 iters[k] = hs[k].iter;
+                if (mixed && !done[k] && !hs[k].flags) {
+                    if (hs[k].rr < cyc_min[k]) {
+                        cyc_min[k] = hs[k].rr;
+                        cyc_min_it[k] = iters[k];
+                    } else if (iters[k] - cyc_min_it[k] >= STAG_ITERS) {
+                        hs[k].flags = FLAG_STOP;
+                        HIPCHK(ctx, hipMemcpyAsync(&dS[k].flags, &hs[k].flags, sizeof(int), hipMemcpyHostToDevice, s));
+                    }
+                }
                 if (!hs[k].flags) all_set = false;
             }
             if (S.tm.on) S.tm.collect((size_t)4 * advanced);
@@ -874,20 +913,51 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
             all_flags |= hs[k].flags;
             if (!done[k]) iter_res[k] = std::sqrt(hs[k].rr) / (scale[k] * bnorm[k]);
         }
-        if (mixed) HIPCHK(ctx, launch_axpy_hi(s, F32, 0.0, dcoef + nprob, W.xlo.p, W.xhi.p, n0, nprob, S.map, S.nmax));
+        bool raise = false;
+        if (mixed) {
+            // a low-precision cycle that overflowed contributes no correction; the problem escalates
+            bool dropped = false;
+            for (int k = 0; k < nprob; k++)
+                if (!done[k] && (hs[k].flags & FLAG_NAN)) {
+                    hc[nprob + k] = 0.0;
+                    dropped = raise = true;
+                }
+            if (dropped)
+                HIPCHK(ctx, hipMemcpyAsync(dcoef + nprob, hc + nprob, nprob * sizeof(double), hipMemcpyHostToDevice,
+                                           s));
+            HIPCHK(ctx, launch_axpy_hi(s, F32, 0.0, dcoef + nprob, W.xlo.p, W.xhi.p, n0, nprob, S.map, S.nmax));
+        }
         for (int k = 0; k < nprob; k++) {
             if (done[k]) continue;
             if (hs[k].flags & FLAG_NAN) {
+                if (mixed) continue;
                 status[k] = QCDW_ENAN;
                 done[k] = 1;
             } else if ((hs[k].flags & FLAG_BREAK) && ++restarts[k] > prm.max_restarts) {
+                if (mixed) {
+                    restarts[k] = 0;
+                    raise = true;
+                    continue;
+                }
                 status[k] = QCDW_EBREAKDOWN;
                 done[k] = 2;
             }
         }
-        if (all_flags & FLAG_BREAK) fault = 0;
+        if (all_flags & (FLAG_BREAK | FLAG_NAN)) fault = 0;
         CHK(S.true_schur_residual(rr_hi));
         reliable++;
+        if (mixed) {
+            for (int k = 0; k < nprob; k++) {
+                if (done[k]) continue;
+                if (rr_hi[k] < 0.25 * progress_rr[k]) {
+                    progress_rr[k] = rr_hi[k];
+                    stalls[k] = 0;
+                } else if (++stalls[k] >= ESCALATE_CYCLES) {
+                    raise = true;
+                }
+            }
+            if (raise) CHK(escalate());
+        }
     }
 
     // ---- unfinished problems: best iterate and its true residual ----------
@@ -913,6 +983,8 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         inf->true_res = true_res[k];
         inf->iter_res = iter_res[k];
         inf->time_ms = wall;
+        inf->fallback = iters_at_escalation[k] >= 0;
+        inf->fallback_iters = iters_at_escalation[k] >= 0 ? iters[k] - iters_at_escalation[k] : 0;
         for (int j = 0; j < 3; j++) {
             inf->hop_ms[j] = S.tm.ms[j];
             inf->n_hop[j] = (int32_t)S.tm.launches[j];

@@ -324,7 +324,8 @@ __global__ __launch_bounds__(256) void k_fin_beta(Scal* S, const double* partial
         S->rr = rr;
         if (hist && it < S->hist_len) hist[it] = sqrt(rr) * S->hist_norm;
         const cx<double> omega = ld2(S->omega);
-        if (!isfinite(rr) || !isfinite(rho_new.re) || !isfinite(rho_new.im)) {
+        if (!isfinite(rr) || !isfinite(rho_new.re) || !isfinite(rho_new.im) ||
+            (S->fault_iter < 0 && it == -S->fault_iter)) {
             S->flags = FLAG_NAN;
         } else if (rr <= S->stop_rr) {
             S->flags = FLAG_CONV;

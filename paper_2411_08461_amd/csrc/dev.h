@@ -73,6 +73,17 @@ struct P64 {
         reinterpret_cast<double2*>(base)[k] = make_double2(z.re, z.im);
     }
     __device__ static cx<double> rt(cx<double> z) { return z; }
+    // streaming (non-temporal) loads: data read once per launch, kept out of the way of reused lines
+    __device__ static cx<double> ldn(const void* base, long k)
+    {
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(base) + k);
+        return {v.x, v.y};
+    }
+    __device__ static double ldrn(const void* base, long k)
+    {
+        return __builtin_nontemporal_load(reinterpret_cast<const double*>(base) + k);
+    }
     __device__ static double ldr(const void* base, long k) { return reinterpret_cast<const double*>(base)[k]; }
     __device__ static void str(void* base, long k, double v) { reinterpret_cast<double*>(base)[k] = v; }
 };
@@ -90,6 +101,16 @@ struct P32 {
         reinterpret_cast<float2*>(base)[k] = make_float2(z.re, z.im);
     }
     __device__ static cx<float> rt(cx<float> z) { return z; }
+    __device__ static cx<float> ldn(const void* base, long k)
+    {
+        typedef float v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(base) + k);
+        return {v.x, v.y};
+    }
+    __device__ static float ldrn(const void* base, long k)
+    {
+        return __builtin_nontemporal_load(reinterpret_cast<const float*>(base) + k);
+    }
     __device__ static float ldr(const void* base, long k) { return reinterpret_cast<const float*>(base)[k]; }
     __device__ static void str(void* base, long k, float v) { reinterpret_cast<float*>(base)[k] = v; }
 };
@@ -107,9 +128,18 @@ struct PBF16 {
         reinterpret_cast<uint32_t*>(base)[k] = f2bf_bits(z.re) | (f2bf_bits(z.im) << 16);
     }
     __device__ static cx<float> rt(cx<float> z) { return {bf_bits2f(f2bf_bits(z.re)), bf_bits2f(f2bf_bits(z.im))}; }
+    __device__ static cx<float> ldn(const void* base, long k)
+    {
+        const uint32_t v = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + k);
+        return {bf_bits2f(v & 0xffffu), bf_bits2f(v >> 16)};
+    }
     __device__ static float ldr(const void* base, long k)
     {
         return bf_bits2f(reinterpret_cast<const uint16_t*>(base)[k]);
+    }
+    __device__ static float ldrn(const void* base, long k)
+    {
+        return bf_bits2f(__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(base) + k));
     }
     __device__ static void str(void* base, long k, float v)
     {
@@ -132,7 +162,17 @@ struct PF16 {
         p[1] = (_Float16)z.im;
     }
     __device__ static cx<float> rt(cx<float> z) { return {(float)(_Float16)z.re, (float)(_Float16)z.im}; }
+    __device__ static cx<float> ldn(const void* base, long k)
+    {
+        typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(base) + k);
+        return {(float)v.x, (float)v.y};
+    }
     __device__ static float ldr(const void* base, long k) { return (float)reinterpret_cast<const _Float16*>(base)[k]; }
+    __device__ static float ldrn(const void* base, long k)
+    {
+        return (float)__builtin_nontemporal_load(reinterpret_cast<const _Float16*>(base) + k);
+    }
     __device__ static void str(void* base, long k, float v) { reinterpret_cast<_Float16*>(base)[k] = (_Float16)v; }
 };
 

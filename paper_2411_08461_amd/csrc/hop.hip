@@ -21,6 +21,11 @@
 #ifndef QCDW_HOP_PREFETCH
 #define QCDW_HOP_PREFETCH 0
 #endif
+// 1: links and clover entries (read once per launch) are loaded non-temporally, so the
+// neighbour spinors, which are re-read by the tiles of adjacent t-slices, stay in L2
+#ifndef QCDW_HOP_NT
+#define QCDW_HOP_NT 0
+#endif
 #ifndef QCDW_HOP_WAVES_PER_EU
 #define QCDW_HOP_WAVES_PER_EU 0
 #endif
@@ -37,10 +42,10 @@ __device__ __forceinline__ void load_link(const void* gauge, long off, cx<typena
 {
     if constexpr (R == 9) {
 #pragma unroll
-        for (int e = 0; e < 9; e++) u[e] = P::ld(gauge, off + e);
+        for (int e = 0; e < 9; e++) u[e] = QCDW_HOP_NT ? P::ldn(gauge, off + e) : P::ld(gauge, off + e);
     } else {
 #pragma unroll
-        for (int e = 0; e < 6; e++) u[e] = P::ld(gauge, off + e);
+        for (int e = 0; e < 6; e++) u[e] = QCDW_HOP_NT ? P::ldn(gauge, off + e) : P::ld(gauge, off + e);
         // third row of an SU(3) matrix: complex conjugate of row0 x row1
         u[6] = conj(u[1] * u[5] - u[2] * u[4]);
         u[7] = conj(u[2] * u[3] - u[0] * u[5]);
@@ -98,7 +103,7 @@ __device__ __forceinline__ void load_window(const void* clov, int site, int q, t
 {
     const long base = ((long)site * 2 + (q >> 1)) * 36 + 9 * (q & 1);
 #pragma unroll
-    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + e);
+    for (int e = 0; e < 27; e++) win[e] = QCDW_HOP_NT ? P::ldrn(clov, base + e) : P::ldr(clov, base + e);
 }
 
 template <typename T>

@@ -95,10 +95,10 @@ struct Scal {
     double hist_norm; // history entry = sqrt(rr) * hist_norm
     int iter;         // iterations completed
     int flags;        // FLAG_* below
-    int fault_iter;   // > 0: force a breakdown when iter reaches this value
+    int fault_iter;   // > 0: force a breakdown when iter reaches this value; < 0: flag an overflow at -value
     int hist_len;     // capacity of the device history
 };
-enum { FLAG_CONV = 1, FLAG_BREAK = 2, FLAG_NAN = 4 };
+enum { FLAG_CONV = 1, FLAG_BREAK = 2, FLAG_NAN = 4, FLAG_STOP = 8 /* cycle ended by the host */ };
 
 constexpr int BLAS_THREADS = 256;
 // number of blocks used by the BLAS reductions on n complex elements

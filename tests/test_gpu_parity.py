@@ -504,3 +504,40 @@ def test_invert_batch_many_small_problems(ctx):
     batch.close()
     for op in ops:
         op.close()
+
+
+def test_mixed_solve_escalates_to_f64_after_an_overflow(ctx):
+    """An overflow flagged in the low-precision cycle (forced at iteration 5) drops that cycle's
+    correction and finishes in FP64; an FP64 solve reports it as ENAN."""
+    L = (8, 8, 8, 16)
+    U = _gauge(L, 0.25, 15)
+    kappa, csw = 0.122, 1.0
+    b = li.gaussian_source(L, 16)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, "bf16")
+    x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(inner="bf16", fault_inject=-5))
+    assert info.status == q.QCDW_OK and info.fallback == 1 and 0 < info.fallback_iters < info.iters
+    assert _oracle_true_res(L, U, host(x), b, kappa, csw) <= 1e-10
+    x.zero_()
+    plain = q.qcdw_invert(op, dev(b), x, q.make_params(inner="bf16"))
+    assert plain.status == q.QCDW_OK and plain.fallback == 0
+    x.zero_()
+    info64 = q.qcdw_invert(op, dev(b), x, q.make_params(fault_inject=-5))
+    assert info64.status == q.QCDW_ENAN
+    op.close()
+
+
+def test_mixed_solve_escalates_near_the_critical_kappa(ctx):
+    """Near kappa_c the BF16-rounded operator is too far from the FP64 one for the low-precision
+    cycles to converge: the solver detects the stall and finishes in FP64 to the same tolerance."""
+    L = (8, 8, 8, 16)
+    U = li.random_gauge(L, 0.15, 0)
+    kappa, csw = 0.1278, 1.0
+    b = li.gaussian_source(L, 1000)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, "bf16")
+    x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+    info = q.qcdw_invert(op, dev(b), x, q.make_params(inner="bf16", maxiter=6000))
+    print(info, info.fallback, info.fallback_iters)
+    assert info.status == q.QCDW_OK and info.fallback == 1
+    assert _oracle_true_res(L, U, host(x), b, kappa, csw) <= 1e-10
+    op.close()
