@@ -2,6 +2,8 @@
 // workspaces, and the host side of the even-odd preconditioned BiCGStab solver
 // whose iterations run entirely on the device (scalars never leave the GPU
 // except for the periodic convergence poll).
+#include <algorithm>
+
 #include "host.h"
 
 extern "C" {
@@ -163,7 +165,7 @@ qcdw_status qcdw_dslash(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, c
     HIPCHK(ctx, gauge.alloc(8UL * g.Vh * 9 * 16));
     HIPCHK(ctx, Apaper.alloc(144UL * g.Vh * 8));
     for (int p = 0; p < 2; p++) {
-        HIPCHK(ctx, A[p].alloc(72UL * g.Vh * 8));
+        HIPCHK(ctx, A[p].alloc(clov_reals(g.Vh) * 8));
         HIPCHK(ctx, in[p].alloc(vb));
     }
     HIPCHK(ctx, res.alloc(vb));
@@ -190,6 +192,90 @@ qcdw_status qcdw_dslash(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, c
         HIPCHK(ctx, launch_unpack_spinor(s, F64, g, res.p, p, out, 1.0));
     }
     HIPCHK(ctx, hipStreamSynchronize(s));
+    return QCDW_OK;
+}
+
+// Form of the operator's single-RHS hop in precision prec: sites per thread along t (nt) and
+// c-tiles per group swept along t (cg).  The cached choice for this lattice (code nt + 16 cg),
+// else the fastest candidate timed on scratch vectors.
+static qcdw_status tune_op_hop(qcdw_op* op, int prec)
+{
+    qcdw_ctx* ctx = op->ctx;
+    const Geom& g = op->g;
+    char key[96];
+    snprintf(key, sizeof key, "hop_nt/p%d/L%dx%dx%dx%d", prec, g.Lx, g.Ly, g.Lz, g.Lt);
+    const int nct = hop_ctiles(g);
+    auto divisor_upto = [&](int m) {  // largest divisor of nct in [4, m], below nct; 0 if none
+        for (int d = std::min(m, nct - 1); d >= 4; d--)
+            if (nct % d == 0) return d;
+        return 0;
+    };
+    std::vector<int> cand;  // codes nt + 16 cg
+    auto add = [&](int nt, int cg) {
+        const int code = nt + 16 * cg;
+        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && std::find(cand.begin(), cand.end(), code) == cand.end())
+            cand.push_back(code);
+    };
+    add(1, 0);
+    for (int m : {8, 16, 32})
+        if (int d = divisor_upto(m)) add(1, d);
+    for (int nt : {2, 4}) {
+        add(nt, 0);
+        if (int d = divisor_upto(16)) add(nt, d);
+    }
+    auto apply = [&](int code) {
+        op->hop_nt[prec] = code % 16;
+        op->hop_cg[prec] = code / 16;
+    };
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) {
+        const int nt = it->second % 16, cg = it->second / 16;
+        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg)) {
+            apply(it->second);
+            return QCDW_OK;
+        }
+    }
+    apply(1);
+    if (cand.size() == 1) return QCDW_OK;
+    const PrecView v = view(op, prec);
+    const size_t vb = 12UL * g.Vh * cplx_bytes(prec);
+    DevBuf in, out;
+    HIPCHK(ctx, in.alloc(vb));
+    HIPCHK(ctx, out.alloc(vb));
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, hipMemsetAsync(in.p, 0, vb, s));
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_c = 1;
+    hipError_t e = hipSuccess;
+    for (int code : cand) {
+        HopArgs a = hop_args(g, 1);
+        a.nt = code % 16;
+        a.cgroup = code / 16;
+        a.psi = in.p;
+        a.out = out.p;
+        a.gauge = v.gauge;
+        a.clov = v.Ainv[1];
+        for (int rep = 0; rep < 2 && e == hipSuccess; rep++) e = launch_hop(s, prec, v.recon, EPI_CLOV, RED_NONE, a);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int rep = 0; rep < 5 && e == hipSuccess; rep++) e = launch_hop(s, prec, v.recon, EPI_CLOV, RED_NONE, a);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (ms < best) {
+            best = ms;
+            best_c = code;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(ctx, QCDW_EHIP, "hop tuning failed: %s", hipGetErrorString(e));
+    apply(best_c);
+    ctx->tune_store(key, best_c);
     return QCDW_OK;
 }
 
@@ -225,7 +311,7 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
         inv.alloc(144UL * g.Vh * 8) != hipSuccess || Ap.alloc(144UL * g.Vh * 8) != hipSuccess)
         return cleanup(fail(ctx, QCDW_ENOMEM, "out of device memory creating the operator"));
     for (int p = 0; p < 2; p++)
-        if (op->Ainv64[p].alloc(72UL * g.Vh * 8) != hipSuccess || op->A64[p].alloc(72UL * g.Vh * 8) != hipSuccess)
+        if (op->Ainv64[p].alloc(clov_reals(g.Vh) * 8) != hipSuccess || op->A64[p].alloc(clov_reals(g.Vh) * 8) != hipSuccess)
             return cleanup(fail(ctx, QCDW_ENOMEM, "out of device memory creating the operator"));
     hipError_t e = launch_pack_gauge(s, F64, recon, g, U, op->gauge64.p);
     if (e == hipSuccess) e = launch_clover_build(s, g, U, clov.p);
@@ -243,7 +329,7 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
             return cleanup(fail(ctx, QCDW_ENOMEM, "out of device memory creating the operator"));
         e = launch_pack_gauge(s, inner, lrecon, g, U, op->gauge_lo.p);
         for (int p = 0; p < 2 && e == hipSuccess; p++) {
-            if (op->Ainv_lo[p].alloc(72UL * g.Vh * real_bytes(inner)) != hipSuccess)
+            if (op->Ainv_lo[p].alloc(clov_reals(g.Vh) * real_bytes(inner)) != hipSuccess)
                 return cleanup(fail(ctx, QCDW_ENOMEM, "out of device memory creating the operator"));
             e = launch_pack_clover(s, inner, g, inv.p, p, op->Ainv_lo[p].p);
         }
@@ -254,6 +340,10 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
     int bad;
     memcpy(&bad, ctx->host_d, sizeof(int));
     if (bad) return cleanup(fail(ctx, QCDW_ENOTPD, "%d clover blocks are not positive definite", bad));
+    for (int prec : {(int)F64, (int)inner}) {
+        const qcdw_status st = tune_op_hop(op, prec);
+        if (st != QCDW_OK) return cleanup(st);
+    }
     *op_out = op;
     return QCDW_OK;
 }
@@ -401,7 +491,9 @@ struct Solver {
     int nb_blas;                 // BLAS partials per problem
     const long2* map;            // device (off, len) per problem (batch) or nullptr (uniform)
     const int* nbs;              // device hop tiles per problem (batch) or nullptr
-    int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse) or batch grid
+    int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse), batch grid, or
+                                 // single-RHS sites per thread along t
+    int nt = 1, cg = 0;          // single-RHS hop: sites per thread along t, c-tile group
     Timing tm;
 
     Solver(qcdw_ctx* c, Workspace& w, std::vector<qcdw_op*> o, qcdw_batch* b)
@@ -470,6 +562,8 @@ struct Solver {
         a.partials = partials;
         a.stop = S ? &S->flags : nullptr;
         a.nrhs = nprob;
+        a.nt = nprob == 1 ? nt : 1;
+        a.cgroup = nprob == 1 ? cg : 0;
         if (nprob > 1)
             return variant == 1 ? launch_hop_rhs(st, prec, epi, red, a, S, e0, e1)
                                 : launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
@@ -507,9 +601,15 @@ struct Solver {
     // (result cached on the context, keyed by problem shape)
     qcdw_status tune(int kprec)
     {
-        if (nprob == 1) return QCDW_OK;
         std::vector<int> cand;
         char key[160];
+        if (nprob == 1) {  // the operator's own choice (tuned when it was created)
+            nt = ops[0]->hop_nt[kprec];
+            cg = ops[0]->hop_cg[kprec];
+            variant = nt + 16 * cg;
+            nb_hop = hop_blocks_nt(ops[0]->g, nt, cg);
+            return QCDW_OK;
+        }
         if (batch) {
             snprintf(key, sizeof key, "batch_hop/p%d/tiles%d/n%d", kprec, batch->total_tiles, nprob);
             for (int gsz : {256, 512, 1024, 2048, 4096})
@@ -519,9 +619,10 @@ struct Solver {
             snprintf(key, sizeof key, "mrhs_hop/p%d/Vh%d/n%d", kprec, ops[0]->g.Vh, nprob);
             cand = {0, 1};
         }
+        auto choose = [&](int v) { variant = v; };
         auto it = ctx->tune.find(key);
-        if (it != ctx->tune.end()) {
-            variant = it->second;
+        if (it != ctx->tune.end() && std::find(cand.begin(), cand.end(), it->second) != cand.end()) {
+            choose(it->second);
             return QCDW_OK;
         }
         hipEvent_t e0, e1;
@@ -532,7 +633,7 @@ struct Solver {
         const bool was_on = tm.on;
         tm.on = false;
         for (int c : cand) {
-            variant = c;
+            choose(c);
             // hop into odd sites from the (scratch) Krylov vectors; no solver state is touched
             hipError_t e = hop(s, kprec, EPI_CLOV, RED_NONE, W.kr[2].p, W.kr[6].p, nullptr, nullptr, nullptr,
                                nullptr, 1);
@@ -556,7 +657,7 @@ struct Solver {
         tm.on = was_on;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        variant = best_v;
+        choose(best_v);
         ctx->tune_store(key, best_v);
         return QCDW_OK;
     }

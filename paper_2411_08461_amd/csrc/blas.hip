@@ -108,9 +108,9 @@ __global__ __launch_bounds__(256) void k_clov_apply(const void* clov, const void
     const int site = (int)(gid >> 2), q = (int)(gid & 3);  // q = spin
     const int h = q & 1, partner = q ^ 1;
     T win[27];
-    const long base = ((long)site * 2 + (q >> 1)) * 36 + 9 * h;
+    const long base = clov_index(site, q >> 1, 9 * h);
 #pragma unroll
-    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + e);
+    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + (long)e * CLOV_STRIDE);
     cx<T> vo[3], vx[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {

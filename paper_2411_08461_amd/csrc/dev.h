@@ -6,7 +6,9 @@
 //   spinor  [4 spin][Vh site][3 colour] complex        (spin-major, colour inner)
 //   gauge   [4 mu][2 parity][Vh site][R] complex, R = 6 (rows 0,1: reconstruct-12)
 //           or 9 (full link), row-major colour order
-//   clover  [Vh site][2 chirality][36] reals in the reordered packing below
+//   clover  [Vh site][2 chirality][36 entry] reals, entries in the reordered packing of
+//           hop.hip, so a lane's 27-entry window is contiguous (wide per-lane loads; layouts
+//           with sites fastest were measured slower on gfx950)
 // Each lane of a hop kernel reads one spin (3 contiguous complex) of a
 // neighbour, so consecutive sites give contiguous, fully coalesced accesses.
 #pragma once
@@ -73,17 +75,6 @@ struct P64 {
         reinterpret_cast<double2*>(base)[k] = make_double2(z.re, z.im);
     }
     __device__ static cx<double> rt(cx<double> z) { return z; }
-    // streaming (non-temporal) loads: data read once per launch, kept out of the way of reused lines
-    __device__ static cx<double> ldn(const void* base, long k)
-    {
-        typedef double v2 __attribute__((ext_vector_type(2)));
-        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(base) + k);
-        return {v.x, v.y};
-    }
-    __device__ static double ldrn(const void* base, long k)
-    {
-        return __builtin_nontemporal_load(reinterpret_cast<const double*>(base) + k);
-    }
     __device__ static double ldr(const void* base, long k) { return reinterpret_cast<const double*>(base)[k]; }
     __device__ static void str(void* base, long k, double v) { reinterpret_cast<double*>(base)[k] = v; }
 };
@@ -101,16 +92,6 @@ struct P32 {
         reinterpret_cast<float2*>(base)[k] = make_float2(z.re, z.im);
     }
     __device__ static cx<float> rt(cx<float> z) { return z; }
-    __device__ static cx<float> ldn(const void* base, long k)
-    {
-        typedef float v2 __attribute__((ext_vector_type(2)));
-        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(base) + k);
-        return {v.x, v.y};
-    }
-    __device__ static float ldrn(const void* base, long k)
-    {
-        return __builtin_nontemporal_load(reinterpret_cast<const float*>(base) + k);
-    }
     __device__ static float ldr(const void* base, long k) { return reinterpret_cast<const float*>(base)[k]; }
     __device__ static void str(void* base, long k, float v) { reinterpret_cast<float*>(base)[k] = v; }
 };
@@ -128,18 +109,9 @@ struct PBF16 {
         reinterpret_cast<uint32_t*>(base)[k] = f2bf_bits(z.re) | (f2bf_bits(z.im) << 16);
     }
     __device__ static cx<float> rt(cx<float> z) { return {bf_bits2f(f2bf_bits(z.re)), bf_bits2f(f2bf_bits(z.im))}; }
-    __device__ static cx<float> ldn(const void* base, long k)
-    {
-        const uint32_t v = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + k);
-        return {bf_bits2f(v & 0xffffu), bf_bits2f(v >> 16)};
-    }
     __device__ static float ldr(const void* base, long k)
     {
         return bf_bits2f(reinterpret_cast<const uint16_t*>(base)[k]);
-    }
-    __device__ static float ldrn(const void* base, long k)
-    {
-        return bf_bits2f(__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(base) + k));
     }
     __device__ static void str(void* base, long k, float v)
     {
@@ -162,17 +134,7 @@ struct PF16 {
         p[1] = (_Float16)z.im;
     }
     __device__ static cx<float> rt(cx<float> z) { return {(float)(_Float16)z.re, (float)(_Float16)z.im}; }
-    __device__ static cx<float> ldn(const void* base, long k)
-    {
-        typedef _Float16 v2 __attribute__((ext_vector_type(2)));
-        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(base) + k);
-        return {(float)v.x, (float)v.y};
-    }
     __device__ static float ldr(const void* base, long k) { return (float)reinterpret_cast<const _Float16*>(base)[k]; }
-    __device__ static float ldrn(const void* base, long k)
-    {
-        return (float)__builtin_nontemporal_load(reinterpret_cast<const _Float16*>(base) + k);
-    }
     __device__ static void str(void* base, long k, float v) { reinterpret_cast<_Float16*>(base)[k] = (_Float16)v; }
 };
 
@@ -185,6 +147,12 @@ struct Geom {
     int Vh;    // sites per parity
     int t_bc;  // +1 / -1
 };
+
+// real index of entry m (reordered packing) of chirality block chi at `site` in an internal
+// clover-type array of one parity, and the array's length in reals
+constexpr int CLOV_STRIDE = 1;  // distance between consecutive entries of one matrix
+__host__ __device__ inline long clov_index(int site, int chi, int m) { return ((long)site * 2 + chi) * 36 + m; }
+__host__ __device__ inline long clov_reals(long Vh) { return 72L * Vh; }
 
 // coordinates of checkerboard index i on parity p
 __device__ __forceinline__ void site_coords(const Geom& g, int i, int p, int& x, int& y, int& z, int& t)

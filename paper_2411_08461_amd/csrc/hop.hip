@@ -18,14 +18,6 @@
 
 #include "internal.h"
 
-#ifndef QCDW_HOP_PREFETCH
-#define QCDW_HOP_PREFETCH 0
-#endif
-// 1: links and clover entries (read once per launch) are loaded non-temporally, so the
-// neighbour spinors, which are re-read by the tiles of adjacent t-slices, stay in L2
-#ifndef QCDW_HOP_NT
-#define QCDW_HOP_NT 0
-#endif
 #ifndef QCDW_HOP_WAVES_PER_EU
 #define QCDW_HOP_WAVES_PER_EU 0
 #endif
@@ -33,6 +25,19 @@
 #define QCDW_HOP_ATTR __attribute__((amdgpu_waves_per_eu(QCDW_HOP_WAVES_PER_EU, QCDW_HOP_WAVES_PER_EU)))
 #else
 #define QCDW_HOP_ATTR
+#endif
+// t-stepping hop: minimum waves per SIMD the compiler must allow (0: its own choice) and
+// whether the steps are unrolled
+#ifndef QCDW_TKERNEL_WAVES
+#define QCDW_TKERNEL_WAVES 0
+#endif
+#if QCDW_TKERNEL_WAVES > 0
+#define QCDW_TKERNEL_ATTR __attribute__((amdgpu_waves_per_eu(QCDW_TKERNEL_WAVES)))
+#else
+#define QCDW_TKERNEL_ATTR
+#endif
+#ifndef QCDW_TKERNEL_UNROLL
+#define QCDW_TKERNEL_UNROLL 1
 #endif
 
 namespace qcdw {
@@ -42,10 +47,10 @@ __device__ __forceinline__ void load_link(const void* gauge, long off, cx<typena
 {
     if constexpr (R == 9) {
 #pragma unroll
-        for (int e = 0; e < 9; e++) u[e] = QCDW_HOP_NT ? P::ldn(gauge, off + e) : P::ld(gauge, off + e);
+        for (int e = 0; e < 9; e++) u[e] = P::ld(gauge, off + e);
     } else {
 #pragma unroll
-        for (int e = 0; e < 6; e++) u[e] = QCDW_HOP_NT ? P::ldn(gauge, off + e) : P::ld(gauge, off + e);
+        for (int e = 0; e < 6; e++) u[e] = P::ld(gauge, off + e);
         // third row of an SU(3) matrix: complex conjugate of row0 x row1
         u[6] = conj(u[1] * u[5] - u[2] * u[4]);
         u[7] = conj(u[2] * u[3] - u[0] * u[5]);
@@ -98,12 +103,13 @@ __device__ __forceinline__ void herm_rows(const T (&win)[27], int h, const cx<T>
     }
 }
 
+// lane q's 27-entry window: chirality q >> 1, entries 9 (q & 1) .. 9 (q & 1) + 26
 template <class P>
-__device__ __forceinline__ void load_window(const void* clov, int site, int q, typename P::real (&win)[27])
+__device__ __forceinline__ void load_window(const void* clov, long Vh, int site, int q, typename P::real (&win)[27])
 {
-    const long base = ((long)site * 2 + (q >> 1)) * 36 + 9 * (q & 1);
+    const long base = clov_index(site, q >> 1, 9 * (q & 1));
 #pragma unroll
-    for (int e = 0; e < 27; e++) win[e] = QCDW_HOP_NT ? P::ldrn(clov, base + e) : P::ldr(clov, base + e);
+    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + (long)e * CLOV_STRIDE);
 }
 
 template <typename T>
@@ -117,144 +123,134 @@ __device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
     return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
 }
 
-// One 64-site tile of the hop with its epilogue; `part` receives the tile's
-// reduction partials (RED != RED_NONE).  All 256 threads of the block call it.
-template <class P, int R, int EPI, int RED>
-__device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* part)
+// The four hops of one lane at one site: neighbour indices (input parity), link
+// offsets, projection coefficients and time-boundary signs.  Hop h = 2 j + dir,
+// mu = 2 gq + j, dir 0 forward / 1 backward.
+template <typename T, int R>
+struct LaneHops {
+    int nbh[4];
+    long loff[4];
+    T cre[4], cim[4], fsg[4];
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q, LaneHops<T, R>& L)
+{
+    const int gq = q >> 1, k = q & 1;
+    const long Vh = g.Vh;
+    int x, y, z, t;
+    site_coords(g, site, p, x, y, z, t);
+    const int xh = site % g.Lxh;
+    const int Sy = g.Lxh, Sz = g.Lxh * g.Ly, St = g.Lxh * g.Ly * g.Lz;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const int mu = 2 * gq + j;
+        int fwd, bwd;
+        bool fcross = false, bcross = false;
+        T c_re, c_im;  // projection coefficient of the forward hop
+        if (j == 0) {
+            if (gq == 0) {  // x: the neighbour lies in the same row of the other parity
+                const int row = site - xh;
+                const int xp = (x + 1 == g.Lx) ? 0 : x + 1;
+                const int xm = (x == 0) ? g.Lx - 1 : x - 1;
+                fwd = row + (xp >> 1);
+                bwd = row + (xm >> 1);
+                c_re = T(0);
+                c_im = T(-1);
+            } else {  // z
+                fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
+                bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
+                c_re = T(0);
+                c_im = k == 0 ? T(-1) : T(1);
+            }
+        } else {
+            if (gq == 0) {  // y
+                fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
+                bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
+                c_re = k == 0 ? T(1) : T(-1);
+                c_im = T(0);
+            } else {  // t
+                fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
+                bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
+                fcross = (t + 1 == g.Lt);
+                bcross = (t == 0);
+                c_re = T(-1);
+                c_im = T(0);
+            }
+        }
+        // forward: U_mu(x) psi(x+mu) with (1 - g_mu); backward: U_mu(x-mu)^+ psi(x-mu)
+        // with (1 + g_mu), which flips the projection coefficient
+        L.nbh[2 * j] = fwd;
+        L.nbh[2 * j + 1] = bwd;
+        L.loff[2 * j] = ((long)(mu * 2 + p) * Vh + site) * R;
+        L.loff[2 * j + 1] = ((long)(mu * 2 + (1 - p)) * Vh + bwd) * R;
+        L.cre[2 * j] = c_re;
+        L.cim[2 * j] = c_im;
+        L.cre[2 * j + 1] = -c_re;
+        L.cim[2 * j + 1] = -c_im;
+        L.fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
+        L.fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
+    }
+}
+
+// the two spins (su, sl) of neighbour nb that this lane's row of the projection needs
+template <class P>
+__device__ __forceinline__ void load_pair(const void* psi, long Vh, int su, int sl, int nb,
+                                          cx<typename P::real> (&pu)[3], cx<typename P::real> (&pl)[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        pu[c] = P::ld(psi, ((long)su * Vh + nb) * 3 + c);
+        pl[c] = P::ld(psi, ((long)sl * Vh + nb) * 3 + c);
+    }
+}
+
+// W h for hop h with the projected row hv, accumulated into the two output spins
+template <class P, int R>
+__device__ __forceinline__ void hop_apply(const void* gauge, const LaneHops<typename P::real, R>& L, int h,
+                                          const cx<typename P::real> (&hv)[3], cx<typename P::real> (&acc_u)[3],
+                                          cx<typename P::real> (&acc_l)[3])
 {
     using T = typename P::real;
-    const Geom g = a.g;
-    const int q = threadIdx.x & 3;
-    const int site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
-    const bool valid = site < g.Vh;
-    const int gq = q >> 1, k = q & 1;
-    const int p = a.parity;
-    const long Vh = g.Vh;
-
-    cx<T> acc_u[3], acc_l[3];
+    const int dir = h & 1;
+    cx<T> u[9];
+    load_link<P, R>(gauge, L.loff[h], u);
+    cx<T> w[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) acc_u[c] = acc_l[c] = {T(0), T(0)};
-
-    if (valid) {
-        int x, y, z, t;
-        site_coords(g, site, p, x, y, z, t);
-        const int xh = site % g.Lxh;
-        const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
-        const int Sy = g.Lxh, Sz = g.Lxh * g.Ly, St = g.Lxh * g.Ly * g.Lz;
-        // the four hops of this lane: h = 2 j + dir, mu = 2 gq + j, dir 0 forward / 1 backward
-        int nbh[4];
-        long loff[4];
-        T cre[4], cim[4], fsg[4];
+    for (int r = 0; r < 3; r++) {
+        cx<T> sacc = {T(0), T(0)};
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int mu = 2 * gq + j;
-            int fwd, bwd;
-            bool fcross = false, bcross = false;
-            T c_re, c_im;  // projection coefficient of the forward hop
-            if (j == 0) {
-                if (gq == 0) {  // x: the neighbour lies in the same row of the other parity
-                    const int row = site - xh;
-                    const int xp = (x + 1 == g.Lx) ? 0 : x + 1;
-                    const int xm = (x == 0) ? g.Lx - 1 : x - 1;
-                    fwd = row + (xp >> 1);
-                    bwd = row + (xm >> 1);
-                    c_re = T(0);
-                    c_im = T(-1);
-                } else {  // z
-                    fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
-                    bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
-                    c_re = T(0);
-                    c_im = k == 0 ? T(-1) : T(1);
-                }
-            } else {
-                if (gq == 0) {  // y
-                    fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
-                    bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
-                    c_re = k == 0 ? T(1) : T(-1);
-                    c_im = T(0);
-                } else {  // t
-                    fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
-                    bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
-                    fcross = (t + 1 == g.Lt);
-                    bcross = (t == 0);
-                    c_re = T(-1);
-                    c_im = T(0);
-                }
-            }
-            // forward: U_mu(x) psi(x+mu) with (1 - g_mu); backward: U_mu(x-mu)^+ psi(x-mu)
-            // with (1 + g_mu), which flips the projection coefficient
-            nbh[2 * j] = fwd;
-            nbh[2 * j + 1] = bwd;
-            loff[2 * j] = ((long)(mu * 2 + p) * Vh + site) * R;
-            loff[2 * j + 1] = ((long)(mu * 2 + (1 - p)) * Vh + bwd) * R;
-            cre[2 * j] = c_re;
-            cim[2 * j] = c_im;
-            cre[2 * j + 1] = -c_re;
-            cim[2 * j + 1] = -c_im;
-            fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
-            fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
-        }
-#if QCDW_HOP_PREFETCH
-        // issue every load of the four hops before any arithmetic
-        cx<T> ur[4][R], pu[4][3], pl[4][3];
-#pragma unroll
-        for (int h = 0; h < 4; h++) {
-#pragma unroll
-            for (int e = 0; e < R; e++) ur[h][e] = P::ld(a.gauge, loff[h] + e);
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                pu[h][c] = P::ld(a.psi, ((long)su * Vh + nbh[h]) * 3 + c);
-                pl[h][c] = P::ld(a.psi, ((long)sl * Vh + nbh[h]) * 3 + c);
-            }
-        }
-#endif
-#pragma unroll
-        for (int h = 0; h < 4; h++) {
-            const int dir = h & 1;
-            const cx<T> cc = {cre[h], cim[h]};
-            cx<T> u[9];
-#if QCDW_HOP_PREFETCH
-#pragma unroll
-            for (int e = 0; e < R; e++) u[e] = ur[h][e];
-            if constexpr (R == 6) {
-                u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-                u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-                u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-            }
-#else
-            load_link<P, R>(a.gauge, loff[h], u);
-#endif
-            cx<T> hv[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-#if QCDW_HOP_PREFETCH
-                hv[c] = pu[h][c] + cc * pl[h][c];
-#else
-                const cx<T> pu_ = P::ld(a.psi, ((long)su * Vh + nbh[h]) * 3 + c);
-                const cx<T> pl_ = P::ld(a.psi, ((long)sl * Vh + nbh[h]) * 3 + c);
-                hv[c] = pu_ + cc * pl_;
-#endif
-            }
-            cx<T> w[3];
-#pragma unroll
-            for (int r = 0; r < 3; r++) {
-                cx<T> sacc = {T(0), T(0)};
-#pragma unroll
-                for (int c = 0; c < 3; c++)
-                    sacc = dir == 0 ? sacc + u[3 * r + c] * hv[c] : sacc + cmul_conj(u[3 * c + r], hv[c]);
-                w[r] = sacc;
-            }
-            const cx<T> cd = conj(cc);
-#pragma unroll
-            for (int r = 0; r < 3; r++) {
-                const cx<T> wr = fsg[h] * w[r];
-                acc_u[r] = acc_u[r] + wr;
-                acc_l[r] = acc_l[r] + cd * wr;
-            }
-        }
+        for (int c = 0; c < 3; c++)
+            sacc = dir == 0 ? sacc + u[3 * r + c] * hv[c] : sacc + cmul_conj(u[3 * c + r], hv[c]);
+        w[r] = sacc;
     }
+    const cx<T> cd = conj(cx<T>{L.cre[h], L.cim[h]});
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        const cx<T> wr = L.fsg[h] * w[r];
+        acc_u[r] = acc_u[r] + wr;
+        acc_l[r] = acc_l[r] + cd * wr;
+    }
+}
 
-    // gather: lane q finishes spin q
+template <typename T>
+__device__ __forceinline__ void project(const cx<T> (&pu)[3], const cx<T> (&pl)[3], T cr, T ci, cx<T> (&hv)[3])
+{
+    const cx<T> cc = {cr, ci};
+#pragma unroll
+    for (int c = 0; c < 3; c++) hv[c] = pu[c] + cc * pl[c];
+}
+
+// Gather of the lane partial sums (lane q finishes spin q), epilogue, store, and
+// this site's contribution to the fused reduction (added to v).
+template <class P, int EPI, int RED>
+__device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool valid, int q,
+                                           const cx<typename P::real> (&acc_u)[3],
+                                           const cx<typename P::real> (&acc_l)[3], double (&v)[3])
+{
+    using T = typename P::real;
+    const long Vh = a.g.Vh;
+    const int gq = q >> 1;
     const int lane = threadIdx.x & 63;
     const int src = (lane & ~3) + (q < 2 ? q + 2 : 3 - q);
     cx<T> res[3];
@@ -277,7 +273,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* par
     } else {
         T win[27];
         if (valid) {
-            load_window<P>(a.clov, site, q, win);
+            load_window<P>(a.clov, Vh, site, q, win);
         } else {
 #pragma unroll
             for (int e = 0; e < 27; e++) win[e] = T(0);
@@ -315,7 +311,6 @@ __device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* par
     }
 
     if constexpr (RED != RED_NONE) {
-        double v[3] = {0.0, 0.0, 0.0};
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 3; c++) {
@@ -331,16 +326,143 @@ __device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* par
                 }
             }
         }
-        block_sum_store<3>(v, part);
     }
 }
 
+// The hop with its epilogue at one site per 4 lanes (site valid or not: every
+// thread of the block calls it); `part` receives the block's reduction partials
+// (RED != RED_NONE).
+template <class P, int R, int EPI, int RED>
+__device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid, double* part)
+{
+    using T = typename P::real;
+    const Geom g = a.g;
+    const int q = threadIdx.x & 3;
+    const int gq = q >> 1, k = q & 1;
+    const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
+
+    cx<T> acc_u[3], acc_l[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) acc_u[c] = acc_l[c] = {T(0), T(0)};
+    if (valid) {
+        LaneHops<T, R> L;
+        lane_hops<T, R>(g, site, a.parity, q, L);
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+            cx<T> pu[3], pl[3], hv[3];
+            load_pair<P>(a.psi, g.Vh, su, sl, L.nbh[h], pu, pl);
+            project(pu, pl, L.cre[h], L.cim[h], hv);
+            hop_apply<P, R>(a.gauge, L, h, hv, acc_u, acc_l);
+        }
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    hop_finish<P, EPI, RED>(a, site, valid, q, acc_u, acc_l, v);
+    if constexpr (RED != RED_NONE) block_sum_store<3>(v, part);
+}
+
+// One 64-site tile (consecutive eo indices) of the hop with its epilogue.
+template <class P, int R, int EPI, int RED>
+__device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* part)
+{
+    const int site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
+    hop_site<P, R, EPI, RED>(a, site, site < a.g.Vh, part);
+}
+
+// Single-RHS hop, one site per 4 lanes.  With cgroup = G > 0 the tiles are 64
+// consecutive c (eo index within a t-slice) of one slice, and the launch sweeps
+// t inside each group of G c-tiles: (c-tile in group, then t, then group).  The
+// input slice t is read by the output slices t - 1, t, t + 1, which then run
+// G tiles apart instead of a whole slice apart, so its spinors stay in L2.
 template <class P, int R, int EPI, int RED>
 __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
 {
     if (a.stop && *a.stop) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    hop_tile<P, R, EPI, RED>(a, tile, a.partials + 3 * (long)tile);
+    double* part = a.partials + 3 * (long)tile;
+    if (a.cgroup > 0) {
+        const Geom& g = a.g;
+        const int G = a.cgroup, St = g.Lxh * g.Ly * g.Lz;
+        const int grp = tile / (G * g.Lt), r = tile - grp * G * g.Lt;
+        const int t = r / G, ct = grp * G + (r - t * G);
+        const int c = ct * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
+        hop_site<P, R, EPI, RED>(a, t * St + c, c < St, part);
+    } else {
+        hop_tile<P, R, EPI, RED>(a, tile, part);
+    }
+}
+
+// Hop with NT output sites per thread along t.  Output sites of one parity are
+// (c, t) with eo index t St + c, c in [0, St); for fixed c and t stepping by 2 the
+// physical (x, y, z) is fixed, and the input site (c, t + 1) is both the forward
+// t-neighbour of (c, t) and the backward t-neighbour of (c, t + 2).  A thread
+// walks t = e + 2 (tg NT + j), j < NT, and carries that half-spinor from one
+// step to the next, so the t-neighbour spinors are read once per chain instead
+// of being re-fetched by the tiles of the adjacent t-slices.  Blocks: 64
+// consecutive c; the order is e, then c-tile (within its group of cgroup
+// c-tiles), then chain group tg, then c-tile group.  Requires Lt % (2 NT) == 0.
+template <class P, int R, int EPI, int RED, int NT>
+__global__ __launch_bounds__(256) QCDW_TKERNEL_ATTR void hop_tkernel(HopArgs a)
+{
+    if (a.stop && *a.stop) return;
+    using T = typename P::real;
+    const Geom g = a.g;
+    const int nct = hop_ctiles(g);
+    const int blk = xcd_tile(blockIdx.x, gridDim.x);
+    // e fastest: the two chains over one t-range read the same input slices (one for its x, y, z
+    // hops, the other for its t hops), so they run back to back; then the c-tile within its group
+    // of G, then the t-range, then the group (G = all c-tiles of a slice without grouping)
+    const int G = a.cgroup > 0 ? a.cgroup : nct, ntg = g.Lt / (2 * NT);
+    const int e = blk & 1, rest = blk >> 1;
+    const int grp = rest / (G * ntg), r = rest - grp * G * ntg;
+    const int tg = r / G, ct = grp * G + (r - tg * G);
+    const int St = g.Lxh * g.Ly * g.Lz;
+    const int q = threadIdx.x & 3;
+    const int c = ct * 64 + (threadIdx.x >> 2);
+    const bool valid = c < St;
+    const int gq = q >> 1, k = q & 1;
+    const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
+    double v[3] = {0.0, 0.0, 0.0};
+    cx<T> carry[3];  // t-lanes: projected backward half-spinor for the next step
+#pragma unroll
+    for (int cc = 0; cc < 3; cc++) carry[cc] = {T(0), T(0)};
+#if QCDW_TKERNEL_UNROLL
+#pragma unroll
+#else
+#pragma unroll 1
+#endif
+    for (int j = 0; j < NT; j++) {
+        const int t = e + 2 * (tg * NT + j);
+        const int site = t * St + c;
+        cx<T> acc_u[3], acc_l[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) acc_u[cc] = acc_l[cc] = {T(0), T(0)};
+        if (valid) {
+            LaneHops<T, R> L;
+            lane_hops<T, R>(g, site, a.parity, q, L);
+            cx<T> next[3];  // this step's forward t-neighbour, projected for the next step
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                cx<T> hv[3];
+                if (gq == 1 && h == 3 && j > 0) {
+                    // backward t-hop: the input site is the previous step's forward t-neighbour
+#pragma unroll
+                    for (int cc = 0; cc < 3; cc++) hv[cc] = carry[cc];
+                } else {
+                    cx<T> pu[3], pl[3];
+                    load_pair<P>(a.psi, g.Vh, su, sl, L.nbh[h], pu, pl);
+                    project(pu, pl, L.cre[h], L.cim[h], hv);
+                    if (gq == 1 && h == 2) project(pu, pl, -L.cre[h], -L.cim[h], next);
+                }
+                hop_apply<P, R>(a.gauge, L, h, hv, acc_u, acc_l);
+            }
+            if (gq == 1) {
+#pragma unroll
+                for (int cc = 0; cc < 3; cc++) carry[cc] = next[cc];
+            }
+        }
+        hop_finish<P, EPI, RED>(a, site, valid, q, acc_u, acc_l, v);
+    }
+    if constexpr (RED != RED_NONE) block_sum_store<3>(v, a.partials + 3 * (long)blk);
 }
 
 // Multi-RHS hop, L2-reuse form: block -> (tile, rhs) with rhs fastest, so the
@@ -396,18 +518,23 @@ __global__ __launch_bounds__(256) void hop_batch_kernel(BatchHopArgs b)
     }
 }
 
-template <class P, int R>
-static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
+template <class P, int R, int NT>
+static hipError_t launch_hop_nt(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
-    dim3 grid(hop_blocks(a.g.Vh)), block(256);
+    dim3 grid(hop_blocks_nt(a.g, NT, a.cgroup)), block(256);
     // with events, they are recorded by the dispatch itself (exact kernel time)
-#define QCDW_HOP_CASE(E, D)                                                                          \
-    if (epi == E && red == D) {                                                                     \
-        if (e0)                                                                                     \
-            hipExtLaunchKernelGGL((hop_kernel<P, R, E, D>), grid, block, 0, s, e0, e1, 0, a);        \
-        else                                                                                        \
-            hipLaunchKernelGGL((hop_kernel<P, R, E, D>), grid, block, 0, s, a);                      \
-        return hipGetLastError();                                                                   \
+#define QCDW_HOP_KERNEL(E, D) hop_kernel<P, R, E, D>
+#define QCDW_TKERNEL(E, D) hop_tkernel<P, R, E, D, NT>
+#define QCDW_HOP_CASE(E, D)                                                                            \
+    if (epi == E && red == D) {                                                                       \
+        if constexpr (NT == 1) {                                                                      \
+            if (e0) hipExtLaunchKernelGGL((QCDW_HOP_KERNEL(E, D)), grid, block, 0, s, e0, e1, 0, a);    \
+            else hipLaunchKernelGGL((QCDW_HOP_KERNEL(E, D)), grid, block, 0, s, a);                     \
+        } else {                                                                                      \
+            if (e0) hipExtLaunchKernelGGL((QCDW_TKERNEL(E, D)), grid, block, 0, s, e0, e1, 0, a);       \
+            else hipLaunchKernelGGL((QCDW_TKERNEL(E, D)), grid, block, 0, s, a);                        \
+        }                                                                                             \
+        return hipGetLastError();                                                                     \
     }
     QCDW_HOP_CASE(EPI_NONE, RED_NONE)
     QCDW_HOP_CASE(EPI_CLOV, RED_NONE)
@@ -416,7 +543,21 @@ static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& 
     QCDW_HOP_CASE(EPI_CLOV_XPAY, RED_TS)
     QCDW_HOP_CASE(EPI_XPAY_CLOVY, RED_NONE)
 #undef QCDW_HOP_CASE
+#undef QCDW_TKERNEL
+#undef QCDW_HOP_KERNEL
     return hipErrorInvalidValue;
+}
+
+template <class P, int R>
+static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
+{
+    if (!hop_nt_fits(a.g, a.nt) || !hop_cgroup_fits(a.g, a.cgroup)) return hipErrorInvalidValue;
+    switch (a.nt) {
+    case 2: return launch_hop_nt<P, R, 2>(s, epi, red, a, e0, e1);
+    case 4: return launch_hop_nt<P, R, 4>(s, epi, red, a, e0, e1);
+    case 8: return launch_hop_nt<P, R, 8>(s, epi, red, a, e0, e1);
+    default: return launch_hop_nt<P, R, 1>(s, epi, red, a, e0, e1);
+    }
 }
 
 template <class P>

@@ -152,9 +152,9 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
             fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
         }
         if constexpr (EPI != EPI_NONE) {
-            const long base = ((long)site * 2 + (q >> 1)) * 36 + 9 * (q & 1);
+            const long base = clov_index(site, q >> 1, 9 * (q & 1));
 #pragma unroll
-            for (int e = 0; e < 27; e++) win[e] = P::ldr(a.clov, base + e);
+            for (int e = 0; e < 27; e++) win[e] = P::ldr(a.clov, base + (long)e * CLOV_STRIDE);
         }
     }
 

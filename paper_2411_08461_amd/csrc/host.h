@@ -193,7 +193,9 @@ struct qcdw_op {
     int recon = 12;
     DevBuf gauge64, gauge_lo;
     DevBuf Ainv64[2], Ainv_lo[2], A64[2];
-    Workspace ws;  // single- and multi-RHS solves
+    int hop_nt[4] = {1, 1, 1, 1};  // single-RHS hop, per precision (tuned): sites per thread along t
+    int hop_cg[4] = {0, 0, 0, 0};  //   and c-tiles per group swept along t (0: none)
+    Workspace ws;                  // single- and multi-RHS solves
 };
 
 // a set of operators solved together (different lattices and kappas)
@@ -232,14 +234,18 @@ inline HopArgs hop_args(const Geom& g, int parity)
     a.g = g;
     a.parity = parity;
     a.nrhs = 1;
+    a.nt = 1;
     return a;
 }
 
 // out_e = M_hat in_e = in_e - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe in_e, with an optional fused reduction
+// (hop_blocks_nt(op->g, op->hop_nt[v.prec], op->hop_cg[v.prec]) partials)
 inline hipError_t matpc(hipStream_t s, const qcdw_op* op, const PrecView& v, const void* in, void* out, void* tmp_o, int red,
                  const void* w, double* partials, const int* stop)
 {
     HopArgs a = hop_args(op->g, 1);
+    a.nt = op->hop_nt[v.prec];
+    a.cgroup = op->hop_cg[v.prec];
     a.psi = in;
     a.out = tmp_o;
     a.gauge = v.gauge;
@@ -248,6 +254,8 @@ inline hipError_t matpc(hipStream_t s, const qcdw_op* op, const PrecView& v, con
     hipError_t e = launch_hop(s, v.prec, v.recon, EPI_CLOV, RED_NONE, a);
     if (e != hipSuccess) return e;
     HopArgs b = hop_args(op->g, 0);
+    b.nt = op->hop_nt[v.prec];
+    b.cgroup = op->hop_cg[v.prec];
     b.psi = tmp_o;
     b.out = out;
     b.gauge = v.gauge;

@@ -43,6 +43,8 @@ struct HopArgs {
     int nrhs;           // right-hand sides interleaved per site (1 or more)
     const int* active;  // multi-RHS: per-RHS active flag (nullptr: all active)
     const int* stop;    // if non-null and *stop != 0 the launch does nothing
+    int nt;             // single-RHS hop: output sites per thread along t (1, 2, 4 or 8; 0 means 1)
+    int cgroup;         // single-RHS hop: c-tiles per group swept along t (0: no grouping)
 };
 
 // one problem of a batched solve (device table entry); reconstruct-12 operators
@@ -75,6 +77,24 @@ struct BatchHopArgs {
 
 constexpr int HOP_SITES_PER_BLOCK = 64;  // 4 lanes per site, 256 threads
 __host__ __device__ inline int hop_blocks(int Vh) { return (Vh + HOP_SITES_PER_BLOCK - 1) / HOP_SITES_PER_BLOCK; }
+// the t-stepping hop (nt sites per thread along t) needs Lt % (2 nt) == 0
+__host__ __device__ inline bool hop_nt_fits(const Geom& g, int nt)
+{
+    return nt <= 1 || ((nt == 2 || nt == 4 || nt == 8) && g.Lt % (2 * nt) == 0);
+}
+// tiles of 64 consecutive sites within one t-slice (eo index c in [0, Lxh Ly Lz))
+__host__ __device__ inline int hop_ctiles(const Geom& g) { return (g.Lxh * g.Ly * g.Lz + 63) / 64; }
+// a c-tile group size is valid if it divides the c-tiles of a slice
+__host__ __device__ inline bool hop_cgroup_fits(const Geom& g, int cg)
+{
+    return cg == 0 || (cg > 0 && hop_ctiles(g) % cg == 0);
+}
+// blocks (and reduction partials) of one single-RHS hop launch
+__host__ __device__ inline int hop_blocks_nt(const Geom& g, int nt, int cg)
+{
+    if (nt <= 1) return cg > 0 ? hop_ctiles(g) * g.Lt : hop_blocks(g.Vh);
+    return hop_ctiles(g) * (g.Lt / nt);
+}
 
 // e0/e1: optional events recorded by the kernel dispatch itself (timing)
 hipError_t launch_hop(hipStream_t s, int prec, int recon, int epi, int red, const HopArgs& a,

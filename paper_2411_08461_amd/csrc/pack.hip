@@ -46,7 +46,7 @@ __global__ void k_pack_gauge(const double2* __restrict__ paper, void* out, int V
     P::st(out, e, cx<T>{(T)v.x, (T)v.y});
 }
 
-// clover: paper [2][Vh][2][36] -> internal [Vh][2][36] in the reordered packing
+// clover: paper [2][Vh][2][36] -> internal (one parity) [Vh][2][36] in the reordered packing
 //   [d0 d1 d2 | L10 L20 L21 | L30 L31 L32 L40 L41 L42 L50 L51 L52 | d3 d4 d5 | L43 L53 L54]
 // The paper packing is [d0..d5 | L10 L20 L21 L30 L31 L32 L40 L41 L42 L43 L50 .. L54].
 __device__ __forceinline__ int clover_src_pos(int m)
@@ -70,10 +70,10 @@ __device__ __forceinline__ int clover_src_pos(int m)
 template <class P>
 __global__ void k_pack_clover(const double* __restrict__ paper, void* out, int Vh, int parity)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 72L * Vh) return;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;  // = clov_index(site, chi, m)
+    if (e >= clov_reals(Vh)) return;
     const int m = (int)(e % 36);
-    const long blk = e / 36;  // site*2 + chirality
+    const long blk = e / 36;  // site * 2 + chirality
     using T = typename P::real;
     P::str(out, e, (T)paper[((long)parity * Vh * 2 + blk) * 36 + clover_src_pos(m)]);
 }
@@ -136,7 +136,7 @@ hipError_t launch_pack_gauge(hipStream_t s, int prec, int recon, const Geom& g, 
 
 hipError_t launch_pack_clover(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal)
 {
-    const long n = 72L * g.Vh;
+    const long n = clov_reals(g.Vh);
     if (n == 0) return hipSuccess;
     const double* pp = (const double*)paper;
     switch (prec) {
