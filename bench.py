@@ -87,10 +87,15 @@ def parse():
     ap.add_argument("--matpc-only", default="",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then a few M_hat "
                          "applications in FP64 and BF16 on this lattice, e.g. 24,24,24,64; prints nothing else")
+    ap.add_argument("--forms", default="",
+                    help="with --matpc-only: hop forms nt:cgroup to run one after the other (each in a fresh "
+                         "context whose tuning file fixes the form), e.g. 1:0,1:27,2:12")
     return ap.parse_args()
 
 
-def matpc_only(L):
+def matpc_only(L, forms):
+    import tempfile
+
     import numpy as np
     import torch
 
@@ -106,21 +111,32 @@ def matpc_only(L):
     U = torch.from_numpy(li.random_gauge(L, 0.2, 0)).cuda()
     xe = torch.from_numpy(li.z2_source(L, 1000).reshape(-1, 4, 3)[:Vh].copy()).cuda()
     out = torch.empty_like(xe)
-    ctx = q.Context(0)
-    op = q.Operator(ctx, q.make_lattice(L), U, 0.125, 1.1, "bf16", 12)
-    for prec in ("f64", "bf16"):
-        for _ in range(3):
-            q.qcdw_op_matpc(op, prec, xe, out)
-    torch.cuda.synchronize()
-    op.close()
-    ctx.close()
-    print(json.dumps({"matpc_only": list(L), "copy_bytes": 2 * src.numel() * 8}))
+    runs = []
+    for f in forms or [None]:
+        if f is not None:  # a fresh context reads the tuning file that fixes the form
+            nt, cg = f
+            path = os.path.join(tempfile.gettempdir(), f"qcdw_form_{nt}_{cg}.txt")
+            with open(path, "w") as fh:
+                for p in range(4):
+                    fh.write(f"hop_nt/p{p}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {nt + 16 * cg}\n")
+            os.environ["QCDW_TUNE_CACHE"] = path
+        ctx = q.Context(0)
+        op = q.Operator(ctx, q.make_lattice(L), U, 0.125, 1.1, "bf16", 12)
+        runs.append({"f64": q.qcdw_op_hop_form(op, "f64"), "bf16": q.qcdw_op_hop_form(op, "bf16")})
+        for prec in ("f64", "bf16"):
+            for _ in range(3):
+                q.qcdw_op_matpc(op, prec, xe, out)
+        torch.cuda.synchronize()
+        op.close()
+        ctx.close()
+    print(json.dumps({"matpc_only": list(L), "copy_bytes": 2 * src.numel() * 8, "forms": runs}))
 
 
 def main():
     args = parse()
     if args.matpc_only:
-        matpc_only([int(v) for v in args.matpc_only.split(",")])
+        forms = [tuple(int(x) for x in f.split(":")) for f in args.forms.split(",") if f]
+        matpc_only([int(v) for v in args.matpc_only.split(",")], forms)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -199,6 +215,7 @@ def main():
     t64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True)
     tlo = q.make_params(tol=1e-10, maxiter=20000, inner=args.inner, delta=plo.delta, collect_timing=True)
     op = q.Operator(ctx, lat, Ud, kappa, csw, args.inner, 12)
+    form = q.qcdw_op_hop_form(op, "f64")
     timed = []
     t1 = time.perf_counter()
     for _ in range(args.steps):
@@ -236,9 +253,10 @@ def main():
         "config": {"workload": "wilson-clover even-odd BiCGStab 16^3x32, kappa 0.124, csw 1.0, eps 0.2, Z2 source",
                    "lattice": list(L), "kappa": kappa, "csw": csw, "tol": 1e-10, "inner": args.inner},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "hop_kernel<P64, r12, EPI_CLOV, RED_NONE>", "launches_timed": n_a,
-                     "bytes_per_launch": hop_a_bytes("f64") * Vh, "avg_launch_us": round(avg_a_ms * 1e3, 2)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form),
+                     "kernel": hop_kernel_name(form), "form": {"nt": form[0], "cgroup": form[1]},
+                     "launches_timed": n_a, "bytes_per_launch": hop_a_bytes("f64") * Vh,
+                     "avg_launch_us": round(avg_a_ms * 1e3, 2)},
         "solve": {
             "f64": {"iters": i64.iters, "true_res": i64.true_res, "time_ms": round(i64.time_ms, 3),
                     "reliable": i64.n_reliable},
@@ -269,6 +287,43 @@ def main():
     print(json.dumps(result))
     sys.stdout.flush()
     ctx.close()
+
+
+def hop_kernel_name(form):
+    nt, cg = form
+    if nt == 1:
+        return "hop_kernel<P64, r12, EPI_CLOV, RED_NONE>" + (f" (slice groups of {cg} c-tiles)" if cg else "")
+    return f"hop_tkernel<P64, r12, EPI_CLOV, RED_NONE, {nt}>" + (f" (slice groups of {cg} c-tiles)" if cg else "")
+
+
+KERNEL_SOURCES = ("paper_2411_08461_amd/csrc/hop.hip", "paper_2411_08461_amd/csrc/dev.h",
+                  "paper_2411_08461_amd/csrc/internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_wc16x32_traffic.md")
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(form):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
+    profile of this workload, if it was taken from the current kernel sources with the same hop
+    form; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            line = next(ln for ln in f if ln.startswith("traffic-json: "))
+        rec = json.loads(line[len("traffic-json: "):])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel_sources_sha256() or [rec.get("nt"), rec.get("cgroup")] != list(form):
+        return None
+    return int(rec["read_bytes"] + rec["write_bytes"])
 
 
 def stream_probe(torch):

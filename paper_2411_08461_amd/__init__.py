@@ -34,7 +34,7 @@ PREC = {"f64": QCDW_F64, "f32": QCDW_F32, "bf16": QCDW_BF16, "f16": QCDW_F16}
 EXPORTED = (
     "qcdw_solver_params_default", "qcdw_ctx_create", "qcdw_ctx_destroy", "qcdw_last_error", "qcdw_ctx_set_stream",
     "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_op_create",
-    "qcdw_op_destroy", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
+    "qcdw_op_destroy", "qcdw_op_hop_form", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
     "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_destroy": (None, [p]),
+        "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
         "qcdw_op_matpc_multi": (i, [p, i, i, p, p]),
         "qcdw_invert": (i, [p, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
@@ -376,6 +377,13 @@ def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8,
     prm.gmres_restart = int(gmres_restart)
     prm.gmres_fallback = 1 if gmres_fallback else 0
     return prm
+
+
+def qcdw_op_hop_form(op: Operator, prec: str = "f64"):
+    """(nt, cgroup): the tuned form of the operator's single-RHS hop in precision prec."""
+    nt, cg = ctypes.c_int(), ctypes.c_int()
+    _check(op.ctx.handle, load_library().qcdw_op_hop_form(op.handle, PREC[prec], ctypes.byref(nt), ctypes.byref(cg)))
+    return nt.value, cg.value
 
 
 def qcdw_invert(op: Operator, b, x, params: qcdw_solver_params | None = None, raise_on_error: bool = False):

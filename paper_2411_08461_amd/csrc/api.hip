@@ -266,8 +266,11 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e != hipSuccess) break;
-        if (ms < best) {
-            best = ms;
+        // the plain form (first candidate) is kept unless another is more than 3 % faster, so
+        // that timing noise does not flip the choice between runs
+        const float t = code == cand[0] ? ms : ms * 1.03f;
+        if (t < best) {
+            best = t;
             best_c = code;
         }
     }
@@ -354,6 +357,17 @@ void qcdw_op_destroy(qcdw_op* op)
     DeviceGuard dg(op->ctx->device);
     (void)hipStreamSynchronize(op->ctx->stream);
     delete op;
+}
+
+qcdw_status qcdw_op_hop_form(const qcdw_op* op, qcdw_prec prec, int* nt, int* cgroup)
+{
+    if (!op) return QCDW_EINVAL;
+    if (!nt || !cgroup) return fail(op->ctx, QCDW_EINVAL, "nt and cgroup must not be NULL");
+    if (prec != QCDW_F64 && prec != (qcdw_prec)op->inner)
+        return fail(op->ctx, QCDW_EINVAL, "prec must be F64 or the operator's inner precision");
+    *nt = op->hop_nt[prec];
+    *cgroup = op->hop_cg[prec];
+    return QCDW_OK;
 }
 
 qcdw_status qcdw_op_matpc(qcdw_op* op, qcdw_prec prec, const void* in_e, void* out_e)

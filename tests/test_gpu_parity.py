@@ -181,6 +181,7 @@ def test_t_stepping_matpc(tmp_path, monkeypatch, L, nt, cg):
         c = _forced_nt_context(tmp_path, monkeypatch, L, n, g)
         for prec in ("f64", "bf16", "f16", "f32"):
             op = q.Operator(c, q.make_lattice(L), dev(U), kappa, csw, prec, 12)
+            assert q.qcdw_op_hop_form(op, "f64") == (n, g) and q.qcdw_op_hop_form(op, prec) == (n, g)
             for pr in ("f64", prec):
                 out = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
                 q.qcdw_op_matpc(op, pr, xe, out)
