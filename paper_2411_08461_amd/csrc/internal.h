@@ -171,8 +171,10 @@ hipError_t launch_hop_rhs(hipStream_t s, int prec, int epi, int red, const HopAr
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // learned preconditioner layers (activations [parity][channel][Vh][3], FP32/BF16 storage)
+// mfma: layers with a BF16 end mix channels on the BF16 matrix cores (k_net_layer_mfma)
 hipError_t launch_net_layer(hipStream_t s, int pin, int pout, int cin, int cout, const void* in, void* out,
-                            const void* gauge32, const void* W, const Geom& g);
+                            const void* gauge32, const void* W, const Geom& g,
+                            int mfma = 0);
 // out[2 cin cout] (+)= weight gradient of hop a: sum_x g_{c'} conj(T_a phi_c); partials: [blocks][2 cin cout]
 hipError_t launch_net_wgrad(hipStream_t s, int cin, int cout, const void* phi, const void* gz, const void* gauge32,
                             const Geom& g, int a, double* partials, double* out, int accumulate);

@@ -21,6 +21,7 @@ struct qcdw_net {
     DevBuf diff, tmp64, partials, res;
     int adam_step = 0;
     bool bf_dirty = true;
+    int mfma = 0;  // BF16 application layers on the matrix cores (chosen by timing at creation)
 };
 
 namespace {
@@ -72,13 +73,63 @@ qcdw_status net_forward_internal(qcdw_net* net, int prec, const void* in_int, vo
     HIPCHK(ctx, hipMemsetAsync((char*)net->act0.p + n * 8, 0, n * 8, s));
     if (prec == BF16) {
         CHK(net_refresh_bf16(net));
-        HIPCHK(ctx, launch_net_layer(s, F32, BF16, 4, h, net->act0.p, net->hid16.p, net->gauge32.p, net->W1bf.p, g));
-        HIPCHK(ctx, launch_net_layer(s, BF16, F32, h, 4, net->hid16.p, net->z.p, net->gauge32.p, net->W2bf.p, g));
+        HIPCHK(ctx, launch_net_layer(s, F32, BF16, 4, h, net->act0.p, net->hid16.p, net->gauge32.p, net->W1bf.p, g,
+                                     net->mfma));
+        HIPCHK(ctx, launch_net_layer(s, BF16, F32, h, 4, net->hid16.p, net->z.p, net->gauge32.p, net->W2bf.p, g,
+                                     net->mfma));
     } else {
         HIPCHK(ctx, launch_net_layer(s, F32, F32, 4, h, net->act0.p, net->hid.p, net->gauge32.p, net->W1.p, g));
         HIPCHK(ctx, launch_net_layer(s, F32, F32, h, 4, net->hid.p, net->z.p, net->gauge32.p, net->W2.p, g));
     }
     HIPCHK(ctx, launch_convert(s, F32, F64, net->z.p, out_int, n, 1.0));
+    return QCDW_OK;
+}
+
+// Layer kernels of the BF16 application: channel mixing on the matrix cores or on vector FMA, whichever
+// is faster on this lattice (timed on zero fields; cached per lattice and width on the context and in
+// the tuning file as "net_mfma/h<hidden>/L<Lx>x<Ly>x<Lz>x<Lt> 0|1").
+qcdw_status net_tune_layers(qcdw_net* net)
+{
+    qcdw_ctx* ctx = net->ctx;
+    const Geom& g = net->op->g;
+    char key[96];
+    snprintf(key, sizeof key, "net_mfma/h%d/L%dx%dx%dx%d", net->hidden, g.Lx, g.Ly, g.Lz, g.Lt);
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end() && (it->second == 0 || it->second == 1)) {
+        net->mfma = it->second;
+        return QCDW_OK;
+    }
+    hipStream_t s = ctx->stream;
+    const long n = 12L * g.Vh;
+    HIPCHK(ctx, hipMemsetAsync(net->tmp64.p, 0, n * 16, s));
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_m = 0;
+    qcdw_status st = QCDW_OK;
+    for (int m : {0, 1}) {
+        net->mfma = m;
+        st = net_forward_internal(net, BF16, net->tmp64.p, net->diff.p);  // warm-up
+        hipError_t e = hipEventRecord(e0, s);
+        for (int rep = 0; rep < 3 && st == QCDW_OK && e == hipSuccess; rep++)
+            st = net_forward_internal(net, BF16, net->tmp64.p, net->diff.p);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (st == QCDW_OK && e != hipSuccess) st = fail(ctx, QCDW_EHIP, "net tuning failed: %s", hipGetErrorString(e));
+        if (st != QCDW_OK) break;
+        if (ms < best) {
+            best = ms;
+            best_m = m;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != QCDW_OK) return st;
+    net->mfma = best_m;
+    ctx->tune_store(key, best_m);
     return QCDW_OK;
 }
 
@@ -170,6 +221,8 @@ extern "C" qcdw_status qcdw_net_create(qcdw_op* op, int hidden, uint64_t seed, d
         hipMemset(net->m2.p, 0, net->nw2 * 16) != hipSuccess || hipMemset(net->v2.p, 0, net->nw2 * 16) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return bail(fail(ctx, QCDW_EHIP, "net initialisation failed"));
+    const qcdw_status st = net_tune_layers(net);
+    if (st != QCDW_OK) return bail(st);
     *out = net;
     return QCDW_OK;
 }

@@ -93,6 +93,132 @@ __device__ __forceinline__ void transport(const void* in, const void* gauge, con
     }
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) { return (short)f2bf_bits(f); }
+
+// The layer with its channel mixing on the matrix cores in BF16 (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation): the application path of the preconditioner, whose weights are BF16 values.  For each
+// colour k the layer is the real product  OUT_k[site, n] = sum_kk A_k[site, kk] B[kk, n]:  rows are the
+// 16 sites of a wave, kk runs over (pair (a, c), re/im) with A the transported inputs (T_a phi_c)(site)_k
+// rounded to BF16, and n over (output channel d, re/im) with B the weights in real form
+// [[Re W, Im W], [-Im W, Re W]].  The instruction takes A[m][kk] from lane m + 16 (kk / 4), element
+// kk % 4, and B[kk][n] from lane n + 16 (kk / 4), element kk % 4 (16 kk per step), so each 16-lane group
+// q of a wave supplies 4 reals per step: two of its PG = 9 CIN / 4 pairs (channels q, q + 4, ... of
+// each hop, hop-major, padded to an even count with zero pairs) for its lane's site, and the matching
+// rows of B.  The result D[m][n] sits in lane n + 16 (m / 4), element m % 4.  A hop's link and
+// neighbour serve its CIN / 4 consecutive pairs.
+template <class PI, class PO, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_net_layer_mfma(NetArgs n)
+{
+    constexpr int PG = 9 * CIN / 4;
+    constexpr int STEPS = (PG + 1) / 2;
+    constexpr int NTILE = (2 * COUT + 15) / 16;
+    static_assert(9 * CIN % 4 == 0, "pairs must split over the four lane groups");
+    const Geom g = n.g;
+    const long Vh = g.Vh;
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    const long gsite = wave * 16 + row;  // this lane's A row: site over both parities
+    const bool valid = gsite < 2 * Vh;
+    const int p = valid ? (int)(gsite / Vh) : 0, i = valid ? (int)(gsite % Vh) : 0;
+    int x, y, z, t;
+    site_coords(g, i, p, x, y, z, t);
+    mfma_f4 acc[3][NTILE];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int tl = 0; tl < NTILE; tl++) acc[k][tl] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    int cur_a = -1, nb = i;
+    cx<float> u[9];
+    for (int st = 0; st < STEPS; st++) {
+        mfma_s4 A[3], B[NTILE];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {  // the two pairs of this step
+            const int s2 = 2 * st + h;
+            const bool real_pair = s2 < PG;
+            // group q takes channels q, q + 4, ... of every hop, hop-major: all groups are on the
+            // same hop at each step, so link loads and the identity hop stay uniform over the wave
+            const int s2r = real_pair ? s2 : 0, a = s2r / (CIN / 4), c = grp + 4 * (s2r - a * (CIN / 4));
+            cx<float> Y[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+            if (valid && real_pair) {
+                const int mu = (a - 1) >> 1, back = (a - 1) & 1;
+                if (a != cur_a) {
+                    cur_a = a;
+                    if (a > 0) {
+                        nb = nbr_index(g, i, x, y, z, t, mu, back);
+                        su3_row3(n.gauge, back == 0 ? (((long)mu * 2 + p) * Vh + i) * 6
+                                                    : (((long)mu * 2 + (1 - p)) * Vh + nb) * 6, u);
+                    }
+                }
+                if (a == 0) {
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const auto v = PI::ld(n.in, (((long)p * CIN + c) * Vh + i) * 3 + k);
+                        Y[k] = {(float)v.re, (float)v.im};
+                    }
+                } else {
+                    cx<float> v[3];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const auto w = PI::ld(n.in, (((long)(1 - p) * CIN + c) * Vh + nb) * 3 + k);
+                        v[k] = {(float)w.re, (float)w.im};
+                    }
+#pragma unroll
+                    for (int r = 0; r < 3; r++) {
+                        cx<float> sacc = {0.f, 0.f};
+#pragma unroll
+                        for (int k = 0; k < 3; k++)
+                            sacc = back == 0 ? sacc + u[3 * r + k] * v[k] : sacc + cmul_conj(u[3 * k + r], v[k]);
+                        Y[r] = sacc;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                A[k][2 * h] = bf16_bits(Y[k].re);
+                A[k][2 * h + 1] = bf16_bits(Y[k].im);
+            }
+            // B rows (pair, re) and (pair, im) for column (d, re/im) = lane & 15 + 16 tl
+#pragma unroll
+            for (int tl = 0; tl < NTILE; tl++) {
+                const int col = row + 16 * tl, d = col >> 1;
+                float bre = 0.f, bim = 0.f;
+                if (real_pair && d < COUT) {
+                    const float2 w = n.W[((long)a * COUT + d) * CIN + c];
+                    bre = (col & 1) ? w.y : w.x;
+                    bim = (col & 1) ? w.x : -w.y;
+                }
+                B[tl][2 * h] = bf16_bits(bre);
+                B[tl][2 * h + 1] = bf16_bits(bim);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int tl = 0; tl < NTILE; tl++)
+                acc[k][tl] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[k], B[tl], acc[k][tl], 0, 0, 0);
+    }
+    using TO = typename PO::real;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int tl = 0; tl < NTILE; tl++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const float v = acc[k][tl][e];
+                const float vp = __shfl_xor(v, 1, 64);  // the partner lane holds the other part
+                const int col = row + 16 * tl, d = col >> 1;
+                const long srow = wave * 16 + 4 * grp + e;
+                if ((col & 1) == 0 && d < COUT && srow < 2 * Vh) {
+                    const int pp = (int)(srow / Vh), ii = (int)(srow % Vh);
+                    PO::st(n.out, (((long)pp * COUT + d) * Vh + ii) * 3 + k, cx<TO>{(TO)v, (TO)vp});
+                }
+            }
+}
+
 template <class PI, class PO, int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_net_layer(NetArgs n)
 {
@@ -252,21 +378,37 @@ hipError_t launch_gaussian(hipStream_t s, void* out, long n, uint64_t seed, uint
 }
 
 hipError_t launch_net_layer(hipStream_t s, int pin, int pout, int cin, int cout, const void* in, void* out,
-                            const void* gauge32, const void* W, const Geom& g)
+                            const void* gauge32, const void* W, const Geom& g, int mfma)
 {
     NetArgs n{in, out, gauge32, (const float2*)W, g};
     const dim3 grid = g256(2L * g.Vh);
+    const dim3 grid_mfma((unsigned)((2L * g.Vh + 63) / 64));  // 16 sites per wave, 4 waves per block
+    // layers with a BF16 end (the preconditioner's application) mix channels on the matrix cores
+#define QCDW_NET_MFMA_CASE(PI, PO, CI, CO, pi, po)                                                \
+    if (pin == pi && pout == po && cin == CI && cout == CO) {                                     \
+        hipLaunchKernelGGL((k_net_layer_mfma<PI, PO, CI, CO>), grid_mfma, dim3(256), 0, s, n);     \
+        return hipGetLastError();                                                                 \
+    }
 #define QCDW_NET_CASE(PI, PO, CI, CO, pi, po)                                              \
     if (pin == pi && pout == po && cin == CI && cout == CO) {                              \
         hipLaunchKernelGGL((k_net_layer<PI, PO, CI, CO>), grid, dim3(256), 0, s, n);        \
         return hipGetLastError();                                                          \
+    }
+    if (mfma) {
+        QCDW_NET_MFMA_CASE(P32, PBF16, 4, 12, F32, BF16)
+        QCDW_NET_MFMA_CASE(PBF16, P32, 12, 4, BF16, F32)
+        QCDW_NET_MFMA_CASE(P32, PBF16, 4, 4, F32, BF16)
+        QCDW_NET_MFMA_CASE(PBF16, P32, 4, 4, BF16, F32)
     }
     QCDW_NET_CASE(P32, P32, 4, 12, F32, F32)
     QCDW_NET_CASE(P32, P32, 12, 4, F32, F32)
     QCDW_NET_CASE(P32, PBF16, 4, 12, F32, BF16)
     QCDW_NET_CASE(PBF16, P32, 12, 4, BF16, F32)
     QCDW_NET_CASE(P32, P32, 4, 4, F32, F32)
+    QCDW_NET_CASE(P32, PBF16, 4, 4, F32, BF16)
+    QCDW_NET_CASE(PBF16, P32, 4, 4, BF16, F32)
 #undef QCDW_NET_CASE
+#undef QCDW_NET_MFMA_CASE
     return hipErrorInvalidValue;
 }
 

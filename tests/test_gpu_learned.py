@@ -27,16 +27,24 @@ def ctx():
     c.close()
 
 
-def _setup(ctx, L, seed=0, kappa=0.12, init_scale=0.3):
+def _setup(ctx, L, seed=0, kappa=0.12, init_scale=0.3, hidden=12):
     U = li.random_gauge(L, 0.3, 40 + seed)
     op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, 1.0, "bf16", 12)
-    net = q.Net(op, 12, seed=seed, init_scale=init_scale)
+    net = q.Net(op, hidden, seed=seed, init_scale=init_scale)
     return U, op, net
 
 
-@pytest.mark.parametrize("L", [(6, 4, 2, 6), (8, 4, 4, 8)])
-def test_net_forward_matches_oracle(ctx, L):
-    U, op, net = _setup(ctx, L, 1)
+@pytest.mark.parametrize("mfma", [0, 1])
+@pytest.mark.parametrize("L,hidden", [((6, 4, 2, 6), 12), ((8, 4, 4, 8), 12), ((6, 4, 4, 6), 4), ((10, 6, 2, 4), 12)])
+def test_net_forward_matches_oracle(tmp_path, monkeypatch, L, hidden, mfma):
+    """FP32 application and BF16 application against the FP64 oracle, with the BF16 layers' channel
+    mixing forced (through the tuning cache) onto vector FMA or onto the BF16 matrix cores; the
+    10x6x2x4 lattice leaves a ragged last wave of 16 sites."""
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"net_mfma/h{hidden}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {mfma}\n")
+    monkeypatch.setenv("QCDW_TUNE_CACHE", str(cache))
+    ctx = q.Context(0)
+    U, op, net = _setup(ctx, L, 1, hidden=hidden)
     W1, W2 = q.qcdw_net_get_weights(net)
     Vh = int(np.prod(L)) // 2
     r = li.gaussian_source(L, 50).reshape(-1, 4, 3)[:Vh].copy()
@@ -51,6 +59,8 @@ def test_net_forward_matches_oracle(ctx, L):
     assert err16 < 3e-2
     net.close()
     op.close()
+    torch.cuda.synchronize()
+    ctx.close()
 
 
 def test_net_loss_and_gradients_match_oracle(ctx):
