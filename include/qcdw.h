@@ -91,7 +91,11 @@ typedef struct {
                               Both run the same kernels in the same order (bitwise equal x). */
     int32_t gmres_restart; /* FGMRES: Krylov vectors per restart cycle (1..64) */
     int32_t gmres_fallback;/* FGMRES: 1 = hand a stalled solve to BiCGStab, 0 = keep restarting */
-    int32_t pad_;
+    int32_t inner_resume;  /* mixed precision: 0 = every reliable update restarts BiCGStab from the true
+                              residual; 1 = it replaces the iterated residual by the true one and continues
+                              the recurrence (search direction, shadow residual and scalars kept), which
+                              saves iterations on well-conditioned systems and costs them near the critical
+                              kappa.  A cycle after a breakdown, overflow or stall always restarts. */
 } qcdw_solver_params;
 
 typedef struct {
@@ -118,7 +122,8 @@ typedef struct {
 } qcdw_solve_info;
 
 /* Defaults: tol 1e-10, maxiter 10000, inner F64, delta 0.1, check_every 8,
-   max_restarts 8, collect_timing 0, fault_inject 0, use_graph 1, gmres_restart 32, gmres_fallback 1. */
+   max_restarts 8, collect_timing 0, fault_inject 0, use_graph 1, gmres_restart 32, gmres_fallback 1,
+   inner_resume 0. */
 void qcdw_solver_params_default(qcdw_solver_params *p);
 
 /* Context bound to one device and one HIP stream (hipStream_t, may be NULL for

@@ -64,7 +64,7 @@ class qcdw_solver_params(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("gmres_restart", ctypes.c_int32),
         ("gmres_fallback", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("inner_resume", ctypes.c_int32),
     ]
 
 
@@ -363,7 +363,7 @@ class SolveInfo:
 
 def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8, max_restarts=8,
                 collect_timing=False, fault_inject=0, use_graph=True, gmres_restart=32,
-                gmres_fallback=True) -> qcdw_solver_params:
+                gmres_fallback=True, inner_resume=False) -> qcdw_solver_params:
     prm = qcdw_solver_params_default()
     prm.tol = float(tol)
     prm.maxiter = int(maxiter)
@@ -376,6 +376,7 @@ def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8,
     prm.use_graph = 1 if use_graph else 0
     prm.gmres_restart = int(gmres_restart)
     prm.gmres_fallback = 1 if gmres_fallback else 0
+    prm.inner_resume = 1 if inner_resume else 0
     return prm
 
 

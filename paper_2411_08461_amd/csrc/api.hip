@@ -22,7 +22,7 @@ void qcdw_solver_params_default(qcdw_solver_params* p)
     p->use_graph = 1;
     p->gmres_restart = 32;
     p->gmres_fallback = 1;
-    p->pad_ = 0;
+    p->inner_resume = 0;
 }
 
 qcdw_status qcdw_ctx_create(qcdw_ctx** ctx, int device, void* hip_stream)
@@ -895,7 +895,7 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
     CHK(S.true_schur_residual(rr_hi));
     for (int k = 0; k < nprob; k++)
         if (!done[k]) hist_host[k].push_back(std::sqrt(rr_hi[k]) / bnorm[k]);
-    int lock_iters = 0, reliable = 0, fault = prm.fault_inject;
+    int lock_iters = 0, reliable = 0, fault = prm.fault_inject, cycles = 0;
     const int maxiter = prm.maxiter;
     bool mixed = kprec != F64;
     void *r = W.kr[0].p, *r0 = W.kr[1].p, *p = W.kr[2].p;
@@ -923,6 +923,7 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         r0 = W.kr[1].p;
         p = W.kr[2].p;
         xk = W.xhi.p;
+        cycles = 0;
         for (int k = 0; k < nprob; k++) iters_at_escalation[k] = iters[k];
         return QCDW_OK;
     };
@@ -955,6 +956,13 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         if (!pending || lock_iters >= maxiter) break;
 
         // --- one Krylov cycle on M_hat c = rhi for the pending problems -----
+        // with inner_resume a low-precision cycle continues the previous one's recurrence if every pending
+        // problem's last cycle ended by convergence of its iterated residual; else (first cycle,
+        // breakdown, overflow, stagnation stop, FP64) it restarts from the true residual
+        bool resume = mixed && prm.inner_resume != 0 && cycles > 0;
+        for (int k = 0; k < nprob && resume; k++)
+            if (!done[k] && ctx->host_scal[k].flags != FLAG_CONV) resume = false;
+        cycles++;
         double* hc = ctx->host_d;  // [0, nprob): scales, [nprob, 2 nprob): coefficients of the x update
         std::vector<double> scale(nprob, 1.0);
         for (int k = 0; k < nprob; k++) {
@@ -964,16 +972,18 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         }
         HIPCHK(ctx, hipMemcpyAsync(dcoef, hc, 2 * nprob * sizeof(double), hipMemcpyHostToDevice, s));
         HIPCHK(ctx, launch_convert(s, F64, kprec, W.rhi.p, r, n0, 1.0, dcoef, nprob, S.map, S.nmax));
-        HIPCHK(ctx, launch_convert(s, kprec, kprec, r, r0, n0, 1.0, nullptr, nprob, S.map, S.nmax));
-        HIPCHK(ctx, launch_convert(s, kprec, kprec, r, p, n0, 1.0, nullptr, nprob, S.map, S.nmax));
+        if (!resume) {
+            HIPCHK(ctx, launch_convert(s, kprec, kprec, r, r0, n0, 1.0, nullptr, nprob, S.map, S.nmax));
+            HIPCHK(ctx, launch_convert(s, kprec, kprec, r, p, n0, 1.0, nullptr, nprob, S.map, S.nmax));
+        }
         if (mixed) {
             long total = 0;
             for (int k = 0; k < nprob; k++) total += S.len[k];
             HIPCHK(ctx, hipMemsetAsync(W.xlo.p, 0, (size_t)total * 8, s));
         }
-        HIPCHK(ctx, launch_norm2(s, kprec, r, n0, dpart, dres, nprob, S.map, S.nmax));
-        Scal* hs = ctx->host_scal;
-        memset(hs, 0, nprob * sizeof(Scal));
+        if (!resume) HIPCHK(ctx, launch_norm2(s, kprec, r, n0, dpart, dres, nprob, S.map, S.nmax));
+        Scal* hs = ctx->host_scal;  // a resumed cycle keeps the last cycle's rho, alpha, omega, r0 norm
+        if (!resume) memset(hs, 0, nprob * sizeof(Scal));
         for (int k = 0; k < nprob; k++) {
             double cycle_stop = target[k] * scale[k];
             if (mixed) cycle_stop = std::max(cycle_stop, prm.delta * std::sqrt((double)S.len[k]));
@@ -982,9 +992,17 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
             hs[k].iter = iters[k];
             hs[k].fault_iter = fault;
             hs[k].hist_len = hist_len;
+            if (resume) hs[k].flags = done[k] ? FLAG_CONV : 0;
         }
         HIPCHK(ctx, hipMemcpyAsync(dS, hs, nprob * sizeof(Scal), hipMemcpyHostToDevice, s));
-        HIPCHK(ctx, launch_bicg_init(s, dS, dres, nprob));
+        if (resume) {
+            // reliable update without restart: r is the rescaled true residual, r0, p, v and the scalars
+            // carry on (Sleijpen and van der Vorst 1996)
+            HIPCHK(ctx, launch_bicg_resume(s, kprec, r0, r, n0, dS, dpart, nprob, S.map, S.nmax));
+            HIPCHK(ctx, launch_bicg_p(s, kprec, p, r, W.kr[3].p, n0, dS, nprob, S.map, S.nmax));
+        } else {
+            HIPCHK(ctx, launch_bicg_init(s, dS, dres, nprob));
+        }
         int all_flags = 0;
         // stagnation of a low-precision cycle: no new minimum of the iterated residual for
         // STAG_ITERS iterations ends the cycle (a reliable update follows)

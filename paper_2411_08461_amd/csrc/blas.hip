@@ -249,6 +249,52 @@ __device__ __forceinline__ void sum3(const double* partials, int nb, double (&v)
     v[2] = res[2];
 }
 
+// partials ((w, r), ||r||^2) per vector of a launch
+template <class P>
+__global__ __launch_bounds__(256) void k_wdot_norm2(const void* w, const void* r, long n, double* partials,
+                                                    const long2* map)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    QCDW_VEC_RANGE(n, map)
+    QCDW_GRID_LOOP(e, nn)
+    {
+        const auto wv = P::ld(w, off + e), rv = P::ld(r, off + e);
+        acc[0] += (double)wv.re * rv.re + (double)wv.im * rv.im;
+        acc[1] += (double)wv.re * rv.im - (double)wv.im * rv.re;
+        acc[2] += (double)rv.re * rv.re + (double)rv.im * rv.im;
+    }
+    block_sum_store<3>(acc, partials + 3L * ((long)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Continue the recurrence after a reliable update that replaced r by the (rescaled) true residual:
+// rho' = (r0, r), beta = (rho' / rho)(alpha / omega) with the last step's alpha and omega, then the
+// usual p = r + beta (p - omega v).  Any rescaling of r cancels in beta (p, v and rho carry the old
+// scale together).  A near-zero rho' is a breakdown (the caller restarts).
+__global__ __launch_bounds__(256) void k_bicg_resume(Scal* S, const double* partials, int nb)
+{
+    S += blockIdx.x;
+    if (S->flags) return;
+    double v[3];
+    sum3(partials + 3L * nb * blockIdx.x, nb, v);
+    if (threadIdx.x == 0) {
+        const cx<double> rho_new = {v[0], v[1]};
+        const double rr = v[2];
+        const cx<double> omega = ld2(S->omega);
+        S->rr = rr;
+        if (!isfinite(rr) || !isfinite(rho_new.re) || !isfinite(rho_new.im)) {
+            S->flags = FLAG_NAN;
+        } else if (rr <= S->stop_rr) {
+            S->flags = FLAG_CONV;
+        } else if ((omega.re == 0.0 && omega.im == 0.0) ||
+                   sqrt(rho_new.re * rho_new.re + rho_new.im * rho_new.im) <= 1e-30 * sqrt(S->r0n2 * rr)) {
+            S->flags = FLAG_BREAK;
+        } else {
+            st2(S->beta, cdiv(rho_new, ld2(S->rho)) * cdiv(ld2(S->alpha), omega));
+            st2(S->rho, rho_new);
+        }
+    }
+}
+
 // start (or restart) from the residual r with r0 = r: rho = (r0, r) = ||r||^2
 __global__ void k_bicg_init(Scal* S, const double* rr_dev, int nrhs)
 {
@@ -438,6 +484,15 @@ hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, co
 hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nrhs)
 {
     hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(64), 0, s, S, rr_dev, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_resume(hipStream_t s, int prec, const void* r0, const void* r, long n, Scal* S,
+                              double* partials, int nrhs, const long2* map, long nmax)
+{
+    const int nb = blas_blocks(map ? nmax : n);
+    QCDW_DISPATCH1(prec, k_wdot_norm2, dim3(nb, nrhs), dim3(256), 0, s, r0, r, n, partials, map)
+    hipLaunchKernelGGL(k_bicg_resume, dim3(nrhs), dim3(256), 0, s, S, partials, nb);
     return hipGetLastError();
 }
 

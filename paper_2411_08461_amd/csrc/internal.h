@@ -148,6 +148,9 @@ hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, co
 
 // BiCGStab iteration pieces
 hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nrhs = 1);
+// rho' = (r0, r), beta from the previous step's scalars, for a cycle that continues the recurrence
+hipError_t launch_bicg_resume(hipStream_t s, int prec, const void* r0, const void* r, long n, Scal* S,
+                              double* partials, int nrhs, const long2* map, long nmax);
 hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S,
                          int nrhs = 1, const long2* map = nullptr, long nmax = 0);
 hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S,

@@ -609,3 +609,25 @@ def test_t_stepping_hop_in_solves(tmp_path, monkeypatch, nt, cg):
         op.close()
         torch.cuda.synchronize()
         c.close()
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16", "f16"])
+def test_mixed_solve_resuming_the_recurrence(ctx, inner):
+    """Reliable updates that continue the recurrence (inner_resume) reach the same oracle-checked
+    tolerance; on this well-conditioned system they need no more iterations than restarting."""
+    L = (8, 8, 8, 16)
+    U = li.random_gauge(L, 0.15, 0)
+    kappa, csw = 0.124, 1.0
+    b = li.gaussian_source(L, 1000)
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, inner)
+    its = {}
+    for resume in (False, True):
+        x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+        info = q.qcdw_invert(op, dev(b), x, q.make_params(inner=inner, delta=0.2 if inner == "f16" else 0.1,
+                                                            inner_resume=resume))
+        assert info.status == q.QCDW_OK, (resume, info)
+        assert _oracle_true_res(L, U, host(x), b, kappa, csw) <= 1e-10
+        its[resume] = info.iters
+    print(inner, its)
+    assert its[True] <= its[False]
+    op.close()
