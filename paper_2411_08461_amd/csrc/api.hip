@@ -501,7 +501,8 @@ struct Solver {
     int nprob;
     std::vector<long> off, len;  // element offsets / lengths (complex) of each problem
     long nmax;                   // longest problem
-    int nb_hop;                  // hop partials stride per problem
+    int nb_hop;                  // hop partials stride per problem (set by the hop form in use)
+    int nb_hop_cap;              // largest stride any hop form of these problems can need
     int nb_blas;                 // BLAS partials per problem
     const long2* map;            // device (off, len) per problem (batch) or nullptr (uniform)
     const int* nbs;              // device hop tiles per problem (batch) or nullptr
@@ -517,7 +518,7 @@ struct Solver {
             off = batch->off;
             len = batch->len;
             nmax = batch->nmax;
-            nb_hop = batch->nbmax;
+            nb_hop = nb_hop_cap = batch->nbmax;
             map = (const long2*)batch->map.p;
             nbs = (const int*)batch->nbs.p;
         } else {
@@ -528,6 +529,8 @@ struct Solver {
             }
             nmax = n;
             nb_hop = hop_blocks(ops[0]->g.Vh);
+            // slice-group forms launch one block per (c-tile, t), t-stepping forms fewer
+            nb_hop_cap = std::max(nb_hop, hop_ctiles(ops[0]->g) * ops[0]->g.Lt);
             map = nullptr;
             nbs = nullptr;
         }
@@ -578,6 +581,9 @@ struct Solver {
         a.nrhs = nprob;
         a.nt = nprob == 1 ? nt : 1;
         a.cgroup = nprob == 1 ? cg : 0;
+        // the reduction partials of this form must fit the workspace sized for nb_hop_cap
+        if (red != RED_NONE && nprob == 1 && hop_blocks_nt(op->g, a.nt, a.cgroup) > nb_hop_cap)
+            return hipErrorInvalidValue;
         if (nprob > 1)
             return variant == 1 ? launch_hop_rhs(st, prec, epi, red, a, S, e0, e1)
                                 : launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
@@ -777,7 +783,7 @@ struct Solver {
         HIPCHK(ctx, W.tmpo64.alloc((size_t)nmax * 16));
         for (auto& b : W.kr) HIPCHK(ctx, b.alloc((size_t)total * cplx_bytes(kprec)));
         if (kprec != F64) HIPCHK(ctx, W.xlo.alloc((size_t)total * 8));
-        const long nbmax = std::max<long>(std::max<long>(nb_blas, nb_hop), 1);
+        const long nbmax = std::max<long>(std::max<long>(nb_blas, nb_hop_cap), 1);
         HIPCHK(ctx, W.partials.alloc(3UL * nprob * nbmax * sizeof(double)));
         HIPCHK(ctx, W.scal.alloc(MAX_BATCH * sizeof(Scal)));
         HIPCHK(ctx, W.dres.alloc(MAX_BATCH * sizeof(double)));
