@@ -584,9 +584,11 @@ struct Solver {
         // the reduction partials of this form must fit the workspace sized for nb_hop_cap
         if (red != RED_NONE && nprob == 1 && hop_blocks_nt(op->g, a.nt, a.cgroup) > nb_hop_cap)
             return hipErrorInvalidValue;
-        if (nprob > 1)
-            return variant == 1 ? launch_hop_rhs(st, prec, epi, red, a, S, e0, e1)
-                                : launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
+        if (nprob > 1) {  // variant: kernel form (bit 0: 0 register loop, 1 L2 reuse) + 2 * c-tile group
+            a.cgroup = (variant & 1) ? 0 : variant >> 1;
+            return (variant & 1) ? launch_hop_rhs(st, prec, epi, red, a, S, e0, e1)
+                                 : launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
+        }
         return launch_hop(st, prec, v.recon, epi, red, a, e0, e1);
     }
 
@@ -636,14 +638,32 @@ struct Solver {
                 if (gsz < batch->total_tiles) cand.push_back(gsz);
             cand.push_back(batch->total_tiles);
         } else {
-            snprintf(key, sizeof key, "mrhs_hop/p%d/Vh%d/n%d", kprec, ops[0]->g.Vh, nprob);
+            const Geom& g = ops[0]->g;
+            snprintf(key, sizeof key, "mrhs_hop/p%d/L%dx%dx%dx%d/n%d", kprec, g.Lx, g.Ly, g.Lz, g.Lt, nprob);
             cand = {0, 1};
+            const int nct = hop_ctiles(g);
+            for (int m : {8, 16})  // register loop in slice-group order: largest divisor of nct in [4, m]
+                for (int d = std::min(m, nct - 1); d >= 4; d--)
+                    if (nct % d == 0) {
+                        if (std::find(cand.begin(), cand.end(), 2 * d) == cand.end()) cand.push_back(2 * d);
+                        break;
+                    }
         }
-        auto choose = [&](int v) { variant = v; };
+        auto choose = [&](int v) {
+            variant = v;
+            // multi-RHS register loop in slice-group order: one block per (c-tile, t)
+            if (!batch && nprob > 1)
+                nb_hop = (v & 1) == 0 && (v >> 1) > 0 ? hop_ctiles(ops[0]->g) * ops[0]->g.Lt : hop_blocks(ops[0]->g.Vh);
+        };
         auto it = ctx->tune.find(key);
-        if (it != ctx->tune.end() && std::find(cand.begin(), cand.end(), it->second) != cand.end()) {
-            choose(it->second);
-            return QCDW_OK;
+        if (it != ctx->tune.end()) {
+            const int v = it->second;
+            const bool fits = batch ? std::find(cand.begin(), cand.end(), v) != cand.end()
+                                    : (v == 0 || v == 1 || ((v & 1) == 0 && hop_cgroup_fits(ops[0]->g, v >> 1)));
+            if (fits) {
+                choose(v);
+                return QCDW_OK;
+            }
         }
         hipEvent_t e0, e1;
         HIPCHK(ctx, hipEventCreate(&e0));

@@ -1,0 +1,216 @@
+// Device helpers shared by the parity-hop kernels (single-RHS forms, multi-RHS
+// and batched): link reconstruction, the lane geometry of the four-lanes-per-site
+// decomposition, the projected hop, and the Hermitian clover rows.
+//
+// Lane q = 2 gq + k of a site handles directions mu = 2 gq and 2 gq + 1
+// (forward and backward) and only row k of the half-spinor that (1 -/+ g_mu)
+// projects onto: in the DeGrand-Rossi basis h_k = psi_k + c psi_l with a unit
+// coefficient c and l = 3 - k (mu = x, y) or 2 + k (mu = z, t); W h_k adds to
+// spin k and conj(c) W h_k to spin l (paper Sec. III.B, Eq. "clover", the
+// Wilson hopping term written out).
+#pragma once
+#include "internal.h"
+
+namespace qcdw {
+
+template <class P, int R>
+__device__ __forceinline__ void load_link(const void* gauge, long off, cx<typename P::real> (&u)[9])
+{
+    if constexpr (R == 9) {
+#pragma unroll
+        for (int e = 0; e < 9; e++) u[e] = P::ld(gauge, off + e);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 6; e++) u[e] = P::ld(gauge, off + e);
+        // third row of an SU(3) matrix: complex conjugate of row0 x row1
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+}
+
+// Rows 3h..3h+2 of a Hermitian 6x6 block times the 6-vector (own | other),
+// own = the 3 entries of this lane's spin.  `win` holds the lane's 27-real
+// window of the reordered packing:
+//   [d0 d1 d2 | L10 L20 L21 | L30 L31 L32 L40 L41 L42 L50 L51 L52 | d3 d4 d5 | L43 L53 L54]
+//   half 0 reads entries 0..26, half 1 reads entries 9..35.
+template <typename T>
+__device__ __forceinline__ void herm_rows(const T (&win)[27], int h, const cx<T> (&vo)[3], const cx<T> (&vx)[3],
+                                          cx<T> (&out)[3])
+{
+    T d[3], lo[6], Xr[9], Xi[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++) d[i] = h ? win[18 + i] : win[i];
+#pragma unroll
+    for (int i = 0; i < 6; i++) lo[i] = h ? win[21 + i] : win[3 + i];
+#pragma unroll
+    for (int m = 0; m < 9; m++) {
+        Xr[m] = h ? win[2 * m] : win[9 + 2 * m];
+        Xi[m] = h ? win[2 * m + 1] : win[10 + 2 * m];
+    }
+    const cx<T> l10 = {lo[0], lo[1]}, l20 = {lo[2], lo[3]}, l21 = {lo[4], lo[5]};
+    cx<T> own[3][3];
+    own[0][0] = {d[0], T(0)};
+    own[1][1] = {d[1], T(0)};
+    own[2][2] = {d[2], T(0)};
+    own[1][0] = l10;
+    own[2][0] = l20;
+    own[2][1] = l21;
+    own[0][1] = conj(l10);
+    own[0][2] = conj(l20);
+    own[1][2] = conj(l21);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        cx<T> s = {T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b < 3; b++) s = s + own[a][b] * vo[b];
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            // cross block: rows of this half, columns of the other half
+            cx<T> cb = h ? cx<T>{Xr[3 * a + b], Xi[3 * a + b]} : cx<T>{Xr[3 * b + a], -Xi[3 * b + a]};
+            s = s + cb * vx[b];
+        }
+        out[a] = s;
+    }
+}
+
+// lane q's 27-entry window: chirality q >> 1, entries 9 (q & 1) .. 9 (q & 1) + 26
+template <class P>
+__device__ __forceinline__ void load_window(const void* clov, long Vh, int site, int q, typename P::real (&win)[27])
+{
+    const long base = clov_index(site, q >> 1, 9 * (q & 1));
+#pragma unroll
+    for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + (long)e * CLOV_STRIDE);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src)
+{
+    return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
+{
+    return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
+}
+
+// The four hops of one lane at one site: neighbour indices (input parity), link
+// offsets, projection coefficients and time-boundary signs.  Hop h = 2 j + dir,
+// mu = 2 gq + j, dir 0 forward / 1 backward.
+template <typename T, int R>
+struct LaneHops {
+    int nbh[4];
+    long loff[4];
+    T cre[4], cim[4], fsg[4];
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q, LaneHops<T, R>& L)
+{
+    const int gq = q >> 1, k = q & 1;
+    const long Vh = g.Vh;
+    int x, y, z, t;
+    site_coords(g, site, p, x, y, z, t);
+    const int xh = site % g.Lxh;
+    const int Sy = g.Lxh, Sz = g.Lxh * g.Ly, St = g.Lxh * g.Ly * g.Lz;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const int mu = 2 * gq + j;
+        int fwd, bwd;
+        bool fcross = false, bcross = false;
+        T c_re, c_im;  // projection coefficient of the forward hop
+        if (j == 0) {
+            if (gq == 0) {  // x: the neighbour lies in the same row of the other parity
+                const int row = site - xh;
+                const int xp = (x + 1 == g.Lx) ? 0 : x + 1;
+                const int xm = (x == 0) ? g.Lx - 1 : x - 1;
+                fwd = row + (xp >> 1);
+                bwd = row + (xm >> 1);
+                c_re = T(0);
+                c_im = T(-1);
+            } else {  // z
+                fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
+                bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
+                c_re = T(0);
+                c_im = k == 0 ? T(-1) : T(1);
+            }
+        } else {
+            if (gq == 0) {  // y
+                fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
+                bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
+                c_re = k == 0 ? T(1) : T(-1);
+                c_im = T(0);
+            } else {  // t
+                fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
+                bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
+                fcross = (t + 1 == g.Lt);
+                bcross = (t == 0);
+                c_re = T(-1);
+                c_im = T(0);
+            }
+        }
+        // forward: U_mu(x) psi(x+mu) with (1 - g_mu); backward: U_mu(x-mu)^+ psi(x-mu)
+        // with (1 + g_mu), which flips the projection coefficient
+        L.nbh[2 * j] = fwd;
+        L.nbh[2 * j + 1] = bwd;
+        L.loff[2 * j] = ((long)(mu * 2 + p) * Vh + site) * R;
+        L.loff[2 * j + 1] = ((long)(mu * 2 + (1 - p)) * Vh + bwd) * R;
+        L.cre[2 * j] = c_re;
+        L.cim[2 * j] = c_im;
+        L.cre[2 * j + 1] = -c_re;
+        L.cim[2 * j + 1] = -c_im;
+        L.fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
+        L.fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
+    }
+}
+
+// the two spins (su, sl) of neighbour nb that this lane's row of the projection needs
+template <class P>
+__device__ __forceinline__ void load_pair(const void* psi, long Vh, int su, int sl, int nb,
+                                          cx<typename P::real> (&pu)[3], cx<typename P::real> (&pl)[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        pu[c] = P::ld(psi, ((long)su * Vh + nb) * 3 + c);
+        pl[c] = P::ld(psi, ((long)sl * Vh + nb) * 3 + c);
+    }
+}
+
+// W h for hop h with the projected row hv, accumulated into the two output spins
+template <class P, int R>
+__device__ __forceinline__ void hop_apply(const void* gauge, const LaneHops<typename P::real, R>& L, int h,
+                                          const cx<typename P::real> (&hv)[3], cx<typename P::real> (&acc_u)[3],
+                                          cx<typename P::real> (&acc_l)[3])
+{
+    using T = typename P::real;
+    const int dir = h & 1;
+    cx<T> u[9];
+    load_link<P, R>(gauge, L.loff[h], u);
+    cx<T> w[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        cx<T> sacc = {T(0), T(0)};
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            sacc = dir == 0 ? sacc + u[3 * r + c] * hv[c] : sacc + cmul_conj(u[3 * c + r], hv[c]);
+        w[r] = sacc;
+    }
+    const cx<T> cd = conj(cx<T>{L.cre[h], L.cim[h]});
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        const cx<T> wr = L.fsg[h] * w[r];
+        acc_u[r] = acc_u[r] + wr;
+        acc_l[r] = acc_l[r] + cd * wr;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void project(const cx<T> (&pu)[3], const cx<T> (&pl)[3], T cr, T ci, cx<T> (&hv)[3])
+{
+    const cx<T> cc = {cr, ci};
+#pragma unroll
+    for (int c = 0; c < 3; c++) hv[c] = pu[c] + cc * pl[c];
+}
+
+
+}  // namespace qcdw

@@ -4,63 +4,19 @@
 // and its clover window once and applies them to every right-hand side in a
 // register-resident loop, so link and clover bytes are paid once per site for
 // all RHS.  RHS k of a field lives at offset k * 12 * Vh complex (a stack of
-// single-RHS fields), and RHS whose solver flag is set are skipped.
+// single-RHS fields), and RHS whose solver flag is set are skipped.  With
+// cgroup > 0 the tiles follow the slice-group order of the single-RHS hop.
 #include <hip/hip_ext.h>
 
-#include "internal.h"
+#include "hop_common.h"
+
+// right-hand sides processed together per loop step (their neighbour loads in flight together); two
+// per step were measured 1.5x slower at 24^3x64 (the doubled accumulators push the kernel to 256 VGPRs)
+#ifndef QCDW_MRHS_STEP
+#define QCDW_MRHS_STEP 1
+#endif
 
 namespace qcdw {
-
-template <typename T>
-__device__ __forceinline__ cx<T> mshfl(cx<T> v, int src)
-{
-    return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
-}
-template <typename T>
-__device__ __forceinline__ cx<T> mshfl_xor(cx<T> v, int m)
-{
-    return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
-}
-
-// rows 3h..3h+2 of the Hermitian block times (own | other); window layout as in hop.hip
-template <typename T>
-__device__ __forceinline__ void mrhs_herm_rows(const T (&win)[27], int h, const cx<T> (&vo)[3], const cx<T> (&vx)[3],
-                                               cx<T> (&out)[3])
-{
-    T d[3], lo[6], Xr[9], Xi[9];
-#pragma unroll
-    for (int i = 0; i < 3; i++) d[i] = h ? win[18 + i] : win[i];
-#pragma unroll
-    for (int i = 0; i < 6; i++) lo[i] = h ? win[21 + i] : win[3 + i];
-#pragma unroll
-    for (int m = 0; m < 9; m++) {
-        Xr[m] = h ? win[2 * m] : win[9 + 2 * m];
-        Xi[m] = h ? win[2 * m + 1] : win[10 + 2 * m];
-    }
-    const cx<T> l10 = {lo[0], lo[1]}, l20 = {lo[2], lo[3]}, l21 = {lo[4], lo[5]};
-    cx<T> own[3][3];
-    own[0][0] = {d[0], T(0)};
-    own[1][1] = {d[1], T(0)};
-    own[2][2] = {d[2], T(0)};
-    own[1][0] = l10;
-    own[2][0] = l20;
-    own[2][1] = l21;
-    own[0][1] = conj(l10);
-    own[0][2] = conj(l20);
-    own[1][2] = conj(l21);
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        cx<T> s = {T(0), T(0)};
-#pragma unroll
-        for (int b = 0; b < 3; b++) s = s + own[a][b] * vo[b];
-#pragma unroll
-        for (int b = 0; b < 3; b++) {
-            cx<T> cb = h ? cx<T>{Xr[3 * a + b], Xi[3 * a + b]} : cx<T>{Xr[3 * b + a], -Xi[3 * b + a]};
-            s = s + cb * vx[b];
-        }
-        out[a] = s;
-    }
-}
 
 template <class P, int EPI, int RED>
 __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
@@ -70,137 +26,110 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int nblk = gridDim.x;
     const int q = threadIdx.x & 3;
-    const int site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
-    const bool valid = site < g.Vh;
+    int site;
+    bool valid;
+    if (a.cgroup > 0) {  // slice-group order, as in the single-RHS hop_kernel
+        const int G = a.cgroup, St = g.Lxh * g.Ly * g.Lz;
+        const int grp = tile / (G * g.Lt), rr = tile - grp * G * g.Lt;
+        const int t = rr / G, ct = grp * G + (rr - t * G);
+        const int c = ct * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
+        site = t * St + c;
+        valid = c < St;
+    } else {
+        site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
+        valid = site < g.Vh;
+    }
     const int gq = q >> 1, k = q & 1;
-    const int p = a.parity;
     const long Vh = g.Vh;
     const long field = 12L * Vh;  // complex per RHS
     const int lane = threadIdx.x & 63;
-    const int src = (lane & ~3) + (q < 2 ? q + 2 : 3 - q);
-
-    // per-lane hop geometry, raw links and clover window (loaded once for all RHS)
-    int nbh[4] = {0, 0, 0, 0};
-    T cre[4], cim[4], fsg[4];
-    cx<T> ur[4][6];
-    T win[27];
+    const int src = (lane & ~3) + (q < 2 ? q + 2 : 3 - q);  // in-quad partner finishing the other spin
     const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
+
+    // per-lane hop geometry, links (row 2 rebuilt once) and clover window, shared by all RHS
+    LaneHops<T, 6> L;
+    cx<T> ur[4][9];
+    T win[27];
 #pragma unroll
     for (int h = 0; h < 4; h++) {
-        cre[h] = cim[h] = T(0);
-        fsg[h] = T(1);
+        L.nbh[h] = 0;
+        L.loff[h] = 0;
+        L.cre[h] = L.cim[h] = T(0);
+        L.fsg[h] = T(1);
 #pragma unroll
-        for (int e = 0; e < 6; e++) ur[h][e] = {T(0), T(0)};
+        for (int e = 0; e < 9; e++) ur[h][e] = {T(0), T(0)};
     }
 #pragma unroll
     for (int e = 0; e < 27; e++) win[e] = T(0);
     if (valid) {
-        int x, y, z, t;
-        site_coords(g, site, p, x, y, z, t);
-        const int xh = site % g.Lxh;
-        const int Sy = g.Lxh, Sz = g.Lxh * g.Ly, St = g.Lxh * g.Ly * g.Lz;
+        lane_hops<T, 6>(g, site, a.parity, q, L);
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int mu = 2 * gq + j;
-            int fwd, bwd;
-            bool fcross = false, bcross = false;
-            T c_re, c_im;
-            if (j == 0) {
-                if (gq == 0) {
-                    const int row = site - xh;
-                    const int xp = (x + 1 == g.Lx) ? 0 : x + 1;
-                    const int xm = (x == 0) ? g.Lx - 1 : x - 1;
-                    fwd = row + (xp >> 1);
-                    bwd = row + (xm >> 1);
-                    c_re = T(0);
-                    c_im = T(-1);
-                } else {
-                    fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
-                    bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
-                    c_re = T(0);
-                    c_im = k == 0 ? T(-1) : T(1);
-                }
-            } else {
-                if (gq == 0) {
-                    fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
-                    bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
-                    c_re = k == 0 ? T(1) : T(-1);
-                    c_im = T(0);
-                } else {
-                    fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
-                    bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
-                    fcross = (t + 1 == g.Lt);
-                    bcross = (t == 0);
-                    c_re = T(-1);
-                    c_im = T(0);
-                }
-            }
-            nbh[2 * j] = fwd;
-            nbh[2 * j + 1] = bwd;
-            const long lf = ((long)(mu * 2 + p) * Vh + site) * 6;
-            const long lb = ((long)(mu * 2 + (1 - p)) * Vh + bwd) * 6;
-#pragma unroll
-            for (int e = 0; e < 6; e++) {
-                ur[2 * j][e] = P::ld(a.gauge, lf + e);
-                ur[2 * j + 1][e] = P::ld(a.gauge, lb + e);
-            }
-            cre[2 * j] = c_re;
-            cim[2 * j] = c_im;
-            cre[2 * j + 1] = -c_re;
-            cim[2 * j + 1] = -c_im;
-            fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
-            fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
-        }
-        if constexpr (EPI != EPI_NONE) {
-            const long base = clov_index(site, q >> 1, 9 * (q & 1));
-#pragma unroll
-            for (int e = 0; e < 27; e++) win[e] = P::ldr(a.clov, base + (long)e * CLOV_STRIDE);
-        }
+        for (int h = 0; h < 4; h++) load_link<P, 6>(a.gauge, L.loff[h], ur[h]);
+        if constexpr (EPI != EPI_NONE) load_window<P>(a.clov, Vh, site, q, win);
     }
 
-    for (int r = 0; r < a.nrhs; r++) {
-        if (S && S[r].flags) continue;  // uniform: every thread reads the same flag
-        const long off = (long)r * field;
-        cx<T> acc_u[3], acc_l[3];
+    // right-hand sides in groups of QCDW_MRHS_STEP, so that their neighbour loads are in flight together
+    constexpr int RS = QCDW_MRHS_STEP;
+    for (int r0 = 0; r0 < a.nrhs; r0 += RS) {
+        bool act[RS];
 #pragma unroll
-        for (int c = 0; c < 3; c++) acc_u[c] = acc_l[c] = {T(0), T(0)};
+        for (int j = 0; j < RS; j++)  // uniform: every thread reads the same flags
+            act[j] = r0 + j < a.nrhs && !(S && S[r0 + j].flags);
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < RS; j++) any = any || act[j];
+        if (!any) continue;
+        cx<T> acc2_u[RS][3], acc2_l[RS][3];
+#pragma unroll
+        for (int j = 0; j < RS; j++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc2_u[j][c] = acc2_l[j][c] = {T(0), T(0)};
         if (valid) {
 #pragma unroll
             for (int h = 0; h < 4; h++) {
+                cx<T> hv[RS][3];
+#pragma unroll
+                for (int j = 0; j < RS; j++) {
+                    cx<T> pu[3], pl[3];
+                    if (act[j]) {
+                        load_pair<P>((const char*)a.psi + (long)(r0 + j) * field * P::cbytes, Vh, su, sl, L.nbh[h],
+                                     pu, pl);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 3; c++) pu[c] = pl[c] = {T(0), T(0)};
+                    }
+                    project(pu, pl, L.cre[h], L.cim[h], hv[j]);
+                }
                 const int dir = h & 1;
-                const cx<T> cc = {cre[h], cim[h]};
-                cx<T> u[9];
+                const cx<T> cd = conj(cx<T>{L.cre[h], L.cim[h]});
 #pragma unroll
-                for (int e = 0; e < 6; e++) u[e] = ur[h][e];
-                u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-                u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-                u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-                cx<T> hv[3];
+                for (int j = 0; j < RS; j++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const cx<T> pu = P::ld(a.psi, off + ((long)su * Vh + nbh[h]) * 3 + c);
-                    const cx<T> pl = P::ld(a.psi, off + ((long)sl * Vh + nbh[h]) * 3 + c);
-                    hv[c] = pu + cc * pl;
-                }
-                const cx<T> cd = conj(cc);
+                    for (int rr = 0; rr < 3; rr++) {
+                        cx<T> sacc = {T(0), T(0)};
 #pragma unroll
-                for (int rr = 0; rr < 3; rr++) {
-                    cx<T> sacc = {T(0), T(0)};
-#pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        sacc = dir == 0 ? sacc + u[3 * rr + c] * hv[c] : sacc + cmul_conj(u[3 * c + rr], hv[c]);
-                    const cx<T> wr = fsg[h] * sacc;
-                    acc_u[rr] = acc_u[rr] + wr;
-                    acc_l[rr] = acc_l[rr] + cd * wr;
-                }
+                        for (int c = 0; c < 3; c++)
+                            sacc = dir == 0 ? sacc + ur[h][3 * rr + c] * hv[j][c]
+                                            : sacc + cmul_conj(ur[h][3 * c + rr], hv[j][c]);
+                        const cx<T> wr = L.fsg[h] * sacc;
+                        acc2_u[j][rr] = acc2_u[j][rr] + wr;
+                        acc2_l[j][rr] = acc2_l[j][rr] + cd * wr;
+                    }
             }
         }
+#pragma unroll
+        for (int j = 0; j < RS; j++) {
+        if (!act[j]) continue;
+        const int r = r0 + j;
+        const long off = (long)r * field;
+        const cx<T>(&acc_u)[3] = acc2_u[j];
+        const cx<T>(&acc_l)[3] = acc2_l[j];
         cx<T> res[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             const cx<T> mine = gq == 0 ? acc_u[c] : acc_l[c];
             const cx<T> theirs = gq == 0 ? acc_l[c] : acc_u[c];
-            res[c] = mine + mshfl(theirs, src);
+            res[c] = mine + shfl_cx(theirs, src);
         }
         cx<T> outv[3], yv[3];
         if constexpr (EPI == EPI_CLOV_XPAY || RED == RED_TS) {
@@ -214,8 +143,8 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
         } else {
             cx<T> ox[3], br[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) ox[c] = mshfl_xor(res[c], 1);
-            mrhs_herm_rows(win, q & 1, res, ox, br);
+            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
+            herm_rows(win, q & 1, res, ox, br);
             const T aa = (T)a.a;
 #pragma unroll
             for (int c = 0; c < 3; c++) outv[c] = (EPI == EPI_CLOV) ? br[c] : yv[c] - aa * br[c];
@@ -246,6 +175,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
             block_sum_store<3>(v, a.partials + 3 * ((long)r * nblk + tile));
             __syncthreads();  // the block reduction's shared buffer is reused for the next RHS
         }
+        }
     }
 }
 
@@ -253,7 +183,7 @@ template <class P>
 static hipError_t launch_mrhs_p(hipStream_t s, int epi, int red, const HopArgs& a, const Scal* S, hipEvent_t e0,
                                 hipEvent_t e1)
 {
-    dim3 grid(hop_blocks(a.g.Vh)), block(256);
+    dim3 grid(a.cgroup > 0 ? hop_ctiles(a.g) * a.g.Lt : hop_blocks(a.g.Vh)), block(256);
 #define QCDW_MRHS_CASE(E, D)                                                                     \
     if (epi == E && red == D) {                                                                 \
         if (e0)                                                                                 \
