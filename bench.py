@@ -296,8 +296,8 @@ def hop_kernel_name(form):
     return f"hop_tkernel<P64, r12, EPI_CLOV, RED_NONE, {nt}>" + (f" (slice groups of {cg} c-tiles)" if cg else "")
 
 
-KERNEL_SOURCES = ("paper_2411_08461_amd/csrc/hop.hip", "paper_2411_08461_amd/csrc/dev.h",
-                  "paper_2411_08461_amd/csrc/internal.h")
+KERNEL_SOURCES = ("paper_2411_08461_amd/csrc/hop.hip", "paper_2411_08461_amd/csrc/hop_common.h",
+                  "paper_2411_08461_amd/csrc/dev.h", "paper_2411_08461_amd/csrc/internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_wc16x32_traffic.md")
 
 

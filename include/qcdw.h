@@ -251,12 +251,6 @@ qcdw_status qcdw_net_loss_grad(qcdw_net *net, int npairs, const void *const r_e[
    seeded shuffled order; loss_hist (host, `steps` entries or NULL) receives each batch's mean loss. */
 qcdw_status qcdw_net_train(qcdw_net *net, int npairs, const void *const r_e[], const void *const e_e[], int steps,
                            int batch, double lr, uint64_t seed, double *loss_hist);
-/* Flexible GMRES(m) (Saad 1993, m = params->gmres_restart) on the even-odd system with right
-   preconditioning z = P(v) (net may be NULL: no preconditioner), block classical Gram-Schmidt
-   with one reorthogonalisation.  With params->gmres_fallback, a restart cycle that reduces the
-   residual by less than 10 % hands the solve to BiCGStab in the operator's inner precision from
-   the current iterate.  The final acceptance is the FP64 true residual of the full system, as
-   for qcdw_invert. */
 /* Solver-generated training pairs for the net: x* from an FP64 solve of M x = b to 1e-12; the
    iterates x_k of FP64 BiCGStab restarted every `stride` iterations from zero, k = 1..npairs;
    e_k = (x* - x_k) on even sites and r_k = M_hat e_k, both scaled so that ||r_k|| = 1.
@@ -266,6 +260,15 @@ qcdw_status qcdw_net_train(qcdw_net *net, int npairs, const void *const r_e[], c
    *made receives the number of pairs written (fewer than npairs if the iteration converged). */
 qcdw_status qcdw_make_training_pairs(qcdw_op *op, const void *b, int npairs, int stride, void *const r_e[],
                                      void *const e_e[], int *made);
+/* Flexible GMRES(m) (Saad 1993, m = params->gmres_restart) on the even-odd system with right
+   preconditioning z = P(v) (net may be NULL: no preconditioner; the net is applied with BF16
+   hidden activations), block classical Gram-Schmidt applied twice (a single pass with a
+   conditional second one was measured to need the second pass at almost every step, at the
+   cost of a second host synchronisation).  With params->gmres_fallback, a restart cycle that reduces the residual by less
+   than 10 % hands the solve to BiCGStab in the operator's inner precision from the current
+   iterate.  The final acceptance is the FP64 true residual of the full system, as for
+   qcdw_invert.  b, x: full fermion fields as for qcdw_invert (x: initial guess in, solution out).
+   Returns OK, ENOCONV (x holds the best iterate), ENAN, or EINVAL/ENOMEM/EHIP. */
 qcdw_status qcdw_invert_fgmres(qcdw_op *op, qcdw_net *net, const void *b, void *x, const qcdw_solver_params *params,
                                qcdw_solve_info *info);
 
