@@ -525,6 +525,18 @@ def learned(q, li, np, torch, ctx, fields, args):
     prev.close()
     torch.cuda.empty_cache()
     b = torch.from_numpy(li.gaussian_source(L, w["source_seed"])).cuda()
+    # hop bandwidth on this lattice (the largest of the workloads): a capped solve, every hop timed
+    Vh = int(np.prod(L)) // 2
+    out["hop_gbs"] = {"lattice": list(L)}
+    for prec in ("f64", "bf16"):
+        xt = torch.zeros_like(b)
+        ti = q.qcdw_invert(op, b, xt, q.make_params(tol=1e-10, maxiter=24, inner=prec, collect_timing=True,
+                                                    check_every=8))
+        ms = ti.hop_ms[0] / max(ti.n_hop[0], 1)
+        gbs = hop_a_bytes(prec) * Vh / (ms * 1e-3) / 1e9
+        out["hop_gbs"][prec] = {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                "avg_launch_us": round(ms * 1e3, 1), "form": q.qcdw_op_hop_form(op, prec)}
+    del xt
     out["training"] = {"fields": len(losses), "pairs": 32 * len(losses), "steps": 40 * len(losses),
                        "time_s": round(t_train, 2), "loss_first_field": [round(v, 4) for v in losses[0]],
                        "loss_last_field": [round(v, 4) for v in losses[-1]]}
