@@ -57,6 +57,7 @@ void qcdw_ctx_destroy(qcdw_ctx* ctx)
     if (ctx->host_d) (void)hipHostFree(ctx->host_d);
     if (ctx->dev_int) (void)hipFree(ctx->dev_int);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    block_cache().trim(ctx->device);
     delete ctx;
 }
 
@@ -305,11 +306,12 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
     op->inner = inner;
     op->recon = recon;
     auto cleanup = [&](qcdw_status st) {
+        (void)hipStreamSynchronize(s);  // before the blocks return to the cache
         delete op;
         return st;
     };
     const int R = recon == 18 ? 9 : 6;
-    DevBuf clov, inv, Ap;
+    PoolBuf clov, inv, Ap;  // released after the stream synchronisation below (or in cleanup)
     if (op->gauge64.alloc(8UL * g.Vh * R * 16) != hipSuccess || clov.alloc(144UL * g.Vh * 8) != hipSuccess ||
         inv.alloc(144UL * g.Vh * 8) != hipSuccess || Ap.alloc(144UL * g.Vh * 8) != hipSuccess)
         return cleanup(fail(ctx, QCDW_ENOMEM, "out of device memory creating the operator"));
@@ -509,6 +511,7 @@ struct Solver {
     int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse), batch grid, or
                                  // single-RHS sites per thread along t
     int nt = 1, cg = 0;          // single-RHS hop: sites per thread along t, c-tile group
+    int fuse_nb;                 // largest partials count whose scalar is formed in the vector kernel
     Timing tm;
 
     Solver(qcdw_ctx* c, Workspace& w, std::vector<qcdw_op*> o, qcdw_batch* b)
@@ -535,8 +538,13 @@ struct Solver {
             nbs = nullptr;
         }
         nb_blas = blas_blocks(nmax);
+        const char* f = getenv("QCDW_FUSE_NB");
+        fuse_nb = f && *f ? atoi(f) : 2048;
     }
     long n0() const { return len[0]; }  // uniform length (multi-RHS)
+    // partials per problem in each of the two regions of W.partials (hop or vector reductions, then
+    // the x/r update's own)
+    long part_stride() const { return std::max<long>(std::max<long>(nb_blas, nb_hop_cap), 1); }
 
     void* at(const DevBuf& b, int k) const { return (char*)b.p + (size_t)off[k] * 16; }
 
@@ -601,20 +609,28 @@ struct Solver {
              *tmpo = W.kr[6].p;
         Scal* dS = (Scal*)W.scal.p;
         double* dpart = (double*)W.partials.p;
+        double* dpart2 = dpart + 3L * nprob * part_stride();  // partials of the x/r update
+        double* hist = (double*)W.hist.p;
         const long n = n0();
+        // a scalar is formed inside the vector kernel that uses it when its partials are few (every
+        // block of that kernel sums them), else by a single-block kernel in between
+        const bool fh = nb_hop <= fuse_nb, fb = nb_blas <= fuse_nb;
         hipError_t e = hipSuccess;
         for (int i = 0; i < nit && e == hipSuccess; i++) {
             e = hop(st, kprec, EPI_CLOV, RED_NONE, p, tmpo, nullptr, nullptr, nullptr, dS, 1);
             if (e == hipSuccess) e = hop(st, kprec, EPI_CLOV_XPAY, RED_WDOT, tmpo, vv, p, r0, dpart, dS, 0);
-            if (e == hipSuccess) e = launch_fin_alpha(st, dS, dpart, nb_hop, nprob, nbs);
-            if (e == hipSuccess) e = launch_bicg_s(st, kprec, sv, r, vv, n, dS, nprob, map, nmax);
+            if (e == hipSuccess && !fh) e = launch_fin_alpha(st, dS, dpart, nb_hop, nprob, nbs);
+            if (e == hipSuccess)
+                e = launch_bicg_s(st, kprec, sv, r, vv, n, dS, nprob, map, nmax, fh ? dpart : nullptr, nb_hop, nbs);
             if (e == hipSuccess) e = hop(st, kprec, EPI_CLOV, RED_NONE, sv, tmpo, nullptr, nullptr, nullptr, dS, 1);
             if (e == hipSuccess) e = hop(st, kprec, EPI_CLOV_XPAY, RED_TS, tmpo, t, sv, nullptr, dpart, dS, 0);
-            if (e == hipSuccess) e = launch_fin_omega(st, dS, dpart, nb_hop, nprob, nbs);
+            if (e == hipSuccess && !fh) e = launch_fin_omega(st, dS, dpart, nb_hop, nprob, nbs);
             if (e == hipSuccess)
-                e = launch_bicg_xr(st, kprec, xprec, xk, p, sv, r, t, r0, n, dS, dpart, nprob, map, nmax);
-            if (e == hipSuccess) e = launch_fin_beta(st, dS, dpart, nb_blas, (double*)W.hist.p, nprob);
-            if (e == hipSuccess) e = launch_bicg_p(st, kprec, p, r, vv, n, dS, nprob, map, nmax);
+                e = launch_bicg_xr(st, kprec, xprec, xk, p, sv, r, t, r0, n, dS, dpart2, nprob, map, nmax,
+                                   fh ? dpart : nullptr, nb_hop, nbs);
+            if (e == hipSuccess && !fb) e = launch_fin_beta(st, dS, dpart2, nb_blas, hist, nprob);
+            if (e == hipSuccess)
+                e = launch_bicg_p(st, kprec, p, r, vv, n, dS, nprob, map, nmax, fb ? dpart2 : nullptr, nb_blas, hist);
         }
         return e;
     }
@@ -711,7 +727,8 @@ struct Solver {
         }
         Workspace::Graph* gr = nullptr;
         for (auto& c : W.graphs)
-            if (c.kprec == kprec && c.chunk == nit && c.nprob == nprob && c.variant == variant && c.gen == W.ws_gen)
+            if (c.kprec == kprec && c.chunk == nit && c.nprob == nprob && c.variant == variant && c.gen == W.ws_gen &&
+                c.fuse_nb == fuse_nb)
                 gr = &c;
         if (!gr) {
             W.graphs.emplace_back();
@@ -721,6 +738,7 @@ struct Solver {
             gr->nprob = nprob;
             gr->variant = variant;
             gr->gen = W.ws_gen;
+            gr->fuse_nb = fuse_nb;
             hipStream_t cs = ctx->cap_stream;
             HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             hipError_t e = enqueue_iters(cs, nit, kprec, xprec, xk);
@@ -803,8 +821,7 @@ struct Solver {
         HIPCHK(ctx, W.tmpo64.alloc((size_t)nmax * 16));
         for (auto& b : W.kr) HIPCHK(ctx, b.alloc((size_t)total * cplx_bytes(kprec)));
         if (kprec != F64) HIPCHK(ctx, W.xlo.alloc((size_t)total * 8));
-        const long nbmax = std::max<long>(std::max<long>(nb_blas, nb_hop_cap), 1);
-        HIPCHK(ctx, W.partials.alloc(3UL * nprob * nbmax * sizeof(double)));
+        HIPCHK(ctx, W.partials.alloc(2 * 3UL * nprob * part_stride() * sizeof(double)));
         HIPCHK(ctx, W.scal.alloc(MAX_BATCH * sizeof(Scal)));
         HIPCHK(ctx, W.dres.alloc(MAX_BATCH * sizeof(double)));
         HIPCHK(ctx, W.coef.alloc(2 * MAX_BATCH * sizeof(double)));

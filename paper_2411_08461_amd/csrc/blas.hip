@@ -168,54 +168,208 @@ __device__ __forceinline__ void st2(double* p, cx<double> v)
     p[1] = v.im;
 }
 
+// fixed-order sum of nb x 3 partials, result in every thread of the block (all threads must call it).
+// Four rows per thread are loaded before they are added, so the loads overlap.
+__device__ __forceinline__ void sum3(const double* partials, int nb, double (&v)[3])
+{
+    __shared__ double res[3];
+    v[0] = v[1] = v[2] = 0.0;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * 256) {
+        double t[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int b = b0 + u * 256;
+#pragma unroll
+            for (int k = 0; k < 3; k++) t[u][k] = b < nb ? partials[3L * b + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) v[k] += t[u][k];
+    }
+    block_sum_store<3>(v, res);
+    __syncthreads();
+    v[0] = res[0];
+    v[1] = res[1];
+    v[2] = res[2];
+}
+
+// The three scalar steps of a BiCGStab iteration.  Each one turns the summed reduction partials v
+// into the next scalar (or a flag), and a matching record step writes it to the problem's S.  A
+// single-block kernel runs step and record back to back; a fused vector kernel runs the step in
+// every block (same partials, same order: the same value everywhere) and block 0 of each problem
+// records it.  Block 0 writes the flags only when its step sets one, and then every block's step
+// sets the same one, so a block that reads the flags while they change leaves all the same.  A step
+// reads only fields of S that no block writes in the same launch:
+//   alpha step reads rho, r0n2, rr         records alpha, rho_prev (= rho), flags
+//   omega step reads nothing               records omega, iter (+1), flags
+//   beta  step reads rho_prev, alpha,      records beta, rho, rr, history, flags
+//              omega, iter, r0n2, stop_rr, fault_iter
+// alpha = rho / (r0, v) with v = M p; v holds ((r0, v), -)
+__device__ __forceinline__ int alpha_step(const Scal* S, const double (&v)[3], cx<double>& alpha)
+{
+    const cx<double> rv = {v[0], v[1]};
+    const double arv = sqrt(rv.re * rv.re + rv.im * rv.im);
+    if (!isfinite(arv)) return FLAG_NAN;
+    if (arv <= 1e-30 * sqrt(S->r0n2 * S->rr)) return FLAG_BREAK;
+    alpha = cdiv(ld2(S->rho), rv);
+    return 0;
+}
+__device__ __forceinline__ void alpha_record(Scal* S, int flag, cx<double> alpha)
+{
+    if (flag) {
+        S->flags = flag;
+        return;
+    }
+    st2(S->alpha, alpha);
+    st2(S->rho_prev, ld2(S->rho));
+}
+
+// omega = (t, s) / (t, t) with t = M s; v holds ((t, s), ||t||^2).  s = 0 gives omega = 0: x + alpha p
+// is then exact and the beta step flags the breakdown unless the residual has converged.
+__device__ __forceinline__ int omega_step(const double (&v)[3], cx<double>& omega)
+{
+    const double tt = v[2];
+    if (!isfinite(tt) || !isfinite(v[0]) || !isfinite(v[1])) return FLAG_NAN;
+    omega = tt == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{v[0] / tt, v[1] / tt};
+    return 0;
+}
+__device__ __forceinline__ void omega_record(Scal* S, int flag, cx<double> omega)
+{
+    if (flag) {
+        S->flags = flag;
+        return;
+    }
+    st2(S->omega, omega);
+    S->iter = S->iter + 1;
+}
+
+// rho' = (r0, r), beta = (rho' / rho)(alpha / omega); v holds ((r0, r), ||r||^2) of the new residual
+__device__ __forceinline__ int beta_step(const Scal* S, const double (&v)[3], cx<double>& beta)
+{
+    const cx<double> rho_new = {v[0], v[1]};
+    const double rr = v[2];
+    const int it = S->iter;
+    const cx<double> omega = ld2(S->omega);
+    if (!isfinite(rr) || !isfinite(rho_new.re) || !isfinite(rho_new.im) ||
+        (S->fault_iter < 0 && it == -S->fault_iter))
+        return FLAG_NAN;
+    if (rr <= S->stop_rr) return FLAG_CONV;
+    if (omega.re == 0.0 && omega.im == 0.0) return FLAG_BREAK;
+    if (sqrt(rho_new.re * rho_new.re + rho_new.im * rho_new.im) <= 1e-30 * sqrt(S->r0n2 * rr)) return FLAG_BREAK;
+    if (S->fault_iter > 0 && it == S->fault_iter) return FLAG_BREAK;
+    beta = cdiv(rho_new, ld2(S->rho_prev)) * cdiv(ld2(S->alpha), omega);
+    return 0;
+}
+// hist: the problem's residual history (or nullptr)
+__device__ __forceinline__ void beta_record(Scal* S, const double (&v)[3], int flag, cx<double> beta, double* hist)
+{
+    const int it = S->iter;
+    S->rr = v[2];
+    if (hist && it < S->hist_len) hist[it] = sqrt(v[2]) * S->hist_norm;
+    if (flag) {
+        S->flags = flag;
+        return;
+    }
+    st2(S->beta, beta);
+    st2(S->rho, cx<double>{v[0], v[1]});
+}
+
+// Fused scalar input of a vector kernel: fin[y][nb][3] reduction partials of problem y (nbs: per-problem
+// counts, or nullptr for nb).  With fin == nullptr the scalar was recorded in S by a finaliser kernel.
+struct Fin {
+    const double* fin;
+    int nb;
+    const int* nbs;
+    double* hist;  // beta step only
+};
+__device__ __forceinline__ void fin_sum(const Fin& f, double (&v)[3])
+{
+    sum3(f.fin + 3L * f.nb * blockIdx.y, f.nbs ? f.nbs[blockIdx.y] : f.nb, v);
+}
+__device__ __forceinline__ bool records() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
 // p = r + beta (p - omega v)
 // blockIdx.y selects the right-hand side: its scalars S[y] and elements [y n, (y+1) n)
 template <class P>
-__global__ __launch_bounds__(256) void k_bicg_p(void* p, const void* r, const void* v, long n, const Scal* S,
-                                                const long2* map)
+__global__ __launch_bounds__(256) void k_bicg_p(void* p, const void* r, const void* v, long n, Scal* S,
+                                                const long2* map, Fin f)
 {
     S += blockIdx.y;
-    if (S->flags) return;
+    const int f0 = S->flags;  // issued together with the partials' loads
+    cx<double> beta;
+    if (f.fin) {
+        double acc[3];
+        fin_sum(f, acc);  // every thread takes part (block barriers)
+        const int fl = f0 ? f0 : beta_step(S, acc, beta);
+        if (records() && !f0) beta_record(S, acc, fl, beta, f.hist ? f.hist + (long)blockIdx.y * S->hist_len : nullptr);
+        if (fl) return;
+    } else {
+        if (f0) return;
+        beta = ld2(S->beta);
+    }
     using T = typename P::real;
     QCDW_VEC_RANGE(n, map)
-    const cx<T> beta = {(T)S->beta[0], (T)S->beta[1]}, omega = {(T)S->omega[0], (T)S->omega[1]};
+    const cx<T> bt = {(T)beta.re, (T)beta.im}, omega = {(T)S->omega[0], (T)S->omega[1]};
     QCDW_GRID_LOOP(e, nn)
     {
         const auto pv = P::ld(p, off + e), rv = P::ld(r, off + e), vv = P::ld(v, off + e);
-        P::st(p, off + e, rv + beta * (pv - omega * vv));
+        P::st(p, off + e, rv + bt * (pv - omega * vv));
     }
 }
 
 // s = r - alpha v
 template <class P>
-__global__ __launch_bounds__(256) void k_bicg_s(void* sv, const void* r, const void* v, long n, const Scal* S,
-                                                const long2* map)
+__global__ __launch_bounds__(256) void k_bicg_s(void* sv, const void* r, const void* v, long n, Scal* S,
+                                                const long2* map, Fin f)
 {
     S += blockIdx.y;
-    if (S->flags) return;
+    const int f0 = S->flags;  // issued together with the partials' loads
+    cx<double> alpha;
+    if (f.fin) {
+        double acc[3];
+        fin_sum(f, acc);  // every thread takes part (block barriers)
+        const int fl = f0 ? f0 : alpha_step(S, acc, alpha);
+        if (records() && !f0) alpha_record(S, fl, alpha);
+        if (fl) return;
+    } else {
+        if (f0) return;
+        alpha = ld2(S->alpha);
+    }
     using T = typename P::real;
     QCDW_VEC_RANGE(n, map)
-    const cx<T> alpha = {(T)S->alpha[0], (T)S->alpha[1]};
+    const cx<T> al = {(T)alpha.re, (T)alpha.im};
     QCDW_GRID_LOOP(e, nn)
     {
         const auto rv = P::ld(r, off + e), vv = P::ld(v, off + e);
-        P::st(sv, off + e, rv - alpha * vv);
+        P::st(sv, off + e, rv - al * vv);
     }
 }
 
-// x += alpha p + omega s ; r = s - omega t ; partials (r0, r), ||r||^2
+// x += alpha p + omega s ; r = s - omega t ; partials (r0, r), ||r||^2 (must not overlap f.fin)
 template <class P, class PX>
 __global__ __launch_bounds__(256) void k_bicg_xr(void* x, const void* p, const void* sv, void* r, const void* t,
-                                                 const void* r0, long n, const Scal* S, double* partials,
-                                                 const long2* map)
+                                                 const void* r0, long n, Scal* S, double* partials,
+                                                 const long2* map, Fin f)
 {
     S += blockIdx.y;
-    if (S->flags) return;
+    const int f0 = S->flags;  // issued together with the partials' loads
+    cx<double> om;
+    if (f.fin) {
+        double acc[3];
+        fin_sum(f, acc);  // every thread takes part (block barriers)
+        const int fl = f0 ? f0 : omega_step(acc, om);
+        if (records() && !f0) omega_record(S, fl, om);
+        if (fl) return;
+    } else {
+        if (f0) return;
+        om = ld2(S->omega);
+    }
     using T = typename P::real;
     using TX = typename PX::real;
     QCDW_VEC_RANGE(n, map)
-    const cx<TX> alpha = {(TX)S->alpha[0], (TX)S->alpha[1]}, omega_x = {(TX)S->omega[0], (TX)S->omega[1]};
-    const cx<T> omega = {(T)S->omega[0], (T)S->omega[1]};
+    const cx<TX> alpha = {(TX)S->alpha[0], (TX)S->alpha[1]}, omega_x = {(TX)om.re, (TX)om.im};
+    const cx<T> omega = {(T)om.re, (T)om.im};
     double acc[3] = {0.0, 0.0, 0.0};
     QCDW_GRID_LOOP(e, nn)
     {
@@ -230,23 +384,6 @@ __global__ __launch_bounds__(256) void k_bicg_xr(void* x, const void* p, const v
         acc[2] += (double)rn.re * rn.re + (double)rn.im * rn.im;
     }
     block_sum_store<3>(acc, partials + 3L * ((long)blockIdx.y * gridDim.x + blockIdx.x));
-}
-
-// fixed-order sum of nb x 3 partials, result valid in thread 0
-__device__ __forceinline__ void sum3(const double* partials, int nb, double (&v)[3])
-{
-    __shared__ double res[3];
-    v[0] = v[1] = v[2] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        v[0] += partials[3L * b];
-        v[1] += partials[3L * b + 1];
-        v[2] += partials[3L * b + 2];
-    }
-    block_sum_store<3>(v, res);
-    __syncthreads();
-    v[0] = res[0];
-    v[1] = res[1];
-    v[2] = res[2];
 }
 
 // partials ((w, r), ||r||^2) per vector of a launch
@@ -269,7 +406,8 @@ __global__ __launch_bounds__(256) void k_wdot_norm2(const void* w, const void* r
 // Continue the recurrence after a reliable update that replaced r by the (rescaled) true residual:
 // rho' = (r0, r), beta = (rho' / rho)(alpha / omega) with the last step's alpha and omega, then the
 // usual p = r + beta (p - omega v).  Any rescaling of r cancels in beta (p, v and rho carry the old
-// scale together).  A near-zero rho' is a breakdown (the caller restarts).
+// scale together).  A near-zero rho' is a breakdown (the caller restarts).  The last step ended in
+// convergence, so rho is still the value its alpha step used.
 __global__ __launch_bounds__(256) void k_bicg_resume(Scal* S, const double* partials, int nb)
 {
     S += blockIdx.x;
@@ -303,6 +441,8 @@ __global__ void k_bicg_init(Scal* S, const double* rr_dev, int nrhs)
     const double rr = rr_dev[threadIdx.x];
     S->rho[0] = rr;
     S->rho[1] = 0.0;
+    S->rho_prev[0] = rr;
+    S->rho_prev[1] = 0.0;
     S->rr = rr;
     S->r0n2 = rr;
     S->alpha[0] = 1.0;
@@ -315,76 +455,38 @@ __global__ void k_bicg_init(Scal* S, const double* rr_dev, int nrhs)
     if (!isfinite(rr)) S->flags = FLAG_NAN;
 }
 
+// single-block finalisers: one block per problem (blockIdx.x), partials [problem][nb][3]
 __global__ __launch_bounds__(256) void k_fin_alpha(Scal* S, const double* partials, int nb, const int* nbs)
 {
     S += blockIdx.x;
-    if (S->flags) return;
+    if (S->flags) return;  // no other block of this launch writes them
     double v[3];
     sum3(partials + 3L * nb * blockIdx.x, nbs ? nbs[blockIdx.x] : nb, v);
-    if (threadIdx.x == 0) {
-        const cx<double> rv = {v[0], v[1]};
-        const double arv = sqrt(rv.re * rv.re + rv.im * rv.im);
-        if (!isfinite(arv)) {
-            S->flags = FLAG_NAN;
-        } else if (arv <= 1e-30 * sqrt(S->r0n2 * S->rr)) {
-            S->flags = FLAG_BREAK;
-        } else {
-            st2(S->alpha, cdiv(ld2(S->rho), rv));
-        }
-    }
+    cx<double> alpha;
+    const int fl = alpha_step(S, v, alpha);
+    if (threadIdx.x == 0) alpha_record(S, fl, alpha);
 }
 
 __global__ __launch_bounds__(256) void k_fin_omega(Scal* S, const double* partials, int nb, const int* nbs)
 {
     S += blockIdx.x;
-    if (S->flags) return;
+    if (S->flags) return;  // no other block of this launch writes them
     double v[3];
     sum3(partials + 3L * nb * blockIdx.x, nbs ? nbs[blockIdx.x] : nb, v);
-    if (threadIdx.x == 0) {
-        const double tt = v[2];
-        if (!isfinite(tt) || !isfinite(v[0]) || !isfinite(v[1])) {
-            S->flags = FLAG_NAN;
-        } else if (tt == 0.0) {
-            // s = 0: x + alpha p is exact; omega = 0 finishes the step
-            S->omega[0] = 0.0;
-            S->omega[1] = 0.0;
-        } else {
-            S->omega[0] = v[0] / tt;
-            S->omega[1] = v[1] / tt;
-        }
-    }
+    cx<double> omega;
+    const int fl = omega_step(v, omega);
+    if (threadIdx.x == 0) omega_record(S, fl, omega);
 }
 
 __global__ __launch_bounds__(256) void k_fin_beta(Scal* S, const double* partials, int nb, double* hist)
 {
     S += blockIdx.x;
-    if (S->flags) return;
-    if (hist) hist += (long)blockIdx.x * S->hist_len;
+    if (S->flags) return;  // no other block of this launch writes them
     double v[3];
     sum3(partials + 3L * nb * blockIdx.x, nb, v);
-    if (threadIdx.x == 0) {
-        const cx<double> rho_new = {v[0], v[1]};
-        const double rr = v[2];
-        const int it = S->iter + 1;
-        S->iter = it;
-        S->rr = rr;
-        if (hist && it < S->hist_len) hist[it] = sqrt(rr) * S->hist_norm;
-        const cx<double> omega = ld2(S->omega);
-        if (!isfinite(rr) || !isfinite(rho_new.re) || !isfinite(rho_new.im) ||
-            (S->fault_iter < 0 && it == -S->fault_iter)) {
-            S->flags = FLAG_NAN;
-        } else if (rr <= S->stop_rr) {
-            S->flags = FLAG_CONV;
-        } else if (omega.re == 0.0 && omega.im == 0.0) {
-            S->flags = FLAG_BREAK;
-        } else if (sqrt(rho_new.re * rho_new.re + rho_new.im * rho_new.im) <= 1e-30 * sqrt(S->r0n2 * rr)) {
-            S->flags = FLAG_BREAK;
-        } else {
-            st2(S->beta, cdiv(rho_new, ld2(S->rho)) * cdiv(ld2(S->alpha), omega));
-            st2(S->rho, rho_new);
-            if (S->fault_iter > 0 && it == S->fault_iter) S->flags = FLAG_BREAK;
-        }
-    }
+    cx<double> beta;
+    const int fl = beta_step(S, v, beta);
+    if (threadIdx.x == 0) beta_record(S, v, fl, beta, hist ? hist + (long)blockIdx.x * S->hist_len : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -496,43 +598,48 @@ hipError_t launch_bicg_resume(hipStream_t s, int prec, const void* r0, const voi
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S,
-                         int nrhs, const long2* map, long nmax)
+hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, Scal* S,
+                         int nrhs, const long2* map, long nmax, const double* fin, int fin_nb, double* hist)
 {
-    QCDW_DISPATCH1(prec, k_bicg_p, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, p, r, v, n, S, map)
+    const Fin f{fin, fin_nb, nullptr, hist};
+    QCDW_DISPATCH1(prec, k_bicg_p, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, p, r, v, n, S, map, f)
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S,
-                         int nrhs, const long2* map, long nmax)
+hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, Scal* S,
+                         int nrhs, const long2* map, long nmax, const double* fin, int fin_nb, const int* fin_nbs)
 {
-    QCDW_DISPATCH1(prec, k_bicg_s, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, sv, r, v, n, S, map)
+    const Fin f{fin, fin_nb, fin_nbs, nullptr};
+    QCDW_DISPATCH1(prec, k_bicg_s, dim3(blas_blocks(map ? nmax : n), nrhs), dim3(256), 0, s, sv, r, v, n, S, map, f)
     return hipGetLastError();
 }
 
 template <class PX>
 static hipError_t bicg_xr_x(hipStream_t s, int prec, void* x, const void* p, const void* sv, void* r, const void* t,
-                            const void* r0, long n, const Scal* S, double* partials, int nrhs, const long2* map,
-                            int nb)
+                            const void* r0, long n, Scal* S, double* partials, int nrhs, const long2* map, int nb,
+                            const Fin& f)
 {
     const dim3 grid(nb, nrhs);
     switch (prec) {
-    case F64: hipLaunchKernelGGL((k_bicg_xr<P64, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
-    case F32: hipLaunchKernelGGL((k_bicg_xr<P32, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
-    case BF16: hipLaunchKernelGGL((k_bicg_xr<PBF16, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
-    case F16: hipLaunchKernelGGL((k_bicg_xr<PF16, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map); break;
+    case F64: hipLaunchKernelGGL((k_bicg_xr<P64, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map, f); break;
+    case F32: hipLaunchKernelGGL((k_bicg_xr<P32, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map, f); break;
+    case BF16: hipLaunchKernelGGL((k_bicg_xr<PBF16, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map, f); break;
+    case F16: hipLaunchKernelGGL((k_bicg_xr<PF16, PX>), grid, dim3(256), 0, s, x, p, sv, r, t, r0, n, S, partials, map, f); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_bicg_xr(hipStream_t s, int prec, int prec_x, void* x, const void* p, const void* sv, void* r,
-                          const void* t, const void* r0, long n, const Scal* S, double* partials, int nrhs,
-                          const long2* map, long nmax)
+                          const void* t, const void* r0, long n, Scal* S, double* partials, int nrhs,
+                          const long2* map, long nmax, const double* fin, int fin_nb, const int* fin_nbs)
 {
     const int nb = blas_blocks(map ? nmax : n);
-    if (prec_x == F64) return bicg_xr_x<P64>(s, prec, x, p, sv, r, t, r0, n, S, partials, nrhs, map, nb);
-    if (prec_x == F32) return bicg_xr_x<P32>(s, prec, x, p, sv, r, t, r0, n, S, partials, nrhs, map, nb);
+    // the fused omega step reads fin while the blocks write their own partials
+    if (fin && partials < fin + 3L * fin_nb * nrhs && fin < partials + 3L * nb * nrhs) return hipErrorInvalidValue;
+    const Fin f{fin, fin_nb, fin_nbs, nullptr};
+    if (prec_x == F64) return bicg_xr_x<P64>(s, prec, x, p, sv, r, t, r0, n, S, partials, nrhs, map, nb, f);
+    if (prec_x == F32) return bicg_xr_x<P32>(s, prec, x, p, sv, r, t, r0, n, S, partials, nrhs, map, nb, f);
     return hipErrorInvalidValue;
 }
 

@@ -154,6 +154,21 @@ constexpr int CLOV_STRIDE = 1;  // distance between consecutive entries of one m
 __host__ __device__ inline long clov_index(int site, int chi, int m) { return ((long)site * 2 + chi) * 36 + m; }
 __host__ __device__ inline long clov_reals(long Vh) { return 72L * Vh; }
 
+// Internal gauge field of R complex entries per link (R = 6: the first two rows, R = 9: all), by
+// direction mu and parity p.  Entry j of link (mu, p, site) sits at link_base(mu, p, site) +
+// j * link_stride: link-major ([mu][p][Vh][R]), or site-fastest ([mu][p][R][Vh]) with
+// QCDW_LINK_SOA=1, where the consecutive sites of a wave read one contiguous run per entry.  The
+// site-fastest form measured no faster in FP64 and slower in BF16 (the entries of a link can no
+// longer be fetched by one wide load), so link-major is the default.
+#ifndef QCDW_LINK_SOA
+#define QCDW_LINK_SOA 0
+#endif
+__host__ __device__ inline long link_base(int mu, int p, long site, long Vh, int R)
+{
+    return QCDW_LINK_SOA ? (long)(mu * 2 + p) * R * Vh + site : ((long)(mu * 2 + p) * Vh + site) * R;
+}
+__host__ __device__ inline long link_stride(long Vh) { return QCDW_LINK_SOA ? Vh : 1; }
+
 // coordinates of checkerboard index i on parity p
 __device__ __forceinline__ void site_coords(const Geom& g, int i, int p, int& x, int& y, int& z, int& t)
 {

@@ -13,15 +13,16 @@
 
 namespace qcdw {
 
+// link at element offset off (link_base), entries `stride` apart (link_stride)
 template <class P, int R>
-__device__ __forceinline__ void load_link(const void* gauge, long off, cx<typename P::real> (&u)[9])
+__device__ __forceinline__ void load_link(const void* gauge, long off, long stride, cx<typename P::real> (&u)[9])
 {
     if constexpr (R == 9) {
 #pragma unroll
-        for (int e = 0; e < 9; e++) u[e] = P::ld(gauge, off + e);
+        for (int e = 0; e < 9; e++) u[e] = P::ld(gauge, off + e * stride);
     } else {
 #pragma unroll
-        for (int e = 0; e < 6; e++) u[e] = P::ld(gauge, off + e);
+        for (int e = 0; e < 6; e++) u[e] = P::ld(gauge, off + e * stride);
         // third row of an SU(3) matrix: complex conjugate of row0 x row1
         u[6] = conj(u[1] * u[5] - u[2] * u[4]);
         u[7] = conj(u[2] * u[3] - u[0] * u[5]);
@@ -100,7 +101,8 @@ __device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
 template <typename T, int R>
 struct LaneHops {
     int nbh[4];
-    long loff[4];
+    long loff[4];  // link_base of each hop's link
+    long lstr;     // link_stride
     T cre[4], cim[4], fsg[4];
 };
 
@@ -109,6 +111,7 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
 {
     const int gq = q >> 1, k = q & 1;
     const long Vh = g.Vh;
+    L.lstr = link_stride(Vh);
     int x, y, z, t;
     site_coords(g, site, p, x, y, z, t);
     const int xh = site % g.Lxh;
@@ -153,8 +156,8 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
         // with (1 + g_mu), which flips the projection coefficient
         L.nbh[2 * j] = fwd;
         L.nbh[2 * j + 1] = bwd;
-        L.loff[2 * j] = ((long)(mu * 2 + p) * Vh + site) * R;
-        L.loff[2 * j + 1] = ((long)(mu * 2 + (1 - p)) * Vh + bwd) * R;
+        L.loff[2 * j] = link_base(mu, p, site, Vh, R);
+        L.loff[2 * j + 1] = link_base(mu, 1 - p, bwd, Vh, R);
         L.cre[2 * j] = c_re;
         L.cim[2 * j] = c_im;
         L.cre[2 * j + 1] = -c_re;
@@ -185,7 +188,7 @@ __device__ __forceinline__ void hop_apply(const void* gauge, const LaneHops<type
     using T = typename P::real;
     const int dir = h & 1;
     cx<T> u[9];
-    load_link<P, R>(gauge, L.loff[h], u);
+    load_link<P, R>(gauge, L.loff[h], L.lstr, u);
     cx<T> w[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) {

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,27 +59,91 @@ struct qcdw_ctx {
 
 namespace qcdw_host {
 
+// Device blocks of destroyed operators, batches and nets, kept per device and handed to the next
+// allocation of about the same size: creating operators one after another (a new gauge field per
+// solve) then costs no hipMalloc, and no hipFree, which also waits for the whole device.  Blocks
+// enter the cache only once their owner's stream has drained (the destroy calls synchronise it).
+struct BlockCache {
+    std::mutex m;
+    std::map<int, std::multimap<size_t, void*>> free;  // device -> (size, block)
+    // smallest cached block of at least `bytes` and at most a quarter (plus 1 MiB) larger
+    void* take(int dev, size_t bytes, size_t& got)
+    {
+        std::lock_guard<std::mutex> lk(m);
+        auto& f = free[dev];
+        auto it = f.lower_bound(bytes);
+        if (it == f.end() || it->first > bytes + bytes / 4 + (1u << 20)) return nullptr;
+        void* q = it->second;
+        got = it->first;
+        f.erase(it);
+        return q;
+    }
+    void give(int dev, void* q, size_t n)
+    {
+        std::lock_guard<std::mutex> lk(m);
+        free[dev].emplace(n, q);
+    }
+    // return every cached block of the device to the runtime (the current device must be dev)
+    void trim(int dev)
+    {
+        std::lock_guard<std::mutex> lk(m);
+        for (auto& kv : free[dev]) (void)hipFree(kv.second);
+        free[dev].clear();
+    }
+};
+inline BlockCache& block_cache()
+{
+    static BlockCache* c = new BlockCache;  // never destroyed: blocks live until the process ends or a trim
+    return *c;
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
+    int dev = 0;
+    bool pooled = false;  // released into the block cache (only for owners that drain their stream first)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf()
     {
-        if (p) (void)hipFree(p);
+        if (!p) return;
+        if (pooled)
+            block_cache().give(dev, p, n);
+        else
+            (void)hipFree(p);
     }
     hipError_t alloc(size_t bytes)
     {
         if (p && n >= bytes) return hipSuccess;
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFree(p);  // growing: queued work may still use the old block
         p = nullptr;
         n = 0;
         if (bytes == 0) bytes = 16;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (pooled) {
+            size_t got = 0;
+            if ((p = block_cache().take(dev, bytes, got)) != nullptr) {
+                n = got;
+                return hipSuccess;
+            }
+        }
         hipError_t e = hipMalloc(&p, bytes);
-        if (e == hipSuccess) n = bytes;
+        if (e == hipErrorOutOfMemory && pooled) {
+            (void)hipGetLastError();
+            block_cache().trim(dev);
+            e = hipMalloc(&p, bytes);
+        }
+        if (e == hipSuccess)
+            n = bytes;
+        else
+            p = nullptr;
         return e;
     }
+};
+// a DevBuf whose block goes back into the cache
+struct PoolBuf : DevBuf {
+    PoolBuf() { pooled = true; }
 };
 
 struct DeviceGuard {
@@ -163,13 +228,13 @@ using namespace qcdw_host;
 // Solver workspace: stacked/concatenated vectors of all problems of a solve,
 // scalars, partials, and the graphs captured over them.
 struct Workspace {
-    DevBuf be, bo, yo, ye, bhat, xhi, rhi, tmp64, tmpo64;  // FP64, per problem
-    DevBuf kr[7];  // r, r0, p, v, s, t, tmp_o in the Krylov precision
-    DevBuf xlo;    // FP32 correction (mixed precision)
-    DevBuf partials, scal, dres, hist, coef;
+    PoolBuf be, bo, yo, ye, bhat, xhi, rhi, tmp64, tmpo64;  // FP64, per problem
+    PoolBuf kr[7];  // r, r0, p, v, s, t, tmp_o in the Krylov precision
+    PoolBuf xlo;    // FP32 correction (mixed precision)
+    PoolBuf partials, scal, dres, hist, coef;
     int ws_gen = 0;  // bumped whenever a buffer is (re)allocated
     struct Graph {
-        int kprec, chunk, nprob, variant, gen;
+        int kprec, chunk, nprob, variant, gen, fuse_nb;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     };
@@ -191,8 +256,8 @@ struct qcdw_op {
     double kappa = 0, csw = 0;
     int inner = F64;
     int recon = 12;
-    DevBuf gauge64, gauge_lo;
-    DevBuf Ainv64[2], Ainv_lo[2], A64[2];
+    PoolBuf gauge64, gauge_lo;
+    PoolBuf Ainv64[2], Ainv_lo[2], A64[2];
     int hop_nt[4] = {1, 1, 1, 1};  // single-RHS hop, per precision (tuned): sites per thread along t
     int hop_cg[4] = {0, 0, 0, 0};  //   and c-tiles per group swept along t (0: none)
     Workspace ws;                  // single- and multi-RHS solves
@@ -206,7 +271,7 @@ struct qcdw_batch {
     std::vector<long> off, len;  // element offsets / lengths of each problem in concatenated vectors
     long total = 0, nmax = 0;
     int total_tiles = 0, nbmax = 0;
-    DevBuf map, nbs, tab64, tablo;  // device: (off, len) pairs, hop tiles per problem, BatchEntry tables
+    PoolBuf map, nbs, tab64, tablo;  // device: (off, len) pairs, hop tiles per problem, BatchEntry tables
     Workspace ws;
 };
 

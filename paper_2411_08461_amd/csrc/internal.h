@@ -32,7 +32,7 @@ enum Red {
 struct HopArgs {
     const void* psi;    // input spinor, parity 1 - parity
     void* out;          // output spinor, parity `parity`
-    const void* gauge;  // [4][2][Vh][R]
+    const void* gauge;  // R entries per link at link_base / link_stride (dev.h)
     const void* clov;   // clover-type matrix of the output parity, [Vh][2][36] reordered
     const void* y;      // xpay / dot operand on the output parity
     const void* w;      // dot operand on the output parity
@@ -106,6 +106,7 @@ hipError_t launch_hop_batch(hipStream_t s, int prec, int epi, int red, const Bat
 
 struct Scal {
     double rho[2];    // (r0, r)
+    double rho_prev[2];  // rho of the iteration in progress (the beta step's denominator)
     double alpha[2];
     double omega[2];
     double beta[2];
@@ -151,13 +152,21 @@ hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nr
 // rho' = (r0, r), beta from the previous step's scalars, for a cycle that continues the recurrence
 hipError_t launch_bicg_resume(hipStream_t s, int prec, const void* r0, const void* r, long n, Scal* S,
                               double* partials, int nrhs, const long2* map, long nmax);
-hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, const Scal* S,
-                         int nrhs = 1, const long2* map = nullptr, long nmax = 0);
-hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, const Scal* S,
-                         int nrhs = 1, const long2* map = nullptr, long nmax = 0);
+// The BiCGStab vector updates.  Each takes its scalar (beta, alpha, omega) from S, recorded there by
+// the matching launch_fin_* kernel, or, with fin != nullptr, forms it itself from the reduction
+// partials fin [RHS][fin_nb][3] (fin_nbs: per-RHS counts, or nullptr) and records it in S: one
+// launch fewer per scalar.  hist: the residual history of the beta step (fused form only).
+hipError_t launch_bicg_p(hipStream_t s, int prec, void* p, const void* r, const void* v, long n, Scal* S,
+                         int nrhs = 1, const long2* map = nullptr, long nmax = 0, const double* fin = nullptr,
+                         int fin_nb = 0, double* hist = nullptr);
+hipError_t launch_bicg_s(hipStream_t s, int prec, void* sv, const void* r, const void* v, long n, Scal* S,
+                         int nrhs = 1, const long2* map = nullptr, long nmax = 0, const double* fin = nullptr,
+                         int fin_nb = 0, const int* fin_nbs = nullptr);
+// partials (its own output) must not overlap fin
 hipError_t launch_bicg_xr(hipStream_t s, int prec, int prec_x, void* x, const void* p, const void* sv, void* r,
-                          const void* t, const void* r0, long n, const Scal* S, double* partials, int nrhs = 1,
-                          const long2* map = nullptr, long nmax = 0);
+                          const void* t, const void* r0, long n, Scal* S, double* partials, int nrhs = 1,
+                          const long2* map = nullptr, long nmax = 0, const double* fin = nullptr, int fin_nb = 0,
+                          const int* fin_nbs = nullptr);
 // nb: partials stride per RHS; nbs (optional, per RHS) the count actually written
 hipError_t launch_fin_alpha(hipStream_t s, Scal* S, const double* partials, int nb, int nrhs = 1,
                             const int* nbs = nullptr);

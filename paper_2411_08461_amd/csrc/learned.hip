@@ -12,13 +12,13 @@ struct qcdw_net {
     qcdw_ctx* ctx = nullptr;
     int hidden = 12;
     long nw1 = 0, nw2 = 0;            // complex weights per layer
-    DevBuf gauge32;                   // FP32 reconstruct-12 links
-    DevBuf W1, W2, Wt;                // FP32 complex weights and the adjoint-layer scratch
-    DevBuf W1bf, W2bf;                // weights rounded to BF16 values (application)
-    DevBuf G1, G2, m1, v1, m2, v2;    // FP64 gradients and Adam moments
-    DevBuf act0, hid, z, gz, gh;      // activations [parity][channel][Vh][3] complex
-    DevBuf hid16;                     // BF16 hidden activations (application)
-    DevBuf diff, tmp64, partials, res;
+    PoolBuf gauge32;                   // FP32 reconstruct-12 links
+    PoolBuf W1, W2, Wt;                // FP32 complex weights and the adjoint-layer scratch
+    PoolBuf W1bf, W2bf;                // weights rounded to BF16 values (application)
+    PoolBuf G1, G2, m1, v1, m2, v2;    // FP64 gradients and Adam moments
+    PoolBuf act0, hid, z, gz, gh;      // activations [parity][channel][Vh][3] complex
+    PoolBuf hid16;                     // BF16 hidden activations (application)
+    PoolBuf diff, tmp64, partials, res;
     int adam_step = 0;
     bool bf_dirty = true;
     int mfma = 0;  // BF16 application layers on the matrix cores (chosen by timing at creation)

@@ -16,15 +16,17 @@ namespace qcdw {
 struct NetArgs {
     const void* in;
     void* out;
-    const void* gauge;  // P32 [4][2][Vh][6]
+    const void* gauge;  // P32 reconstruct-12 links (link_base, link_stride)
     const float2* W;    // [9][COUT][CIN]
     Geom g;
 };
 
-__device__ __forceinline__ void su3_row3(const void* gauge, long off, cx<float> (&u)[9])
+// link (mu, p, site) of an FP32 reconstruct-12 internal gauge field (two rows stored)
+__device__ __forceinline__ void su3_row3(const void* gauge, int mu, int p, int site, long Vh, cx<float> (&u)[9])
 {
+    const long off = link_base(mu, p, site, Vh, 6), st = link_stride(Vh);
 #pragma unroll
-    for (int e = 0; e < 6; e++) u[e] = P32::ld(gauge, off + e);
+    for (int e = 0; e < 6; e++) u[e] = P32::ld(gauge, off + e * st);
     u[6] = conj(u[1] * u[5] - u[2] * u[4]);
     u[7] = conj(u[2] * u[3] - u[0] * u[5]);
     u[8] = conj(u[0] * u[4] - u[1] * u[3]);
@@ -74,7 +76,7 @@ __device__ __forceinline__ void transport(const void* in, const void* gauge, con
     const int mu = (a - 1) >> 1, back = (a - 1) & 1;
     const int j = nbr_index(g, i, x, y, z, t, mu, back);
     cx<float> u[9];
-    su3_row3(gauge, back == 0 ? (((long)mu * 2 + p) * Vh + i) * 6 : (((long)mu * 2 + (1 - p)) * Vh + j) * 6, u);
+    su3_row3(gauge, mu, back == 0 ? p : 1 - p, back == 0 ? i : j, Vh, u);
 #pragma unroll
     for (int c = 0; c < CIN; c++) {
         cx<float> v[3];
@@ -149,8 +151,7 @@ __global__ __launch_bounds__(256) void k_net_layer_mfma(NetArgs n)
                     cur_a = a;
                     if (a > 0) {
                         nb = nbr_index(g, i, x, y, z, t, mu, back);
-                        su3_row3(n.gauge, back == 0 ? (((long)mu * 2 + p) * Vh + i) * 6
-                                                    : (((long)mu * 2 + (1 - p)) * Vh + nb) * 6, u);
+                        su3_row3(n.gauge, mu, back == 0 ? p : 1 - p, back == 0 ? i : nb, Vh, u);
                     }
                 }
                 if (a == 0) {

@@ -33,7 +33,7 @@ __global__ void k_unpack_spinor(const void* in, double2* __restrict__ paper, int
     paper[((long)parity * Vh + site) * 12 + s * 3 + c] = make_double2(scale * (double)v.re, scale * (double)v.im);
 }
 
-// gauge: paper [4][2][Vh][3][3]  ->  internal [4][2][Vh][R] (rows 0..R/3-1)
+// gauge: paper [4][2][Vh][3][3]  ->  internal links of R entries (rows 0..R/3-1) at link_base
 template <class P, int R>
 __global__ void k_pack_gauge(const double2* __restrict__ paper, void* out, int Vh)
 {
@@ -41,9 +41,10 @@ __global__ void k_pack_gauge(const double2* __restrict__ paper, void* out, int V
     if (e >= 8L * Vh * R) return;
     const int j = (int)(e % R);
     const long link = e / R;  // (mu*2 + parity)*Vh + site
+    const int site = (int)(link % Vh), mp = (int)(link / Vh);
     const double2 v = paper[link * 9 + j];
     using T = typename P::real;
-    P::st(out, e, cx<T>{(T)v.x, (T)v.y});
+    P::st(out, link_base(mp >> 1, mp & 1, site, Vh, R) + j * link_stride(Vh), cx<T>{(T)v.x, (T)v.y});
 }
 
 // clover: paper [2][Vh][2][36] -> internal (one parity) [Vh][2][36] in the reordered packing

@@ -662,3 +662,44 @@ def test_multi_rhs_forms(tmp_path, monkeypatch, variant):
         torch.cuda.synchronize()
         c.close()
         assert f" {variant}" in cache.read_text()
+
+
+@pytest.mark.parametrize("inner", ["f64", "bf16"])
+def test_fused_scalar_steps_match_separate_kernels(ctx, monkeypatch, inner):
+    """The BiCGStab scalars formed inside the vector kernels (every block sums the partials) give
+    bitwise the same iterations, residual histories and solutions as the single-block finaliser
+    kernels: single RHS, lockstep multi-RHS and an uneven batch, in FP64 and BF16-mixed."""
+    L = (8, 8, 8, 16)
+    U = _gauge(L, 0.25, 61)
+    kappa, csw = 0.122, 1.0
+    b = li.gaussian_source(L, 62)
+    bs = np.stack([li.gaussian_source(L, 63 + k) for k in range(3)])
+    specs = [((4, 4, 4, 4), 0.115), ((6, 4, 2, 6), 0.121), ((10, 6, 4, 6), 0.118)]
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw, inner)
+    bops = [q.Operator(ctx, q.make_lattice(Lb), dev(li.random_gauge(Lb, 0.25, 70 + k)), kb, 1.0, inner)
+            for k, (Lb, kb) in enumerate(specs)]
+    bbs = [dev(li.gaussian_source(Lb, 80 + k)) for k, (Lb, _) in enumerate(specs)]
+    batch = q.Batch(ctx, bops)
+    prm = q.make_params(tol=1e-10, inner=inner)
+    res = {}
+    for fuse in ("0", "1000000"):
+        monkeypatch.setenv("QCDW_FUSE_NB", fuse)
+        x = torch.zeros(li.fermion_shape(L), dtype=torch.complex128, device="cuda")
+        info = q.qcdw_invert(op, dev(b), x, prm)
+        xm = torch.zeros(bs.shape, dtype=torch.complex128, device="cuda")
+        infos = q.qcdw_invert_multi(op, dev(bs), xm, prm)
+        xb = [torch.zeros(li.fermion_shape(Lb), dtype=torch.complex128, device="cuda") for Lb, _ in specs]
+        binfos = q.qcdw_invert_batch(batch, bbs, xb, prm)
+        for i in [info] + list(infos) + list(binfos):
+            assert i.status == q.QCDW_OK, (fuse, i)
+        res[fuse] = ([i.iters for i in [info] + list(infos) + list(binfos)],
+                     [i.res_hist for i in [info] + list(infos) + list(binfos)],
+                     [host(x), host(xm)] + [host(t) for t in xb])
+    assert res["0"][0] == res["1000000"][0]
+    assert res["0"][1] == res["1000000"][1]
+    for a, c in zip(res["0"][2], res["1000000"][2]):
+        assert np.array_equal(a, c)
+    assert _oracle_true_res(L, U, res["0"][2][0], b, kappa, csw) <= 1e-10
+    batch.close()
+    for o in [op] + bops:
+        o.close()
