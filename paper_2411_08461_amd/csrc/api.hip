@@ -800,11 +800,11 @@ struct Solver {
             m.a = op->kappa;
             HIPCHK(ctx, launch_hop(s, F64, v64.recon, EPI_XPAY_CLOVY, RED_NONE, m));
             HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, p == 0 ? at(W.be, k) : at(W.bo, k), W.tmp64.p, nullptr, len[k],
-                                         (double*)W.partials.p, (double*)W.dres.p));
-            double rp;
-            CHK(read_double(ctx, (double*)W.dres.p, rp));
-            r2 += rp;
+                                         (double*)W.partials.p, (double*)W.dres.p + p));
         }
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_d, W.dres.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        r2 = ctx->host_d[0] + ctx->host_d[1];
         return QCDW_OK;
     }
 
@@ -895,11 +895,20 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         HIPCHK(ctx, launch_pack_spinor(s, F64, g, bs[k], 1, S.at(W.bo, k), 1.0));
         HIPCHK(ctx, launch_pack_spinor(s, F64, g, xs[k], 0, S.at(W.xhi, k), 1.0));
     }
-    std::vector<double> bn2e, bn2o, bnorm(nprob);
-    HIPCHK(ctx, launch_norm2(s, F64, W.be.p, n0, dpart, dres, nprob, S.map, S.nmax));
-    CHK(S.read_doubles(bn2e));
-    HIPCHK(ctx, launch_norm2(s, F64, W.bo.p, n0, dpart, dres, nprob, S.map, S.nmax));
-    CHK(S.read_doubles(bn2o));
+    std::vector<double> bn2e(nprob), bn2o(nprob), bnorm(nprob);
+    {
+        // ||b_e||^2 into dres[0, nprob), ||b_o||^2 into coef[0, nprob) (both sized for MAX_BATCH), one read
+        HIPCHK(ctx, launch_norm2(s, F64, W.be.p, n0, dpart, dres, nprob, S.map, S.nmax));
+        HIPCHK(ctx, launch_norm2(s, F64, W.bo.p, n0, dpart + 3L * nprob * S.part_stride(), dcoef, nprob, S.map,
+                                 S.nmax));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_d, dres, nprob * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_d + nprob, dcoef, nprob * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        for (int k = 0; k < nprob; k++) {
+            bn2e[k] = ctx->host_d[k];
+            bn2o[k] = ctx->host_d[nprob + k];
+        }
+    }
     std::vector<int> status(nprob, QCDW_ENOCONV), done(nprob, 0), restarts(nprob, 0), iters(nprob, 0);
     std::vector<double> true_res(nprob, NAN), target(nprob), iter_res(nprob, NAN);
     for (int k = 0; k < nprob; k++) {
@@ -1014,17 +1023,6 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
             hc[nprob + k] = done[k] ? 0.0 : 1.0 / scale[k];
         }
         HIPCHK(ctx, hipMemcpyAsync(dcoef, hc, 2 * nprob * sizeof(double), hipMemcpyHostToDevice, s));
-        HIPCHK(ctx, launch_convert(s, F64, kprec, W.rhi.p, r, n0, 1.0, dcoef, nprob, S.map, S.nmax));
-        if (!resume) {
-            HIPCHK(ctx, launch_convert(s, kprec, kprec, r, r0, n0, 1.0, nullptr, nprob, S.map, S.nmax));
-            HIPCHK(ctx, launch_convert(s, kprec, kprec, r, p, n0, 1.0, nullptr, nprob, S.map, S.nmax));
-        }
-        if (mixed) {
-            long total = 0;
-            for (int k = 0; k < nprob; k++) total += S.len[k];
-            HIPCHK(ctx, hipMemsetAsync(W.xlo.p, 0, (size_t)total * 8, s));
-        }
-        if (!resume) HIPCHK(ctx, launch_norm2(s, kprec, r, n0, dpart, dres, nprob, S.map, S.nmax));
         Scal* hs = ctx->host_scal;  // a resumed cycle keeps the last cycle's rho, alpha, omega, r0 norm
         if (!resume) memset(hs, 0, nprob * sizeof(Scal));
         for (int k = 0; k < nprob; k++) {
@@ -1038,13 +1036,14 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
             if (resume) hs[k].flags = done[k] ? FLAG_CONV : 0;
         }
         HIPCHK(ctx, hipMemcpyAsync(dS, hs, nprob * sizeof(Scal), hipMemcpyHostToDevice, s));
+        // r = scale rhi; restart: r0 = p = r, rho = ||r||^2; the FP32 correction starts at zero
+        HIPCHK(ctx, launch_cycle_start(s, kprec, W.rhi.p, r, r0, p, mixed ? W.xlo.p : nullptr, n0, dcoef, dS, dpart,
+                                       nprob, S.map, S.nmax, resume));
         if (resume) {
             // reliable update without restart: r is the rescaled true residual, r0, p, v and the scalars
             // carry on (Sleijpen and van der Vorst 1996)
             HIPCHK(ctx, launch_bicg_resume(s, kprec, r0, r, n0, dS, dpart, nprob, S.map, S.nmax));
             HIPCHK(ctx, launch_bicg_p(s, kprec, p, r, W.kr[3].p, n0, dS, nprob, S.map, S.nmax));
-        } else {
-            HIPCHK(ctx, launch_bicg_init(s, dS, dres, nprob));
         }
         int all_flags = 0;
         // stagnation of a low-precision cycle: no new minimum of the iterated residual for
@@ -1061,14 +1060,7 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
             int advanced = 0;
             bool all_set = true;
             for (int k = 0; k < nprob; k++) {
-                const int done_now = hs[k].iter - iters[k];
-                advanced = std::max(advanced, done_now);
-                if (done_now > 0) {
-                    std::vector<double> h(done_now);
-                    HIPCHK(ctx, hipMemcpy(h.data(), dhist + (size_t)k * hist_len + iters[k] + 1,
-                                          done_now * sizeof(double), hipMemcpyDeviceToHost));
-                    hist_host[k].insert(hist_host[k].end(), h.begin(), h.end());
-                }
+                advanced = std::max(advanced, hs[k].iter - iters[k]);
                 iters[k] = hs[k].iter;
                 if (mixed && !done[k] && !hs[k].flags) {
                     if (hs[k].rr < cyc_min[k]) {
@@ -1147,6 +1139,15 @@ qcdw_status solve(Solver& S, const void* const* bs, void* const* xs, const qcdw_
         HIPCHK(ctx, launch_unpack_spinor(s, F64, g, W.tmpo64.p, 1, xs[k], 1.0));
     }
     HIPCHK(ctx, hipStreamSynchronize(s));
+    // the iterated-residual history of each problem, written by the device at iterations 1..iters
+    for (int k = 0; k < nprob; k++) {
+        const int m = std::min(iters[k], hist_len - 1);
+        if (!user_hist[k] || user_hist_len[k] <= 0 || m <= 0) continue;
+        const size_t at = hist_host[k].size();
+        hist_host[k].resize(at + m);
+        HIPCHK(ctx, hipMemcpy(hist_host[k].data() + at, dhist + (size_t)k * hist_len + 1, m * sizeof(double),
+                              hipMemcpyDeviceToHost));
+    }
 
     const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     qcdw_status worst = QCDW_OK;

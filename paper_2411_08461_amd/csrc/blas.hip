@@ -433,12 +433,45 @@ __global__ __launch_bounds__(256) void k_bicg_resume(Scal* S, const double* part
     }
 }
 
-// start (or restart) from the residual r with r0 = r: rho = (r0, r) = ||r||^2
-__global__ void k_bicg_init(Scal* S, const double* rr_dev, int nrhs)
+// Start of a Krylov cycle from the FP64 residual rhi of every problem: r = scale_y rhi rounded to
+// the Krylov precision; without `resume` also r0 = p = r and partials of ||r||^2 (of the rounded
+// r, as the iteration sees it); x_lo = 0 when given (the FP32 correction of a mixed cycle).
+template <class P>
+__global__ __launch_bounds__(256) void k_cycle_start(const double2* rhi, void* r, void* r0, void* p, float2* xlo,
+                                                     long n, const double* scales, double* partials,
+                                                     const long2* map, int resume)
 {
-    if ((int)threadIdx.x >= nrhs) return;
-    S += threadIdx.x;
-    const double rr = rr_dev[threadIdx.x];
+    using T = typename P::real;
+    QCDW_VEC_RANGE(n, map)
+    const double sc = scales[blockIdx.y];
+    double acc[1] = {0.0};
+    QCDW_GRID_LOOP(e, nn)
+    {
+        const double2 a = rhi[off + e];
+        const cx<T> v = P::rt(cx<T>{(T)(sc * a.x), (T)(sc * a.y)});
+        P::st(r, off + e, v);
+        if (!resume) {
+            P::st(r0, off + e, v);
+            P::st(p, off + e, v);
+            acc[0] += (double)v.re * v.re + (double)v.im * v.im;
+        }
+        if (xlo) xlo[off + e] = make_float2(0.f, 0.f);
+    }
+    if (!resume) block_sum_store<1>(acc, partials + (long)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// start (or restart) from the residual r with r0 = r: rho = (r0, r) = ||r||^2, summed from the nb
+// partials of each problem (one block per problem)
+__global__ __launch_bounds__(256) void k_bicg_init(Scal* S, const double* partials, int nb)
+{
+    S += blockIdx.x;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += 256) v[0] += partials[(long)blockIdx.x * nb + b];
+    __shared__ double res;
+    block_sum_store<1>(v, &res);
+    __syncthreads();
+    if (threadIdx.x) return;
+    const double rr = res;
     S->rho[0] = rr;
     S->rho[1] = 0.0;
     S->rho_prev[0] = rr;
@@ -583,9 +616,14 @@ hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, co
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nrhs)
+hipError_t launch_cycle_start(hipStream_t s, int prec, const void* rhi, void* r, void* r0, void* p, void* xlo, long n,
+                              const double* scales, Scal* S, double* partials, int nrhs, const long2* map, long nmax,
+                              bool resume)
 {
-    hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(64), 0, s, S, rr_dev, nrhs);
+    const int nb = blas_blocks(map ? nmax : n);
+    QCDW_DISPATCH1(prec, k_cycle_start, dim3(nb, nrhs), dim3(256), 0, s, (const double2*)rhi, r, r0, p, (float2*)xlo,
+                   n, scales, partials, map, resume ? 1 : 0)
+    if (!resume) hipLaunchKernelGGL(k_bicg_init, dim3(nrhs), dim3(256), 0, s, S, partials, nb);
     return hipGetLastError();
 }
 

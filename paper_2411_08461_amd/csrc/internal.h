@@ -148,7 +148,12 @@ hipError_t launch_clov_apply_internal(hipStream_t s, int prec, const Geom& g, co
                                       void* out);
 
 // BiCGStab iteration pieces
-hipError_t launch_bicg_init(hipStream_t s, Scal* S, const double* rr_dev, int nrhs = 1);
+// start of a Krylov cycle from the FP64 residuals rhi: r = scales[y] rhi in precision prec; unless
+// resume, r0 = p = r and the scalars S are initialised from ||r||^2 (rho = ||r||^2, flags from
+// stop_rr); xlo (FP32 complex, may be nullptr) is cleared.  partials: nrhs x blas_blocks doubles.
+hipError_t launch_cycle_start(hipStream_t s, int prec, const void* rhi, void* r, void* r0, void* p, void* xlo, long n,
+                              const double* scales, Scal* S, double* partials, int nrhs, const long2* map, long nmax,
+                              bool resume);
 // rho' = (r0, r), beta from the previous step's scalars, for a cycle that continues the recurrence
 hipError_t launch_bicg_resume(hipStream_t s, int prec, const void* r0, const void* r, long n, Scal* S,
                               double* partials, int nrhs, const long2* map, long nmax);
