@@ -511,7 +511,8 @@ struct Solver {
     int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse), batch grid, or
                                  // single-RHS sites per thread along t
     int nt = 1, cg = 0;          // single-RHS hop: sites per thread along t, c-tile group
-    int fuse_nb;                 // largest partials count whose scalar is formed in the vector kernel
+    int fuse_nb;                 // largest partials count (all problems of a launch) whose scalars are
+                                 // formed in the vector kernels
     Timing tm;
 
     Solver(qcdw_ctx* c, Workspace& w, std::vector<qcdw_op*> o, qcdw_batch* b)
@@ -612,9 +613,10 @@ struct Solver {
         double* dpart2 = dpart + 3L * nprob * part_stride();  // partials of the x/r update
         double* hist = (double*)W.hist.p;
         const long n = n0();
-        // a scalar is formed inside the vector kernel that uses it when its partials are few (every
-        // block of that kernel sums them), else by a single-block kernel in between
-        const bool fh = nb_hop <= fuse_nb, fb = nb_blas <= fuse_nb;
+        // a scalar is formed inside the vector kernel that uses it when the launch's partials are few
+        // (every block of that kernel sums its problem's partials, so the reads grow with problems x
+        // partials), else by a single-block kernel in between
+        const bool fh = (long)nprob * nb_hop <= fuse_nb, fb = (long)nprob * nb_blas <= fuse_nb;
         hipError_t e = hipSuccess;
         for (int i = 0; i < nit && e == hipSuccess; i++) {
             e = hop(st, kprec, EPI_CLOV, RED_NONE, p, tmpo, nullptr, nullptr, nullptr, dS, 1);

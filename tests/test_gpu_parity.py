@@ -703,3 +703,30 @@ def test_fused_scalar_steps_match_separate_kernels(ctx, monkeypatch, inner):
     batch.close()
     for o in [op] + bops:
         o.close()
+
+
+def test_operators_reuse_cached_device_blocks(ctx):
+    """Operators created after others were closed take their device blocks from the cache (the same
+    sizes, then other sizes in between): every solve gives bitwise the solution of the first operator
+    on the same inputs, and a different lattice created in between still solves to the oracle."""
+    L, L2 = (8, 8, 8, 16), (6, 4, 2, 6)
+    U = _gauge(L, 0.25, 91)
+    U2 = _gauge(L2, 0.25, 92)
+    b = dev(li.gaussian_source(L, 93))
+    b2 = dev(li.gaussian_source(L2, 94))
+    prm = q.make_params(tol=1e-10, inner="bf16")
+
+    def solve(Lx, Ux, bx, kappa):
+        op = q.Operator(ctx, q.make_lattice(Lx), dev(Ux), kappa, 1.0, "bf16")
+        x = torch.zeros(li.fermion_shape(Lx), dtype=torch.complex128, device="cuda")
+        info = q.qcdw_invert(op, bx, x, prm)
+        op.close()
+        assert info.status == q.QCDW_OK
+        return host(x), info.iters
+
+    x0, it0 = solve(L, U, b, 0.122)
+    for k in range(3):
+        x2, _ = solve(L2, U2, b2, 0.118)
+        assert _oracle_true_res(L2, U2, x2, host(b2), 0.118, 1.0) <= 1e-10
+        x1, it1 = solve(L, U, b, 0.122)
+        assert it1 == it0 and np.array_equal(x1, x0), k
