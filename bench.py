@@ -88,7 +88,7 @@ def parse():
                     help="profiling mode: a 256 MiB device copy (counter calibration), then a few M_hat "
                          "applications in FP64 and BF16 on this lattice, e.g. 24,24,24,64; prints nothing else")
     ap.add_argument("--forms", default="",
-                    help="with --matpc-only: hop forms nt:cgroup to run one after the other (each in a fresh "
+                    help="with --matpc-only: hop forms nt:cgroup[:fma] to run one after the other (each in a fresh "
                          "context whose tuning file fixes the form), e.g. 1:0,1:27,2:12")
     return ap.parse_args()
 
@@ -114,11 +114,11 @@ def matpc_only(L, forms):
     runs = []
     for f in forms or [None]:
         if f is not None:  # a fresh context reads the tuning file that fixes the form
-            nt, cg = f
-            path = os.path.join(tempfile.gettempdir(), f"qcdw_form_{nt}_{cg}.txt")
+            nt, cg, fma = (tuple(f) + (0,))[:3]
+            path = os.path.join(tempfile.gettempdir(), f"qcdw_form_{nt}_{cg}_{fma}.txt")
             with open(path, "w") as fh:
                 for p in range(4):
-                    fh.write(f"hop_nt/p{p}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {nt + 16 * cg}\n")
+                    fh.write(f"hop_nt/p{p}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {nt + 16 * cg + 4096 * fma}\n")
             os.environ["QCDW_TUNE_CACHE"] = path
         ctx = q.Context(0)
         op = q.Operator(ctx, q.make_lattice(L), U, 0.125, 1.1, "bf16", 12)
@@ -254,7 +254,7 @@ def main():
                    "lattice": list(L), "kappa": kappa, "csw": csw, "tol": 1e-10, "inner": args.inner},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form),
-                     "kernel": hop_kernel_name(form), "form": {"nt": form[0], "cgroup": form[1]},
+                     "kernel": hop_kernel_name(form), "form": {"nt": form[0], "cgroup": form[1], "fma": form[2]},
                      "launches_timed": n_a, "bytes_per_launch": hop_a_bytes("f64") * Vh,
                      "avg_launch_us": round(avg_a_ms * 1e3, 2)},
         "solve": {
@@ -290,10 +290,13 @@ def main():
 
 
 def hop_kernel_name(form):
-    nt, cg = form
+    nt, cg, fma = form
+    f = "true" if fma else "false"
     if nt == 1:
-        return "hop_kernel<P64, r12, EPI_CLOV, RED_NONE>" + (f" (slice groups of {cg} c-tiles)" if cg else "")
-    return f"hop_tkernel<P64, r12, EPI_CLOV, RED_NONE, {nt}>" + (f" (slice groups of {cg} c-tiles)" if cg else "")
+        name = f"hop_kernel<P64, r12, EPI_CLOV, RED_NONE, {f}>"
+    else:
+        name = f"hop_tkernel<P64, r12, EPI_CLOV, RED_NONE, {nt}, {f}>"
+    return name + (f" (slice groups of {cg} c-tiles)" if cg else "")
 
 
 KERNEL_SOURCES = ("paper_2411_08461_amd/csrc/hop.hip", "paper_2411_08461_amd/csrc/hop_common.h",
@@ -321,7 +324,7 @@ def measured_traffic(form):
         rec = json.loads(line[len("traffic-json: "):])
     except (OSError, StopIteration, ValueError):
         return None
-    if rec.get("sources_sha256") != kernel_sources_sha256() or [rec.get("nt"), rec.get("cgroup")] != list(form):
+    if rec.get("sources_sha256") != kernel_sources_sha256() or [rec.get("nt"), rec.get("cgroup"), rec.get("fma")] != list(form):
         return None
     return int(rec["read_bytes"] + rec["write_bytes"])
 

@@ -170,9 +170,12 @@ void qcdw_op_destroy(qcdw_op *op);
 /* The form of the operator's single-RHS parity hop in precision prec (F64 or the inner
    precision), chosen by timing when the operator was created or read from the tuning cache
    ($QCDW_TUNE_CACHE, the role of the paper's resource_path, Sec. III.B): *nt output sites per
-   thread along t (1, 2, 4 or 8) and *cgroup c-tiles per group swept along t (0: none).  The
-   choice changes only the order of memory accesses, not the result. */
-qcdw_status qcdw_op_hop_form(const qcdw_op *op, qcdw_prec prec, int *nt, int *cgroup);
+   thread along t (1, 2, 4 or 8), *cgroup c-tiles per group swept along t (0: none) and *fma the
+   arithmetic form (1: every complex multiply-add as real multiply-adds; fma may be NULL).  nt and
+   cgroup change only the order of memory accesses; fma changes the rounding of the result (within
+   a few units in the last place per site).  Returns QCDW_EINVAL for a NULL nt or cgroup or
+   another precision. */
+qcdw_status qcdw_op_hop_form(const qcdw_op *op, qcdw_prec prec, int *nt, int *cgroup, int *fma);
 
 /* out_e = M_hat in_e on even sites.  in_e, out_e: [Lt, Lz, Ly, Lx/2, 4, 3]
    complex FP64 (the even half of the fermion layout).  prec selects the

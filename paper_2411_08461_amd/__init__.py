@@ -113,7 +113,7 @@ def load_library(path: str = LIB_PATH):
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_destroy": (None, [p]),
-        "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
         "qcdw_op_matpc_multi": (i, [p, i, i, p, p]),
         "qcdw_invert": (i, [p, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
@@ -381,10 +381,11 @@ def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8,
 
 
 def qcdw_op_hop_form(op: Operator, prec: str = "f64"):
-    """(nt, cgroup): the tuned form of the operator's single-RHS hop in precision prec."""
-    nt, cg = ctypes.c_int(), ctypes.c_int()
-    _check(op.ctx.handle, load_library().qcdw_op_hop_form(op.handle, PREC[prec], ctypes.byref(nt), ctypes.byref(cg)))
-    return nt.value, cg.value
+    """(nt, cgroup, fma): the tuned form of the operator's single-RHS hop in precision prec."""
+    nt, cg, fma = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(op.ctx.handle, load_library().qcdw_op_hop_form(op.handle, PREC[prec], ctypes.byref(nt), ctypes.byref(cg),
+                                                          ctypes.byref(fma)))
+    return nt.value, cg.value, fma.value
 
 
 def qcdw_invert(op: Operator, b, x, params: qcdw_solver_params | None = None, raise_on_error: bool = False):

@@ -196,9 +196,9 @@ qcdw_status qcdw_dslash(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, c
     return QCDW_OK;
 }
 
-// Form of the operator's single-RHS hop in precision prec: sites per thread along t (nt) and
-// c-tiles per group swept along t (cg).  The cached choice for this lattice (code nt + 16 cg),
-// else the fastest candidate timed on scratch vectors.
+// Form of the operator's single-RHS hop in precision prec: sites per thread along t (nt), c-tiles
+// per group swept along t (cg) and the arithmetic form (fma).  The cached choice for this lattice
+// (code nt + 16 cg + 4096 fma), else the fastest candidate timed on scratch vectors.
 static qcdw_status tune_op_hop(qcdw_op* op, int prec)
 {
     qcdw_ctx* ctx = op->ctx;
@@ -211,11 +211,13 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
             if (nct % d == 0) return d;
         return 0;
     };
-    std::vector<int> cand;  // codes nt + 16 cg
+    std::vector<int> cand;  // codes nt + 16 cg + 4096 fma
     auto add = [&](int nt, int cg) {
-        const int code = nt + 16 * cg;
-        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && std::find(cand.begin(), cand.end(), code) == cand.end())
-            cand.push_back(code);
+        for (int f : {0, 1}) {
+            const int code = nt + 16 * cg + 4096 * f;
+            if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && std::find(cand.begin(), cand.end(), code) == cand.end())
+                cand.push_back(code);
+        }
     };
     add(1, 0);
     for (int m : {8, 16, 32})
@@ -226,12 +228,13 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
     }
     auto apply = [&](int code) {
         op->hop_nt[prec] = code % 16;
-        op->hop_cg[prec] = code / 16;
+        op->hop_cg[prec] = (code / 16) % 256;
+        op->hop_fma[prec] = code / 4096;
     };
     auto it = ctx->tune.find(key);
     if (it != ctx->tune.end()) {
-        const int nt = it->second % 16, cg = it->second / 16;
-        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg)) {
+        const int nt = it->second % 16, cg = (it->second / 16) % 256, f = it->second / 4096;
+        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && (f == 0 || f == 1)) {
             apply(it->second);
             return QCDW_OK;
         }
@@ -254,14 +257,15 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
     for (int code : cand) {
         HopArgs a = hop_args(g, 1);
         a.nt = code % 16;
-        a.cgroup = code / 16;
+        a.cgroup = (code / 16) % 256;
+        a.fma = code / 4096;
         a.psi = in.p;
         a.out = out.p;
         a.gauge = v.gauge;
         a.clov = v.Ainv[1];
         for (int rep = 0; rep < 2 && e == hipSuccess; rep++) e = launch_hop(s, prec, v.recon, EPI_CLOV, RED_NONE, a);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int rep = 0; rep < 5 && e == hipSuccess; rep++) e = launch_hop(s, prec, v.recon, EPI_CLOV, RED_NONE, a);
+        for (int rep = 0; rep < 20 && e == hipSuccess; rep++) e = launch_hop(s, prec, v.recon, EPI_CLOV, RED_NONE, a);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0;
@@ -361,7 +365,7 @@ void qcdw_op_destroy(qcdw_op* op)
     delete op;
 }
 
-qcdw_status qcdw_op_hop_form(const qcdw_op* op, qcdw_prec prec, int* nt, int* cgroup)
+qcdw_status qcdw_op_hop_form(const qcdw_op* op, qcdw_prec prec, int* nt, int* cgroup, int* fma)
 {
     if (!op) return QCDW_EINVAL;
     if (!nt || !cgroup) return fail(op->ctx, QCDW_EINVAL, "nt and cgroup must not be NULL");
@@ -369,6 +373,7 @@ qcdw_status qcdw_op_hop_form(const qcdw_op* op, qcdw_prec prec, int* nt, int* cg
         return fail(op->ctx, QCDW_EINVAL, "prec must be F64 or the operator's inner precision");
     *nt = op->hop_nt[prec];
     *cgroup = op->hop_cg[prec];
+    if (fma) *fma = op->hop_fma[prec];
     return QCDW_OK;
 }
 
@@ -510,7 +515,7 @@ struct Solver {
     const int* nbs;              // device hop tiles per problem (batch) or nullptr
     int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse), batch grid, or
                                  // single-RHS sites per thread along t
-    int nt = 1, cg = 0;          // single-RHS hop: sites per thread along t, c-tile group
+    int nt = 1, cg = 0, fma = 0;  // single-RHS hop: sites per thread along t, c-tile group, arithmetic form
     int fuse_nb;                 // largest partials count (all problems of a launch) whose scalars are
                                  // formed in the vector kernels
     Timing tm;
@@ -590,6 +595,7 @@ struct Solver {
         a.nrhs = nprob;
         a.nt = nprob == 1 ? nt : 1;
         a.cgroup = nprob == 1 ? cg : 0;
+        a.fma = nprob == 1 ? fma : 0;
         // the reduction partials of this form must fit the workspace sized for nb_hop_cap
         if (red != RED_NONE && nprob == 1 && hop_blocks_nt(op->g, a.nt, a.cgroup) > nb_hop_cap)
             return hipErrorInvalidValue;
@@ -646,7 +652,8 @@ struct Solver {
         if (nprob == 1) {  // the operator's own choice (tuned when it was created)
             nt = ops[0]->hop_nt[kprec];
             cg = ops[0]->hop_cg[kprec];
-            variant = nt + 16 * cg;
+            fma = ops[0]->hop_fma[kprec];
+            variant = nt + 16 * cg + 4096 * fma;
             nb_hop = hop_blocks_nt(ops[0]->g, nt, cg);
             return QCDW_OK;
         }

@@ -46,6 +46,24 @@ __device__ __forceinline__ cx<T> cmul_conj(cx<T> a, cx<T> b)
 {
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
+// w += a b and w += conj(a) b, one multiply-add per real term (w + a * b would round the product
+// first and add it separately)
+template <typename T>
+__device__ __forceinline__ void cmac(cx<T>& w, cx<T> a, cx<T> b)
+{
+    w.re += a.re * b.re;
+    w.re -= a.im * b.im;
+    w.im += a.re * b.im;
+    w.im += a.im * b.re;
+}
+template <typename T>
+__device__ __forceinline__ void cmac_conj(cx<T>& w, cx<T> a, cx<T> b)
+{
+    w.re += a.re * b.re;
+    w.re += a.im * b.im;
+    w.im += a.re * b.im;
+    w.im -= a.im * b.re;
+}
 template <typename T>
 __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
 

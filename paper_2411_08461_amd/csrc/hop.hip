@@ -18,6 +18,10 @@
 
 #include "hop_common.h"
 
+// arithmetic form of the clover epilogue (see herm_rows): the multiply-add form measured faster
+#ifndef QCDW_CLOV_FMA
+#define QCDW_CLOV_FMA 1
+#endif
 #ifndef QCDW_HOP_WAVES_PER_EU
 #define QCDW_HOP_WAVES_PER_EU 0
 #endif
@@ -84,14 +88,14 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
             cx<T> ox[3], by[3];
 #pragma unroll
             for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(yv[c], 1);
-            herm_rows(win, q & 1, yv, ox, by);
+            herm_rows<QCDW_CLOV_FMA != 0>(win, q & 1, yv, ox, by);
 #pragma unroll
             for (int c = 0; c < 3; c++) outv[c] = by[c] - aa * res[c];
         } else {
             cx<T> ox[3], br[3];
 #pragma unroll
             for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
-            herm_rows(win, q & 1, res, ox, br);
+            herm_rows<QCDW_CLOV_FMA != 0>(win, q & 1, res, ox, br);
             if constexpr (EPI == EPI_CLOV) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) outv[c] = br[c];
@@ -132,8 +136,9 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
 
 // The hop with its epilogue at one site per 4 lanes (site valid or not: every
 // thread of the block calls it); `part` receives the block's reduction partials
-// (RED != RED_NONE).
-template <class P, int R, int EPI, int RED>
+// (RED != RED_NONE).  F: the multiply-add form of the hop arithmetic (hop_rows);
+// which form is faster depends on the lattice, so the operator's tuner picks it.
+template <class P, int R, int EPI, int RED, bool F = false>
 __device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid, double* part)
 {
     using T = typename P::real;
@@ -152,8 +157,8 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid,
         for (int h = 0; h < 4; h++) {
             cx<T> pu[3], pl[3], hv[3];
             load_pair<P>(a.psi, g.Vh, su, sl, L.nbh[h], pu, pl);
-            project(pu, pl, L.cre[h], L.cim[h], hv);
-            hop_apply<P, R>(a.gauge, L, h, hv, acc_u, acc_l);
+            project<F>(pu, pl, L.cs[h], h < 2, hv);
+            hop_apply<F, P, R>(a.gauge, L, h, hv, acc_u, acc_l);
         }
     }
     double v[3] = {0.0, 0.0, 0.0};
@@ -162,11 +167,11 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid,
 }
 
 // One 64-site tile (consecutive eo indices) of the hop with its epilogue.
-template <class P, int R, int EPI, int RED>
+template <class P, int R, int EPI, int RED, bool F = false>
 __device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* part)
 {
     const int site = tile * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
-    hop_site<P, R, EPI, RED>(a, site, site < a.g.Vh, part);
+    hop_site<P, R, EPI, RED, F>(a, site, site < a.g.Vh, part);
 }
 
 // Single-RHS hop, one site per 4 lanes.  With cgroup = G > 0 the tiles are 64
@@ -174,7 +179,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* par
 // t inside each group of G c-tiles: (c-tile in group, then t, then group).  The
 // input slice t is read by the output slices t - 1, t, t + 1, which then run
 // G tiles apart instead of a whole slice apart, so its spinors stay in L2.
-template <class P, int R, int EPI, int RED>
+template <class P, int R, int EPI, int RED, bool F>
 __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
 {
     if (a.stop && *a.stop) return;
@@ -186,9 +191,9 @@ __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
         const int grp = tile / (G * g.Lt), r = tile - grp * G * g.Lt;
         const int t = r / G, ct = grp * G + (r - t * G);
         const int c = ct * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
-        hop_site<P, R, EPI, RED>(a, t * St + c, c < St, part);
+        hop_site<P, R, EPI, RED, F>(a, t * St + c, c < St, part);
     } else {
-        hop_tile<P, R, EPI, RED>(a, tile, part);
+        hop_tile<P, R, EPI, RED, F>(a, tile, part);
     }
 }
 
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
 // of being re-fetched by the tiles of the adjacent t-slices.  Blocks: 64
 // consecutive c; the order is e, then c-tile (within its group of cgroup
 // c-tiles), then chain group tg, then c-tile group.  Requires Lt % (2 NT) == 0.
-template <class P, int R, int EPI, int RED, int NT>
+template <class P, int R, int EPI, int RED, int NT, bool F>
 __global__ __launch_bounds__(256) QCDW_TKERNEL_ATTR void hop_tkernel(HopArgs a)
 {
     if (a.stop && *a.stop) return;
@@ -251,10 +256,10 @@ __global__ __launch_bounds__(256) QCDW_TKERNEL_ATTR void hop_tkernel(HopArgs a)
                 } else {
                     cx<T> pu[3], pl[3];
                     load_pair<P>(a.psi, g.Vh, su, sl, L.nbh[h], pu, pl);
-                    project(pu, pl, L.cre[h], L.cim[h], hv);
-                    if (gq == 1 && h == 2) project(pu, pl, -L.cre[h], -L.cim[h], next);
+                    project<F>(pu, pl, L.cs[h], h < 2, hv);
+                    if (gq == 1 && h == 2) project<F>(pu, pl, -L.cs[h], false, next);
                 }
-                hop_apply<P, R>(a.gauge, L, h, hv, acc_u, acc_l);
+                hop_apply<F, P, R>(a.gauge, L, h, hv, acc_u, acc_l);
             }
             if (gq == 1) {
 #pragma unroll
@@ -319,13 +324,13 @@ __global__ __launch_bounds__(256) void hop_batch_kernel(BatchHopArgs b)
     }
 }
 
-template <class P, int R, int NT>
+template <class P, int R, int NT, bool F>
 static hipError_t launch_hop_nt(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
     dim3 grid(hop_blocks_nt(a.g, NT, a.cgroup)), block(256);
     // with events, they are recorded by the dispatch itself (exact kernel time)
-#define QCDW_HOP_KERNEL(E, D) hop_kernel<P, R, E, D>
-#define QCDW_TKERNEL(E, D) hop_tkernel<P, R, E, D, NT>
+#define QCDW_HOP_KERNEL(E, D) hop_kernel<P, R, E, D, F>
+#define QCDW_TKERNEL(E, D) hop_tkernel<P, R, E, D, NT, F>
 #define QCDW_HOP_CASE(E, D)                                                                            \
     if (epi == E && red == D) {                                                                       \
         if constexpr (NT == 1) {                                                                      \
@@ -349,16 +354,22 @@ static hipError_t launch_hop_nt(hipStream_t s, int epi, int red, const HopArgs& 
     return hipErrorInvalidValue;
 }
 
+template <class P, int R, bool F>
+static hipError_t launch_hop_prf(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
+{
+    switch (a.nt) {
+    case 2: return launch_hop_nt<P, R, 2, F>(s, epi, red, a, e0, e1);
+    case 4: return launch_hop_nt<P, R, 4, F>(s, epi, red, a, e0, e1);
+    case 8: return launch_hop_nt<P, R, 8, F>(s, epi, red, a, e0, e1);
+    default: return launch_hop_nt<P, R, 1, F>(s, epi, red, a, e0, e1);
+    }
+}
+
 template <class P, int R>
 static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
     if (!hop_nt_fits(a.g, a.nt) || !hop_cgroup_fits(a.g, a.cgroup)) return hipErrorInvalidValue;
-    switch (a.nt) {
-    case 2: return launch_hop_nt<P, R, 2>(s, epi, red, a, e0, e1);
-    case 4: return launch_hop_nt<P, R, 4>(s, epi, red, a, e0, e1);
-    case 8: return launch_hop_nt<P, R, 8>(s, epi, red, a, e0, e1);
-    default: return launch_hop_nt<P, R, 1>(s, epi, red, a, e0, e1);
-    }
+    return a.fma ? launch_hop_prf<P, R, true>(s, epi, red, a, e0, e1) : launch_hop_prf<P, R, false>(s, epi, red, a, e0, e1);
 }
 
 template <class P>

@@ -35,7 +35,9 @@ __device__ __forceinline__ void load_link(const void* gauge, long off, long stri
 // window of the reordered packing:
 //   [d0 d1 d2 | L10 L20 L21 | L30 L31 L32 L40 L41 L42 L50 L51 L52 | d3 d4 d5 | L43 L53 L54]
 //   half 0 reads entries 0..26, half 1 reads entries 9..35.
-template <typename T>
+// FMA: every complex multiply-add as four real multiply-adds (fewer instructions; used by the
+// multi-RHS hop, whose loop is bound by vector ALU issue); else the plain complex products.
+template <bool FMA, typename T>
 __device__ __forceinline__ void herm_rows(const T (&win)[27], int h, const cx<T> (&vo)[3], const cx<T> (&vx)[3],
                                           cx<T> (&out)[3])
 {
@@ -62,14 +64,26 @@ __device__ __forceinline__ void herm_rows(const T (&win)[27], int h, const cx<T>
     own[1][2] = conj(l21);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        cx<T> s = {T(0), T(0)};
+        cx<T> s;
+        if constexpr (FMA) {
+            // diagonal entry (real) first, then the rest of the own block
+            s = {own[a][a].re * vo[a].re, own[a][a].re * vo[a].im};
 #pragma unroll
-        for (int b = 0; b < 3; b++) s = s + own[a][b] * vo[b];
+            for (int b = 0; b < 3; b++)
+                if (b != a) cmac(s, own[a][b], vo[b]);
+        } else {
+            s = {T(0), T(0)};
+#pragma unroll
+            for (int b = 0; b < 3; b++) s = s + own[a][b] * vo[b];
+        }
 #pragma unroll
         for (int b = 0; b < 3; b++) {
             // cross block: rows of this half, columns of the other half
             cx<T> cb = h ? cx<T>{Xr[3 * a + b], Xi[3 * a + b]} : cx<T>{Xr[3 * b + a], -Xi[3 * b + a]};
-            s = s + cb * vx[b];
+            if constexpr (FMA)
+                cmac(s, cb, vx[b]);
+            else
+                s = s + cb * vx[b];
         }
         out[a] = s;
     }
@@ -97,13 +111,15 @@ __device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
 
 // The four hops of one lane at one site: neighbour indices (input parity), link
 // offsets, projection coefficients and time-boundary signs.  Hop h = 2 j + dir,
-// mu = 2 gq + j, dir 0 forward / 1 backward.
+// mu = 2 gq + j, dir 0 forward / 1 backward.  The projection coefficient c is a
+// unit number, imaginary for j = 0 (mu = x, z) and real for j = 1 (mu = y, t), so
+// only its nonzero part cs is kept: c = i cs (h < 2) or c = cs (h >= 2).
 template <typename T, int R>
 struct LaneHops {
     int nbh[4];
     long loff[4];  // link_base of each hop's link
     long lstr;     // link_stride
-    T cre[4], cim[4], fsg[4];
+    T cs[4], fsg[4];
 };
 
 template <typename T, int R>
@@ -121,7 +137,7 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
         const int mu = 2 * gq + j;
         int fwd, bwd;
         bool fcross = false, bcross = false;
-        T c_re, c_im;  // projection coefficient of the forward hop
+        T c_s;  // projection coefficient of the forward hop: i c_s (x, z) or c_s (y, t)
         if (j == 0) {
             if (gq == 0) {  // x: the neighbour lies in the same row of the other parity
                 const int row = site - xh;
@@ -129,27 +145,23 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
                 const int xm = (x == 0) ? g.Lx - 1 : x - 1;
                 fwd = row + (xp >> 1);
                 bwd = row + (xm >> 1);
-                c_re = T(0);
-                c_im = T(-1);
+                c_s = T(-1);
             } else {  // z
                 fwd = (z + 1 == g.Lz) ? site - (g.Lz - 1) * Sz : site + Sz;
                 bwd = (z == 0) ? site + (g.Lz - 1) * Sz : site - Sz;
-                c_re = T(0);
-                c_im = k == 0 ? T(-1) : T(1);
+                c_s = k == 0 ? T(-1) : T(1);
             }
         } else {
             if (gq == 0) {  // y
                 fwd = (y + 1 == g.Ly) ? site - (g.Ly - 1) * Sy : site + Sy;
                 bwd = (y == 0) ? site + (g.Ly - 1) * Sy : site - Sy;
-                c_re = k == 0 ? T(1) : T(-1);
-                c_im = T(0);
+                c_s = k == 0 ? T(1) : T(-1);
             } else {  // t
                 fwd = (t + 1 == g.Lt) ? site - (g.Lt - 1) * St : site + St;
                 bwd = (t == 0) ? site + (g.Lt - 1) * St : site - St;
                 fcross = (t + 1 == g.Lt);
                 bcross = (t == 0);
-                c_re = T(-1);
-                c_im = T(0);
+                c_s = T(-1);
             }
         }
         // forward: U_mu(x) psi(x+mu) with (1 - g_mu); backward: U_mu(x-mu)^+ psi(x-mu)
@@ -158,10 +170,8 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
         L.nbh[2 * j + 1] = bwd;
         L.loff[2 * j] = link_base(mu, p, site, Vh, R);
         L.loff[2 * j + 1] = link_base(mu, 1 - p, bwd, Vh, R);
-        L.cre[2 * j] = c_re;
-        L.cim[2 * j] = c_im;
-        L.cre[2 * j + 1] = -c_re;
-        L.cim[2 * j + 1] = -c_im;
+        L.cs[2 * j] = c_s;
+        L.cs[2 * j + 1] = -c_s;
         L.fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
         L.fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
     }
@@ -179,40 +189,65 @@ __device__ __forceinline__ void load_pair(const void* psi, long Vh, int su, int 
     }
 }
 
+// w = W hv with W = U (dir 0) or U^+ (dir 1); acc_u += s w and acc_l += conj(c) s w for the hop's
+// boundary sign s and projection coefficient c (imag: c = i cs, else c = cs).  FMA: written out so
+// that every update is one multiply-add and no product with a zero coefficient is formed; else the
+// plain complex products (the compiler keeps the products with zero, which IEEE arithmetic needs).
+template <bool FMA, typename T>
+__device__ __forceinline__ void hop_rows(const cx<T> (&u)[9], int dir, bool imag, T s, T cs, const cx<T> (&hv)[3],
+                                         cx<T> (&acc_u)[3], cx<T> (&acc_l)[3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        if constexpr (FMA) {
+            cx<T> w = dir == 0 ? u[3 * r] * hv[0] : cmul_conj(u[r], hv[0]);
+#pragma unroll
+            for (int c = 1; c < 3; c++) {
+                if (dir == 0)
+                    cmac(w, u[3 * r + c], hv[c]);
+                else
+                    cmac_conj(w, u[3 * c + r], hv[c]);
+            }
+            const T cf = cs * s;
+            acc_u[r] = {acc_u[r].re + s * w.re, acc_u[r].im + s * w.im};
+            acc_l[r] = imag ? cx<T>{acc_l[r].re + cf * w.im, acc_l[r].im - cf * w.re}
+                            : cx<T>{acc_l[r].re + cf * w.re, acc_l[r].im + cf * w.im};
+        } else {
+            cx<T> w = {T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < 3; c++) w = dir == 0 ? w + u[3 * r + c] * hv[c] : w + cmul_conj(u[3 * c + r], hv[c]);
+            const cx<T> cd = imag ? cx<T>{T(0), -cs} : cx<T>{cs, T(0)};  // conj(c)
+            const cx<T> wr = s * w;
+            acc_u[r] = acc_u[r] + wr;
+            acc_l[r] = acc_l[r] + cd * wr;
+        }
+    }
+}
+
 // W h for hop h with the projected row hv, accumulated into the two output spins
-template <class P, int R>
+template <bool FMA, class P, int R>
 __device__ __forceinline__ void hop_apply(const void* gauge, const LaneHops<typename P::real, R>& L, int h,
                                           const cx<typename P::real> (&hv)[3], cx<typename P::real> (&acc_u)[3],
                                           cx<typename P::real> (&acc_l)[3])
 {
     using T = typename P::real;
-    const int dir = h & 1;
     cx<T> u[9];
     load_link<P, R>(gauge, L.loff[h], L.lstr, u);
-    cx<T> w[3];
-#pragma unroll
-    for (int r = 0; r < 3; r++) {
-        cx<T> sacc = {T(0), T(0)};
-#pragma unroll
-        for (int c = 0; c < 3; c++)
-            sacc = dir == 0 ? sacc + u[3 * r + c] * hv[c] : sacc + cmul_conj(u[3 * c + r], hv[c]);
-        w[r] = sacc;
-    }
-    const cx<T> cd = conj(cx<T>{L.cre[h], L.cim[h]});
-#pragma unroll
-    for (int r = 0; r < 3; r++) {
-        const cx<T> wr = L.fsg[h] * w[r];
-        acc_u[r] = acc_u[r] + wr;
-        acc_l[r] = acc_l[r] + cd * wr;
-    }
+    hop_rows<FMA>(u, h & 1, h < 2, L.fsg[h], L.cs[h], hv, acc_u, acc_l);
 }
 
-template <typename T>
-__device__ __forceinline__ void project(const cx<T> (&pu)[3], const cx<T> (&pl)[3], T cr, T ci, cx<T> (&hv)[3])
+// hv = pu + c pl with c = i cs (imag) or cs
+template <bool FMA, typename T>
+__device__ __forceinline__ void project(const cx<T> (&pu)[3], const cx<T> (&pl)[3], T cs, bool imag, cx<T> (&hv)[3])
 {
-    const cx<T> cc = {cr, ci};
 #pragma unroll
-    for (int c = 0; c < 3; c++) hv[c] = pu[c] + cc * pl[c];
+    for (int c = 0; c < 3; c++) {
+        if constexpr (FMA)
+            hv[c] = imag ? cx<T>{pu[c].re - cs * pl[c].im, pu[c].im + cs * pl[c].re}
+                         : cx<T>{pu[c].re + cs * pl[c].re, pu[c].im + cs * pl[c].im};
+        else
+            hv[c] = pu[c] + (imag ? cx<T>{T(0), cs} : cx<T>{cs, T(0)}) * pl[c];
+    }
 }
 
 

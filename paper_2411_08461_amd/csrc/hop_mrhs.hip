@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
     for (int h = 0; h < 4; h++) {
         L.nbh[h] = 0;
         L.loff[h] = 0;
-        L.cre[h] = L.cim[h] = T(0);
+        L.cs[h] = T(0);
         L.fsg[h] = T(1);
 #pragma unroll
         for (int e = 0; e < 9; e++) ur[h][e] = {T(0), T(0)};
@@ -98,23 +98,11 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
 #pragma unroll
                         for (int c = 0; c < 3; c++) pu[c] = pl[c] = {T(0), T(0)};
                     }
-                    project(pu, pl, L.cre[h], L.cim[h], hv[j]);
+                    project<true>(pu, pl, L.cs[h], h < 2, hv[j]);
                 }
-                const int dir = h & 1;
-                const cx<T> cd = conj(cx<T>{L.cre[h], L.cim[h]});
 #pragma unroll
                 for (int j = 0; j < RS; j++)
-#pragma unroll
-                    for (int rr = 0; rr < 3; rr++) {
-                        cx<T> sacc = {T(0), T(0)};
-#pragma unroll
-                        for (int c = 0; c < 3; c++)
-                            sacc = dir == 0 ? sacc + ur[h][3 * rr + c] * hv[j][c]
-                                            : sacc + cmul_conj(ur[h][3 * c + rr], hv[j][c]);
-                        const cx<T> wr = L.fsg[h] * sacc;
-                        acc2_u[j][rr] = acc2_u[j][rr] + wr;
-                        acc2_l[j][rr] = acc2_l[j][rr] + cd * wr;
-                    }
+                    hop_rows<true>(ur[h], h & 1, h < 2, L.fsg[h], L.cs[h], hv[j], acc2_u[j], acc2_l[j]);
             }
         }
 #pragma unroll
@@ -144,7 +132,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
             cx<T> ox[3], br[3];
 #pragma unroll
             for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
-            herm_rows(win, q & 1, res, ox, br);
+            herm_rows<true>(win, q & 1, res, ox, br);
             const T aa = (T)a.a;
 #pragma unroll
             for (int c = 0; c < 3; c++) outv[c] = (EPI == EPI_CLOV) ? br[c] : yv[c] - aa * br[c];

@@ -258,8 +258,9 @@ struct qcdw_op {
     int recon = 12;
     PoolBuf gauge64, gauge_lo;
     PoolBuf Ainv64[2], Ainv_lo[2], A64[2];
-    int hop_nt[4] = {1, 1, 1, 1};  // single-RHS hop, per precision (tuned): sites per thread along t
-    int hop_cg[4] = {0, 0, 0, 0};  //   and c-tiles per group swept along t (0: none)
+    int hop_nt[4] = {1, 1, 1, 1};  // single-RHS hop, per precision (tuned): sites per thread along t,
+    int hop_cg[4] = {0, 0, 0, 0};  //   c-tiles per group swept along t (0: none)
+    int hop_fma[4] = {0, 0, 0, 0};  //   and the arithmetic form (1: multiply-add form)
     Workspace ws;                  // single- and multi-RHS solves
 };
 
@@ -304,13 +305,14 @@ inline HopArgs hop_args(const Geom& g, int parity)
 }
 
 // out_e = M_hat in_e = in_e - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe in_e, with an optional fused reduction
-// (hop_blocks_nt(op->g, op->hop_nt[v.prec], op->hop_cg[v.prec]) partials)
+// (hop_blocks_nt(op->g, op->hop_nt[v.prec], op->hop_cg[v.prec]) partials); the operator's tuned form
 inline hipError_t matpc(hipStream_t s, const qcdw_op* op, const PrecView& v, const void* in, void* out, void* tmp_o, int red,
                  const void* w, double* partials, const int* stop)
 {
     HopArgs a = hop_args(op->g, 1);
     a.nt = op->hop_nt[v.prec];
     a.cgroup = op->hop_cg[v.prec];
+    a.fma = op->hop_fma[v.prec];
     a.psi = in;
     a.out = tmp_o;
     a.gauge = v.gauge;
@@ -321,6 +323,7 @@ inline hipError_t matpc(hipStream_t s, const qcdw_op* op, const PrecView& v, con
     HopArgs b = hop_args(op->g, 0);
     b.nt = op->hop_nt[v.prec];
     b.cgroup = op->hop_cg[v.prec];
+    b.fma = op->hop_fma[v.prec];
     b.psi = tmp_o;
     b.out = out;
     b.gauge = v.gauge;

@@ -45,6 +45,7 @@ struct HopArgs {
     const int* stop;    // if non-null and *stop != 0 the launch does nothing
     int nt;             // single-RHS hop: output sites per thread along t (1, 2, 4 or 8; 0 means 1)
     int cgroup;         // single-RHS hop: c-tiles per group swept along t (0: no grouping)
+    int fma;            // single-RHS hop: multiply-add form of the hop arithmetic (0 or 1)
 };
 
 // one problem of a batched solve (device table entry); reconstruct-12 operators

@@ -152,23 +152,25 @@ def test_matpc_low_precision_error_bounded(ctx, prec, bound):
     op.close()
 
 
-def _forced_nt_context(tmp_path, monkeypatch, L, nt, cg=0):
+def _forced_nt_context(tmp_path, monkeypatch, L, nt, cg=0, fma=0):
     """A context whose tuning cache fixes the single-RHS hop's form: nt sites per thread along t,
-    and groups of cg c-tiles swept along t."""
-    cache = tmp_path / f"tune_nt{nt}_cg{cg}_{'x'.join(map(str, L))}.txt"
-    cache.write_text("".join(f"hop_nt/p{p}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {nt + 16 * cg}\n" for p in range(4)))
+    groups of cg c-tiles swept along t, and the arithmetic form."""
+    cache = tmp_path / f"tune_nt{nt}_cg{cg}_f{fma}_{'x'.join(map(str, L))}.txt"
+    cache.write_text("".join(f"hop_nt/p{p}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {nt + 16 * cg + 4096 * fma}\n"
+                             for p in range(4)))
     monkeypatch.setenv("QCDW_TUNE_CACHE", str(cache))
     return q.Context(0)
 
 
 @pytest.mark.parametrize("L", [(8, 8, 8, 16), (6, 4, 2, 8), (10, 6, 4, 8)])
-@pytest.mark.parametrize("nt,cg", [(2, 0), (4, 0), (1, 1), (1, 2), (2, 1), (4, 2)])
-def test_t_stepping_matpc(tmp_path, monkeypatch, L, nt, cg):
+@pytest.mark.parametrize("nt,cg,fma", [(2, 0, 0), (4, 0, 0), (1, 1, 0), (1, 2, 0), (2, 1, 0), (4, 2, 0),
+                                       (1, 0, 1), (2, 0, 1), (4, 0, 1), (1, 1, 1), (2, 1, 1)])
+def test_t_stepping_matpc(tmp_path, monkeypatch, L, nt, cg, fma):
     """M_hat through the other single-RHS hop forms (nt sites per thread along t; tiles of one
-    t-slice swept along t in groups of cg c-tiles) equals the oracle to 1e-13 in FP64 and the plain
-    one-site-per-thread kernel to rounding in every precision (the same operations per site,
-    contracted into FMAs differently); lattices with t-slices of several tiles, of a partial tile,
-    and a ragged last tile."""
+    t-slice swept along t in groups of cg c-tiles; the multiply-add arithmetic form) equals the
+    oracle to 1e-13 in FP64 and the plain one-site-per-thread kernel to rounding in every
+    precision (the same operations per site, contracted into FMAs differently); lattices with
+    t-slices of several tiles, of a partial tile, and a ragged last tile."""
     nct = (L[0] // 2 * L[1] * L[2] + 63) // 64
     if nct % max(cg, 1) or L[3] % (2 * nt):
         pytest.skip("form does not fit this lattice")
@@ -177,21 +179,21 @@ def test_t_stepping_matpc(tmp_path, monkeypatch, L, nt, cg):
     Vh = int(np.prod(L)) // 2
     xe = dev(li.gaussian_source(L, 42).reshape(-1, 4, 3)[:Vh].copy())
     outs = {}
-    for n, g in ((1, 0), (nt, cg)):
-        c = _forced_nt_context(tmp_path, monkeypatch, L, n, g)
+    for n, g, f in ((1, 0, 0), (nt, cg, fma)):
+        c = _forced_nt_context(tmp_path, monkeypatch, L, n, g, f)
         for prec in ("f64", "bf16", "f16", "f32"):
             op = q.Operator(c, q.make_lattice(L), dev(U), kappa, csw, prec, 12)
-            assert q.qcdw_op_hop_form(op, "f64") == (n, g) and q.qcdw_op_hop_form(op, prec) == (n, g)
+            assert q.qcdw_op_hop_form(op, "f64") == (n, g, f) and q.qcdw_op_hop_form(op, prec) == (n, g, f)
             for pr in ("f64", prec):
                 out = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
                 q.qcdw_op_matpc(op, pr, xe, out)
-                outs[(n + 16 * g, prec, pr)] = host(out)
+                outs[(n + 16 * g + 4096 * f, prec, pr)] = host(out)
             op.close()
         torch.cuda.synchronize()
         c.close()
     Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), kappa, csw)
     expect = oracle.schur_matpc(L, U, Ainv, host(xe), kappa)
-    code = nt + 16 * cg
+    code = nt + 16 * cg + 4096 * fma
     assert rel(outs[(code, "f64", "f64")], expect) < 1e-13
     bound = {"f64": 1e-14, "f32": 1e-6, "f16": 2e-3, "bf16": 1e-2}
     for key, val in outs.items():
@@ -590,13 +592,14 @@ def test_mixed_solve_escalates_near_the_critical_kappa(ctx):
     op.close()
 
 
-@pytest.mark.parametrize("nt,cg", [(1, 0), (2, 0), (4, 0), (1, 1), (2, 1)])
-def test_t_stepping_hop_in_solves(tmp_path, monkeypatch, nt, cg):
-    """Solves whose single-RHS hops take nt sites per thread along t (forced through the tuning
-    cache) reach an oracle-checked true residual <= 1e-10, in FP64 and BF16-mixed solves, on a
-    lattice whose t-slices are several tiles and one whose t-slice is a partial tile."""
+@pytest.mark.parametrize("nt,cg,fma", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 0), (1, 0, 1), (2, 1, 1)])
+def test_t_stepping_hop_in_solves(tmp_path, monkeypatch, nt, cg, fma):
+    """Solves whose single-RHS hops take a forced form (nt sites per thread along t, slice groups,
+    arithmetic form; through the tuning cache) reach an oracle-checked true residual <= 1e-10, in
+    FP64 and BF16-mixed solves, on a lattice whose t-slices are several tiles and one whose
+    t-slice is a partial tile."""
     for L, eps, seed in (((8, 8, 8, 16), 0.25, 31), ((6, 4, 2, 8), 0.3, 32)):
-        c = _forced_nt_context(tmp_path, monkeypatch, L, nt, cg)
+        c = _forced_nt_context(tmp_path, monkeypatch, L, nt, cg, fma)
         U = _gauge(L, eps, seed)
         b = li.gaussian_source(L, seed + 100)
         kappa, csw = 0.121, 1.0
