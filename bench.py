@@ -316,17 +316,18 @@ def kernel_sources_sha256():
 
 def measured_traffic(form):
     """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
-    profile of this workload, if it was taken from the current kernel sources with the same hop
-    form; otherwise None."""
+    profile of this workload: the record taken from the current kernel sources with the same hop
+    form, if there is one; otherwise None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            line = next(ln for ln in f if ln.startswith("traffic-json: "))
-        rec = json.loads(line[len("traffic-json: "):])
-    except (OSError, StopIteration, ValueError):
+            recs = [json.loads(ln[len("traffic-json: "):]) for ln in f if ln.startswith("traffic-json: ")]
+    except (OSError, ValueError):
         return None
-    if rec.get("sources_sha256") != kernel_sources_sha256() or [rec.get("nt"), rec.get("cgroup"), rec.get("fma")] != list(form):
-        return None
-    return int(rec["read_bytes"] + rec["write_bytes"])
+    sha = kernel_sources_sha256()
+    for rec in recs:
+        if rec.get("sources_sha256") == sha and [rec.get("nt"), rec.get("cgroup"), rec.get("fma")] == list(form):
+            return int(rec["read_bytes"] + rec["write_bytes"])
+    return None
 
 
 def stream_probe(torch):
