@@ -51,8 +51,12 @@ def lib():
         _lib = ctypes.CDLL(_LIB)
         d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
         _lib.orc_hop.argtypes = [p, i, p, p, p, i]
+        _lib.orc_hop_w.argtypes = [p, i, p, p, p, i, p]
         _lib.orc_clover_build.argtypes = [p, p, p]
         _lib.orc_clover_build.restype = d
+        _lib.orc_clover_build_w.argtypes = [p, p, p, d, d]
+        _lib.orc_clover_build_w.restype = d
+        _lib.orc_dirac_w.argtypes = [p, i, p, p, p, p, d, d, p]
         _lib.orc_packed_apply.argtypes = [p, p, p, p]
         _lib.orc_clover_apply.argtypes = [p, p, p, p, d, d]
         _lib.orc_clover_invert.argtypes = [p, p, d, d, p]
@@ -150,30 +154,55 @@ def parity_mask(L, parity: int) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 
-def hop(L, U, psi, t_bc: int = 1, out_parity: int = -1) -> np.ndarray:
-    """H psi = sum_mu (1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu).
+def hop(L, U, psi, t_bc: int = 1, out_parity: int = -1, weights=None) -> np.ndarray:
+    """H psi = sum_mu w_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu)].
 
     Full-lattice fields in the paper layout; with out_parity >= 0 only the
     sites of that parity are computed (the rest are zero), which is the
     parity-to-parity block H_{p, 1-p} when psi vanishes on parity p.
+    weights: w_mu for mu = x, y, z, t (default all 1; the anisotropic action of
+    Sec. III.B, Eq. "clover", has w = (nu/xi_0, nu/xi_0, nu/xi_0, 1)).
     """
     U, psi = _c128(U), _c128(psi)
     out = np.empty_like(psi)
-    lib().orc_hop(_ptr(_dims(L)), int(t_bc), _ptr(U), _ptr(psi), _ptr(out), int(out_parity))
+    if weights is None:
+        lib().orc_hop(_ptr(_dims(L)), int(t_bc), _ptr(U), _ptr(psi), _ptr(out), int(out_parity))
+    else:
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        lib().orc_hop_w(_ptr(_dims(L)), int(t_bc), _ptr(U), _ptr(psi), _ptr(out), int(out_parity), _ptr(w))
     return out
 
 
-def clover_build(L, U, return_offblock: bool = False):
+def aniso_weights(xi_0: float, nu: float) -> np.ndarray:
+    """Hop weights of the anisotropic clover action (Sec. III.B, Eq. "clover"): nu/xi_0 on the
+    three spatial directions, 1 on t."""
+    r = nu / xi_0
+    return np.array([r, r, r, 1.0])
+
+
+def aniso_kappa(m_0: float, xi_0: float, nu: float) -> float:
+    """kappa from the bare mass of the anisotropic action: 1/kappa = 2 (m_0 + 1 + 3 nu/xi_0) (Sec. III.B)."""
+    return 1.0 / (2.0 * (m_0 + 1.0 + 3.0 * nu / xi_0))
+
+
+def clover_build(L, U, return_offblock: bool = False, plane_weights=None):
     """Packed C = sum_{mu<nu} sigma_{mu nu} F_{mu nu}, [2,Lt,Lz,Ly,Lx/2,2,36] reals.
 
     F_{mu nu} = (Q - Q^+)/8 traceless, Q the four-leaf sum.  The trace removal
     and the overall sign are readings of Eq. "clover" (pinned by the
     single-link closed form and the invariants in the tests).
+    plane_weights = (wt, ws) weights the planes (i, t) by wt and the spatial
+    planes by ws: the anisotropic action (Sec. III.B) has C = c_SW^t sum sigma_i4
+    F_i4 + (c_SW^r / xi_0) sum sigma_ij F_ij, used with c_SW = 1.
     """
     U = _c128(U)
     V = int(np.prod(L))
     clover = np.empty((V, 2, 36))
-    off = lib().orc_clover_build(_ptr(_dims(L)), _ptr(U), _ptr(clover))
+    if plane_weights is None:
+        off = lib().orc_clover_build(_ptr(_dims(L)), _ptr(U), _ptr(clover))
+    else:
+        wt, ws = plane_weights
+        off = lib().orc_clover_build_w(_ptr(_dims(L)), _ptr(U), _ptr(clover), float(wt), float(ws))
     clover = clover.reshape(packed_shape(L))
     return (clover, off) if return_offblock else clover
 
@@ -230,12 +259,18 @@ def clover_invert(L, clover, kappa: float, csw: float):
     return inv, int(bad)
 
 
-def dirac(L, U, clover, psi, kappa: float, csw: float, t_bc: int = 1) -> np.ndarray:
-    """M psi = A psi - kappa H psi on the full lattice."""
+def dirac(L, U, clover, psi, kappa: float, csw: float, t_bc: int = 1, weights=None) -> np.ndarray:
+    """M psi = A psi - kappa H psi on the full lattice (weights: hop weights per direction, as in hop)."""
     U, psi = _c128(U), _c128(psi)
     clover = np.ascontiguousarray(clover, dtype=np.float64)
     out = np.empty_like(psi)
-    lib().orc_dirac(_ptr(_dims(L)), int(t_bc), _ptr(U), _ptr(clover), _ptr(psi), _ptr(out), float(kappa), float(csw))
+    if weights is None:
+        lib().orc_dirac(_ptr(_dims(L)), int(t_bc), _ptr(U), _ptr(clover), _ptr(psi), _ptr(out), float(kappa),
+                        float(csw))
+    else:
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        lib().orc_dirac_w(_ptr(_dims(L)), int(t_bc), _ptr(U), _ptr(clover), _ptr(psi), _ptr(out), float(kappa),
+                          float(csw), _ptr(w))
     return out
 
 
@@ -258,15 +293,15 @@ def _restrict(L, full, parity):
     return np.asarray(full).reshape(V, 4, 3)[parity * (V // 2) : (parity + 1) * (V // 2)].copy()
 
 
-def schur_matpc(L, U, clover_inv, psi_e, kappa: float, t_bc: int = 1):
+def schur_matpc(L, U, clover_inv, psi_e, kappa: float, t_bc: int = 1, weights=None):
     """M_hat psi_e = psi_e - kappa^2 A_ee^{-1} H_eo A_oo^{-1} H_oe psi_e.
 
-    psi_e: (Vh, 4, 3) even-site field.  clover_inv: packed A^{-1}.
+    psi_e: (Vh, 4, 3) even-site field.  clover_inv: packed A^{-1}.  weights: hop weights (see hop).
     """
     full = _embed(L, psi_e, 0)
-    t = hop(L, U, full, t_bc, out_parity=1)
+    t = hop(L, U, full, t_bc, out_parity=1, weights=weights)
     t = packed_apply(L, clover_inv, t)
-    t = hop(L, U, t, t_bc, out_parity=0)
+    t = hop(L, U, t, t_bc, out_parity=0, weights=weights)
     t = packed_apply(L, clover_inv, t)
     return np.asarray(psi_e).reshape(-1, 4, 3) - kappa * kappa * _restrict(L, t, 0)
 

@@ -147,9 +147,12 @@ static const cplx *link(const cplx *U, long V, int mu, long site) { return U + (
 /*
  * out = H psi on every site whose parity equals out_parity (or on all sites
  * when out_parity < 0); other output sites are set to zero.  t_bc multiplies
- * every link that crosses the t = Lt-1 -> 0 boundary.
+ * every link that crosses the t = Lt-1 -> 0 boundary.  w[mu] weights the two
+ * hops of direction mu (the anisotropic operator of Sec. III.B weights the
+ * spatial ones by nu / xi_0); w = NULL means all weights 1.
  */
-void orc_hop(const int L[4], int t_bc, const double *U_, const double *psi_, double *out_, int out_parity)
+void orc_hop_w(const int L[4], int t_bc, const double *U_, const double *psi_, double *out_, int out_parity,
+               const double *w)
 {
     const cplx *U = (const cplx *)U_;
     const cplx *psi = (const cplx *)psi_;
@@ -178,10 +181,10 @@ void orc_hop(const int L[4], int t_bc, const double *U_, const double *psi_, dou
                     } else {
                         mat3_dagger(link(U, V, mu, j), u);
                     }
-                    double sign = 1.0;
+                    double sign = w ? w[mu] : 1.0;
                     if (mu == 3 && t_bc < 0) {
-                        if (dir == 0 && c[3] == L[3] - 1) sign = -1.0;
-                        if (dir == 1 && c[3] == 0) sign = -1.0;
+                        if (dir == 0 && c[3] == L[3] - 1) sign = -sign;
+                        if (dir == 1 && c[3] == 0) sign = -sign;
                     }
                     /* colour: chi[s][a] = sum_b u[a][b] psi_j[s][b] */
                     cplx chi[4][3];
@@ -205,6 +208,11 @@ void orc_hop(const int L[4], int t_bc, const double *U_, const double *psi_, dou
         for (int s = 0; s < 4; s++)
             for (int a = 0; a < 3; a++) out[i * 12 + s * 3 + a] = acc[s][a];
     }
+}
+
+void orc_hop(const int L[4], int t_bc, const double *U_, const double *psi_, double *out_, int out_parity)
+{
+    orc_hop_w(L, t_bc, U_, psi_, out_, out_parity, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -320,7 +328,18 @@ static void unpack_block(const double *p, cplx B[6][6])
  * Returns the largest magnitude found in the off-chirality blocks (which a
  * chiral basis makes exactly zero) so tests can check it.
  */
+double orc_clover_build_w(const int L[4], const double *U_, double *clover, double wt, double ws);
 double orc_clover_build(const int L[4], const double *U_, double *clover)
+{
+    return orc_clover_build_w(L, U_, clover, 1.0, 1.0);
+}
+
+/*
+ * The same with the planes weighted: wt for the three planes (i, t) and ws for
+ * the three spatial planes (i, j) -- the anisotropic clover term of Sec. III.B
+ * has wt = c_SW^t and ws = c_SW^r / xi_0 (with the overall c_SW then 1).
+ */
+double orc_clover_build_w(const int L[4], const double *U_, double *clover, double wt, double ws)
 {
     const cplx *U = (const cplx *)U_;
     long V = volume(L);
@@ -345,10 +364,12 @@ double orc_clover_build(const int L[4], const double *U_, double *clover)
             for (int nu = mu + 1; nu < 4; nu++) {
                 cplx F[9];
                 field_strength(L, U, V, c, mu, nu, F);
+                const double wgt = nu == 3 ? wt : ws;
                 for (int s = 0; s < 4; s++)
                     for (int sp = 0; sp < 4; sp++)
                         for (int a = 0; a < 3; a++)
-                            for (int b = 0; b < 3; b++) C[3 * s + a][3 * sp + b] += sigma[mu][nu][s][sp] * F[3 * a + b];
+                            for (int b = 0; b < 3; b++)
+                                C[3 * s + a][3 * sp + b] += wgt * sigma[mu][nu][s][sp] * F[3 * a + b];
             }
         for (int r = 0; r < 12; r++)
             for (int q = 0; q < 12; q++)
@@ -454,18 +475,24 @@ long orc_clover_invert(const int L[4], const double *clover, double kappa, doubl
 /* Full Wilson-clover operator                                        */
 /* ------------------------------------------------------------------ */
 
-/* out = M psi = A psi - kappa H psi on the full lattice. */
-void orc_dirac(const int L[4], int t_bc, const double *U, const double *clover, const double *psi, double *out_,
-               double kappa, double csw)
+/* out = M psi = A psi - kappa H psi on the full lattice (w: hop weights per direction, or NULL). */
+void orc_dirac_w(const int L[4], int t_bc, const double *U, const double *clover, const double *psi, double *out_,
+                 double kappa, double csw, const double *w)
 {
     long V = volume(L);
     cplx *out = (cplx *)out_;
     cplx *h = malloc(sizeof(cplx) * V * 12);
-    orc_hop(L, t_bc, U, psi, (double *)h, -1);
+    orc_hop_w(L, t_bc, U, psi, (double *)h, -1, w);
     orc_clover_apply(L, clover, psi, out_, kappa, csw);
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < V * 12; k++) out[k] -= kappa * h[k];
     free(h);
+}
+
+void orc_dirac(const int L[4], int t_bc, const double *U, const double *clover, const double *psi, double *out_,
+               double kappa, double csw)
+{
+    orc_dirac_w(L, t_bc, U, clover, psi, out_, kappa, csw, NULL);
 }
 
 /* ------------------------------------------------------------------ */
