@@ -14,9 +14,10 @@ Beside the timed steps (not part of them) the line carries the other
 workloads of the same metric: "propagator" (24^3 x 64, 12 point sources solved
 together with the multi-RHS hop in BF16 against 12 separate FP64 solves),
 "batch" (48 uneven problems in one persistent batched solve against a loop of
-single solves, solves/s) and "learned" (32^3 x 64 near the critical kappa:
+single solves, solves/s), "learned" (32^3 x 64 near the critical kappa:
 FGMRES(32) with the trained gauge-covariant preconditioner against plain FP64
-and mixed BiCGStab).  ``--bisect-kappa`` finds that kappa.
+and mixed BiCGStab) and "aniso" (the paper's anisotropic example action on
+16^3 x 32 with antiperiodic time).  ``--bisect-kappa`` finds that kappa.
 
 Printed line (rank 0): metric/value = algorithmic bytes of the Krylov
 iterations (byte model per iteration and precision, counted with the actual
@@ -80,7 +81,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-lattice", default="24,24,24,64",
                     help="also time the hop kernel on this lattice (empty to skip)")
-    ap.add_argument("--sections", default="propagator,batch,learned",
+    ap.add_argument("--sections", default="propagator,batch,learned,aniso",
                     help="comma-separated extra workloads to run after the timed steps (empty: none)")
     ap.add_argument("--bisect-kappa", action="store_true",
                     help="find the 32^3x64 kappa at which FP64 BiCGStab first needs >= 2000 iterations, then exit")
@@ -571,8 +572,46 @@ def learned(q, li, np, torch, ctx, fields, args):
     return out
 
 
+ANISO_ACTION = {"xi_0": 2.464, "nu": 0.95, "m_0": 0.3, "csw_t": 0.91, "csw_r": 1.07}  # the paper's example
+
+
+def aniso_jobs(li):
+    return [((16, 16, 16, 32), 0.2, 7)]
+
+
+def aniso(q, li, np, torch, ctx, fields, args):
+    """The anisotropic clover action of the paper's example (Sec. III.B) on 16^3x32 with antiperiodic t:
+    FP64 and BF16-mixed solves (graphs on, timed), and the FP64 hop bandwidth from an instrumented solve."""
+    a = ANISO_ACTION
+    L = (16, 16, 16, 32)
+    Vh = int(np.prod(L)) // 2
+    kappa = 1.0 / (2.0 * (a["m_0"] + 1.0 + 3.0 * a["nu"] / a["xi_0"]))
+    op = q.Operator(ctx, q.make_lattice(L, -1), torch.from_numpy(fields[0]).cuda(), kappa, 0.0, "bf16", 12,
+                    aniso=(a["xi_0"], a["nu"], a["csw_t"], a["csw_r"]))
+    b = torch.from_numpy(li.gaussian_source(L, 1007)).cuda()
+    x = torch.zeros_like(b)
+    out = {"workload": "16^3x32, antiperiodic t, xi_0 2.464, nu 0.95, m_0 0.3, csw_t 0.91, csw_r 1.07, eps 0.2, "
+                       "Gaussian source", "kappa": round(kappa, 6)}
+    for prec in ("f64", "bf16"):
+        prm = q.make_params(tol=1e-10, maxiter=20000, inner=prec, delta=0.1)
+        q.qcdw_invert(op, b, x, prm)  # warm-up: graph capture
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = q.qcdw_invert(op, b, x, prm)
+        torch.cuda.synchronize()
+        out[prec] = dict(_solve_summary([info]), time_ms=round(1e3 * (time.perf_counter() - t0), 3))
+        x.zero_()
+    info = q.qcdw_invert(op, b, x, q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True))
+    us = 1e3 * info.hop_ms[0] / max(info.n_hop[0], 1)
+    out["hop_f64"] = {"gbs": round(hop_a_bytes("f64") * Vh / us / 1e3, 1), "avg_launch_us": round(us, 2),
+                      "form": q.qcdw_op_hop_form(op, "f64")}
+    op.close()
+    return out
+
+
 SECTIONS = {"propagator": (propagator_jobs, propagator), "batch": (batch_jobs, batch),
-            "learned": (learned_jobs, learned)}
+            "learned": (learned_jobs, learned), "aniso": (aniso_jobs, aniso)}
 
 
 def bisect_kappa(q, li, np, torch):

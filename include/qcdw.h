@@ -165,6 +165,18 @@ qcdw_status qcdw_dslash(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, c
    plus copies in `inner` storage precision.  U is not referenced afterwards. */
 qcdw_status qcdw_op_create(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, double kappa, double csw,
                            qcdw_prec inner, int recon, qcdw_op **op);
+
+/* The anisotropic clover operator of the paper's example action (Sec. III.B, Eq. "clover"):
+     M = A - kappa [H_t + (nu / xi_0) sum_i H_i],
+     A = 1 - kappa [csw_t sum_i sigma_i4 F_i4 + (csw_r / xi_0) sum_{i<j} sigma_ij F_ij],
+   with H_mu the two hops of direction mu (i = x, y, z spatial) and, in the paper's convention,
+   kappa = 1 / (2 (m_0 + 1 + 3 nu / xi_0)) (the caller passes kappa).  xi_0 = nu = 1 and
+   csw_t = csw_r = csw is the isotropic operator of qcdw_op_create.  Arguments, ownership and the
+   precision handling are those of qcdw_op_create; every operator call (matpc, solves, multi-RHS,
+   batches, FGMRES) then uses the anisotropic operator.  QCDW_EINVAL for xi_0 or nu not positive
+   and finite. */
+qcdw_status qcdw_op_create_aniso(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, double kappa, double xi_0,
+                                 double nu, double csw_t, double csw_r, qcdw_prec inner, int recon, qcdw_op **op);
 void qcdw_op_destroy(qcdw_op *op);
 
 /* The form of the operator's single-RHS parity hop in precision prec (F64 or the inner

@@ -34,7 +34,7 @@ PREC = {"f64": QCDW_F64, "f32": QCDW_F32, "bf16": QCDW_BF16, "f16": QCDW_F16}
 EXPORTED = (
     "qcdw_solver_params_default", "qcdw_ctx_create", "qcdw_ctx_destroy", "qcdw_last_error", "qcdw_ctx_set_stream",
     "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_op_create",
-    "qcdw_op_destroy", "qcdw_op_hop_form", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
+    "qcdw_op_create_aniso", "qcdw_op_destroy", "qcdw_op_hop_form", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
     "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "qcdw_hop": (i, [p, lat, p, p, p, i]),
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
+        "qcdw_op_create_aniso": (i, [p, lat, p, d, d, d, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_destroy": (None, [p]),
         "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
@@ -282,17 +283,27 @@ class Operator:
 
     _rank = 2  # destroyed after the nets and batches that use it
 
-    def __init__(self, ctx: Context, lat: qcdw_lattice, U, kappa: float, csw: float, inner="f64", recon: int = 12):
+    def __init__(self, ctx: Context, lat: qcdw_lattice, U, kappa: float, csw: float, inner="f64", recon: int = 12,
+                 aniso=None):
+        """aniso = (xi_0, nu, csw_t, csw_r): the anisotropic clover operator (qcdw_op_create_aniso; csw is
+        then not used)."""
         self.ctx = ctx
         self.lat = lat
         self.kappa = kappa
         self.csw = csw
+        self.aniso = aniso
         self.inner = PREC[inner] if isinstance(inner, str) else int(inner)
         self.volume = _volume(lat)
         _need(U, 36 * self.volume, "U")
         h = ctypes.c_void_p()
-        st = load_library().qcdw_op_create(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
-                                           float(kappa), float(csw), self.inner, int(recon), ctypes.byref(h))
+        if aniso is None:
+            st = load_library().qcdw_op_create(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                               float(kappa), float(csw), self.inner, int(recon), ctypes.byref(h))
+        else:
+            xi_0, nu, csw_t, csw_r = (float(v) for v in aniso)
+            st = load_library().qcdw_op_create_aniso(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                                     float(kappa), xi_0, nu, csw_t, csw_r, self.inner, int(recon),
+                                                     ctypes.byref(h))
         _check(ctx.handle, st)
         self.handle = h
         self._children = weakref.WeakSet()

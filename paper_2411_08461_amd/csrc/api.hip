@@ -287,8 +287,10 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
     return QCDW_OK;
 }
 
-qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, double kappa, double csw,
-                           qcdw_prec inner, int recon, qcdw_op** op_out)
+// The operator M = A - kappa H with A = 1 - kappa csw C, C = wt sum_i sigma_i4 F_i4 + ws sum_{i<j}
+// sigma_ij F_ij and the spatial hops of H weighted by xs (isotropic: wt = ws = xs = 1).
+static qcdw_status op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, double kappa, double csw,
+                             double wt, double ws, double xs, qcdw_prec inner, int recon, qcdw_op** op_out)
 {
     if (!ctx) return QCDW_EINVAL;
     if (!op_out) return fail(ctx, QCDW_EINVAL, "op pointer is NULL");
@@ -297,6 +299,9 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
     Geom g;
     CHK(check_lattice(ctx, lat, g));
     CHK(check_dev(ctx, U, "U"));
+    if (!(xs > 0.0) || !std::isfinite(xs) || !std::isfinite(wt) || !std::isfinite(ws))
+        return fail(ctx, QCDW_EINVAL, "anisotropy coefficients must be finite (and nu / xi_0 positive)");
+    g.xs = xs;
     if (recon != 12 && recon != 18) return fail(ctx, QCDW_EINVAL, "recon must be 12 or 18, got %d", recon);
     if (inner < QCDW_F64 || inner > QCDW_F16) return fail(ctx, QCDW_EINVAL, "bad inner precision %d", (int)inner);
     if (!(kappa > 0.0) || !std::isfinite(kappa) || !std::isfinite(csw))
@@ -323,7 +328,7 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
         if (op->Ainv64[p].alloc(clov_reals(g.Vh) * 8) != hipSuccess || op->A64[p].alloc(clov_reals(g.Vh) * 8) != hipSuccess)
             return cleanup(fail(ctx, QCDW_ENOMEM, "out of device memory creating the operator"));
     hipError_t e = launch_pack_gauge(s, F64, recon, g, U, op->gauge64.p);
-    if (e == hipSuccess) e = launch_clover_build(s, g, U, clov.p);
+    if (e == hipSuccess) e = launch_clover_build(s, g, U, clov.p, wt, ws);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->dev_int, 0, sizeof(int), s);
     if (e == hipSuccess) e = launch_clover_invert(s, g, clov.p, kappa, csw, inv.p, ctx->dev_int);
     if (e == hipSuccess) e = launch_clover_to_A(s, g, clov.p, kappa, csw, Ap.p);
@@ -355,6 +360,20 @@ qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U
     }
     *op_out = op;
     return QCDW_OK;
+}
+
+qcdw_status qcdw_op_create(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, double kappa, double csw,
+                           qcdw_prec inner, int recon, qcdw_op** op_out)
+{
+    return op_create(ctx, lat, U, kappa, csw, 1.0, 1.0, 1.0, inner, recon, op_out);
+}
+
+qcdw_status qcdw_op_create_aniso(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, double kappa, double xi_0,
+                                 double nu, double csw_t, double csw_r, qcdw_prec inner, int recon, qcdw_op** op_out)
+{
+    if (!(xi_0 > 0.0) || !(nu > 0.0) || !std::isfinite(xi_0) || !std::isfinite(nu))
+        return ctx ? fail(ctx, QCDW_EINVAL, "xi_0 and nu must be positive and finite") : QCDW_EINVAL;
+    return op_create(ctx, lat, U, kappa, 1.0, csw_t, csw_r / xi_0, nu / xi_0, inner, recon, op_out);
 }
 
 void qcdw_op_destroy(qcdw_op* op)

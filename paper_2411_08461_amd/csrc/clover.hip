@@ -142,16 +142,26 @@ __device__ M3 field_strength(const double2* U, const Geom& g, const int (&c)[4],
 //   lower (spins 2,3): B00 = -iF01 - iF23   B11 = iF01 + iF23
 //                      B01 = -F02 - iF03 - iF12 + F13   B10 = F02 - iF03 - iF12 - F13
 // and the 6x6 chirality block is [[B00, B01], [B10, B11]] in colour-inner order.
-__global__ void k_clover_build(const double2* __restrict__ U, double* __restrict__ clover, Geom g)
+// wt weights the planes (i, t) and ws the spatial planes (the anisotropic action of Sec. III.B:
+// wt = c_SW^t, ws = c_SW^r / xi_0; 1 and 1 for the isotropic C).
+__device__ __forceinline__ M3 scaled(M3 f, double w)
+{
+#pragma unroll
+    for (int e = 0; e < 9; e++) f.m[e] = {w * f.m[e].re, w * f.m[e].im};
+    return f;
+}
+
+__global__ void k_clover_build(const double2* __restrict__ U, double* __restrict__ clover, Geom g, double wt,
+                               double ws)
 {
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= 2L * g.Vh) return;
     const int parity = (int)(gid / g.Vh), site = (int)(gid % g.Vh);
     int c[4];
     site_coords(g, site, parity, c[0], c[1], c[2], c[3]);
-    const M3 F01 = field_strength(U, g, c, 0, 1), F02 = field_strength(U, g, c, 0, 2),
-             F03 = field_strength(U, g, c, 0, 3), F12 = field_strength(U, g, c, 1, 2),
-             F13 = field_strength(U, g, c, 1, 3), F23 = field_strength(U, g, c, 2, 3);
+    const M3 F01 = scaled(field_strength(U, g, c, 0, 1), ws), F02 = scaled(field_strength(U, g, c, 0, 2), ws),
+             F03 = scaled(field_strength(U, g, c, 0, 3), wt), F12 = scaled(field_strength(U, g, c, 1, 2), ws),
+             F13 = scaled(field_strength(U, g, c, 1, 3), wt), F23 = scaled(field_strength(U, g, c, 2, 3), wt);
     const cd I = {0.0, 1.0};
     double* out = clover + gid * 72;
 #pragma unroll
@@ -300,11 +310,11 @@ __global__ void k_clover_to_A(const double* __restrict__ clover, double* __restr
 
 static inline dim3 grid_for(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
-hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover)
+hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover, double wt, double ws)
 {
     const long n = 2L * g.Vh;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_clover_build, grid_for(n), dim3(256), 0, s, (const double2*)U, (double*)clover, g);
+    hipLaunchKernelGGL(k_clover_build, grid_for(n), dim3(256), 0, s, (const double2*)U, (double*)clover, g, wt, ws);
     return hipGetLastError();
 }
 

@@ -164,6 +164,7 @@ struct Geom {
     int Lxh;   // Lx / 2
     int Vh;    // sites per parity
     int t_bc;  // +1 / -1
+    double xs = 1.0;  // weight of the spatial hops (nu / xi_0 for the anisotropic action, Sec. III.B)
 };
 
 // real index of entry m (reordered packing) of chirality block chi at `site` in an internal

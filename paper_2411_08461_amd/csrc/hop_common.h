@@ -172,8 +172,10 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
         L.loff[2 * j + 1] = link_base(mu, 1 - p, bwd, Vh, R);
         L.cs[2 * j] = c_s;
         L.cs[2 * j + 1] = -c_s;
-        L.fsg[2 * j] = (g.t_bc < 0 && fcross) ? T(-1) : T(1);
-        L.fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? T(-1) : T(1);
+        // boundary sign times the direction's weight (spatial hops: g.xs)
+        const T wgt = (j == 1 && gq == 1) ? T(1) : T(g.xs);
+        L.fsg[2 * j] = (g.t_bc < 0 && fcross) ? -wgt : wgt;
+        L.fsg[2 * j + 1] = (g.t_bc < 0 && bcross) ? -wgt : wgt;
     }
 }
 

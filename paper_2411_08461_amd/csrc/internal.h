@@ -218,7 +218,9 @@ hipError_t launch_pack_gauge(hipStream_t s, int prec, int recon, const Geom& g, 
 hipError_t launch_pack_clover(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal);
 
 // clover kernels on the paper layouts (FP64)
-hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover);
+// C = wt sum_i sigma_i4 F_i4 + ws sum_{i<j} sigma_ij F_ij (wt = ws = 1: the isotropic clover field)
+hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover, double wt = 1.0,
+                               double ws = 1.0);
 hipError_t launch_clover_apply(hipStream_t s, const Geom& g, const void* clover, const void* psi, void* out,
                                double kappa, double csw);
 hipError_t launch_clover_invert(hipStream_t s, const Geom& g, const void* clover, double kappa, double csw,
