@@ -422,6 +422,17 @@ def propagator(q, li, np, torch, ctx, fields, args):
     torch.cuda.synchronize()
     t_sep = time.perf_counter() - t0
     diff = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+    # the contraction after the solves: pion two-point function of the propagator (reads the 12 fields once)
+    lat = q.make_lattice(L)
+    corr = torch.empty(L[3], dtype=torch.complex128, device="cuda")
+    q.qcdw_meson_2pt(ctx, lat, x, 15, 15, (0, 0, 0), corr)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        q.qcdw_meson_2pt(ctx, lat, x, 15, 15, (0, 0, 0), corr)
+    torch.cuda.synchronize()
+    t_con = (time.perf_counter() - t0) / 5
+    pion = corr.cpu().numpy()
     # hop bandwidth of the multi-RHS kernel: a capped solve with every hop dispatch timed
     pt = q.make_params(tol=1e-10, maxiter=16, inner="bf16", collect_timing=True, check_every=8)
     xt = torch.zeros_like(bs)
@@ -436,7 +447,11 @@ def propagator(q, li, np, torch, ctx, fields, args):
             "separate_f64": dict(_solve_summary(sep), time_ms=round(1e3 * t_sep, 1)),
             "speedup": round(t_sep / t_multi, 3), "rel_diff_multi_vs_f64": diff,
             "multi_hop": {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "avg_launch_us": round(ms * 1e3, 1), "bytes_per_site_12rhs": hop_a_bytes_multi("bf16", 12)}}
+                          "avg_launch_us": round(ms * 1e3, 1), "bytes_per_site_12rhs": hop_a_bytes_multi("bf16", 12)},
+            "pion_2pt": {"call_ms": round(1e3 * t_con, 3),
+                         "gbs_incl_call": round(12 * 192 * 2 * Vh / t_con / 1e9, 1),
+                         "c_t0": float(pion[0].real), "c_t_mid": float(pion[L[3] // 2].real),
+                         "positive": bool((pion.real > 0).all())}}
 
 
 def batch_jobs(li):

@@ -133,6 +133,22 @@ void qcdw_ctx_destroy(qcdw_ctx *ctx);
 const char *qcdw_last_error(const qcdw_ctx *ctx);
 qcdw_status qcdw_ctx_set_stream(qcdw_ctx *ctx, void *hip_stream);
 
+/* The 12 wall sources of the propagator workflow (Sec. III.B, the sources of the 12
+   inversions): field k = 3 s0 + c0 is e^{+i p.x} on time slice t0 in spin s0, colour c0 and zero
+   elsewhere, p_i = 2 pi mom[i] / L_i (mom: 3 host ints, x, y, z).  out: 12 consecutive device
+   fields in the fermion layout (written).  QCDW_EINVAL for t0 outside [0, Lt). */
+qcdw_status qcdw_wall_sources(qcdw_ctx *ctx, const qcdw_lattice *lat, int t0, const int *mom, void *out);
+
+/* Meson two-point function of a propagator (the contraction after the solves, Sec. III.B):
+     out[t] = sum_{x: x_t = t} e^{-i p.x} Tr[Gamma(gamma_snk) S(x) Gamma(gamma_src) g5 S(x)^+ g5],
+   t = 0 .. Lt-1, with S(x)[3 s + c][k] = S_k(x)[s][c] from the 12 device fields S (fermion layout,
+   k = 3 s0 + c0, read), Gamma(n) the paper's bitmask product of gamma matrices (n in [0, 15];
+   15 is g5, so gamma_snk = gamma_src = 15 gives the pion), p_i = 2 pi mom[i] / L_i (3 host
+   ints).  out: Lt complex FP64 on the device (written).  The sum over each slice runs in a
+   fixed order (reproducible).  QCDW_EINVAL for a bitmask outside [0, 15]. */
+qcdw_status qcdw_meson_2pt(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *S, int gamma_snk, int gamma_src,
+                           const int *mom, void *out);
+
 /* Clover field construction when the gauge field is loaded (Sec. III.B, the
    clover term of Eq. "clover"): clover = C = sum_{mu<nu} sigma F, without
    kappa or csw.  U: gauge layout (read); clover: clover layout (written). */

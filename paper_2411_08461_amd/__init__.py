@@ -38,6 +38,7 @@ EXPORTED = (
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
     "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
+    "qcdw_wall_sources", "qcdw_meson_2pt",
 )
 
 
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH):
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_create_aniso": (i, [p, lat, p, d, d, d, d, d, i, i, ctypes.POINTER(p)]),
+        "qcdw_wall_sources": (i, [p, lat, i, ctypes.POINTER(i), p]),
+        "qcdw_meson_2pt": (i, [p, lat, p, i, i, ctypes.POINTER(i), p]),
         "qcdw_op_destroy": (None, [p]),
         "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
@@ -397,6 +400,24 @@ def qcdw_op_hop_form(op: Operator, prec: str = "f64"):
     _check(op.ctx.handle, load_library().qcdw_op_hop_form(op.handle, PREC[prec], ctypes.byref(nt), ctypes.byref(cg),
                                                           ctypes.byref(fma)))
     return nt.value, cg.value, fma.value
+
+
+def qcdw_wall_sources(ctx: Context, lat: qcdw_lattice, t0: int, mom, out):
+    """The 12 wall sources on slice t0 with spatial momentum mom into out (12 fermion fields, complex128)."""
+    _need(out, 12 * 12 * _volume(lat), "out")
+    m = (ctypes.c_int * 3)(*[int(v) for v in mom])
+    _check(ctx.handle, load_library().qcdw_wall_sources(ctx.handle, ctypes.byref(lat), int(t0), m,
+                                                        _ptr(out, torch.complex128, "out")))
+
+
+def qcdw_meson_2pt(ctx: Context, lat: qcdw_lattice, S, gamma_snk: int, gamma_src: int, mom, out):
+    """C(t) of the 12-field propagator S into out (Lt complex128 on the device)."""
+    _need(S, 12 * 12 * _volume(lat), "S")
+    _need(out, lat.L[3], "out")
+    m = (ctypes.c_int * 3)(*[int(v) for v in mom])
+    _check(ctx.handle, load_library().qcdw_meson_2pt(ctx.handle, ctypes.byref(lat), _ptr(S, torch.complex128, "S"),
+                                                     int(gamma_snk), int(gamma_src), m,
+                                                     _ptr(out, torch.complex128, "out")))
 
 
 def qcdw_invert(op: Operator, b, x, params: qcdw_solver_params | None = None, raise_on_error: bool = False):

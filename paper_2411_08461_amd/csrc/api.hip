@@ -70,6 +70,39 @@ qcdw_status qcdw_ctx_set_stream(qcdw_ctx* ctx, void* hip_stream)
     return QCDW_OK;
 }
 
+qcdw_status qcdw_wall_sources(qcdw_ctx* ctx, const qcdw_lattice* lat, int t0, const int* mom, void* out)
+{
+    if (!ctx) return QCDW_EINVAL;
+    DeviceGuard dg(ctx->device);
+    Geom g;
+    CHK(check_lattice(ctx, lat, g));
+    if (!mom) return fail(ctx, QCDW_EINVAL, "mom is NULL");
+    if (t0 < 0 || t0 >= g.Lt) return fail(ctx, QCDW_EINVAL, "t0 = %d outside [0, %d)", t0, g.Lt);
+    CHK(check_dev(ctx, out, "out"));
+    HIPCHK(ctx, launch_wall_sources(ctx->stream, g, t0, mom, out));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return QCDW_OK;
+}
+
+qcdw_status qcdw_meson_2pt(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* S, int gamma_snk, int gamma_src,
+                           const int* mom, void* out)
+{
+    if (!ctx) return QCDW_EINVAL;
+    DeviceGuard dg(ctx->device);
+    Geom g;
+    CHK(check_lattice(ctx, lat, g));
+    if (!mom) return fail(ctx, QCDW_EINVAL, "mom is NULL");
+    if (gamma_snk < 0 || gamma_snk > 15 || gamma_src < 0 || gamma_src > 15)
+        return fail(ctx, QCDW_EINVAL, "gamma bitmasks must lie in [0, 15], got %d and %d", gamma_snk, gamma_src);
+    CHK(check_dev(ctx, S, "S"));
+    CHK(check_dev(ctx, out, "out"));
+    DevBuf site;  // per-site contributions
+    HIPCHK(ctx, site.alloc(2UL * g.Vh * 16));
+    HIPCHK(ctx, launch_meson_2pt(ctx->stream, g, S, gamma_snk, gamma_src, mom, site.p, out));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return QCDW_OK;
+}
+
 qcdw_status qcdw_clover_build(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* U, void* clover)
 {
     if (!ctx) return QCDW_EINVAL;

@@ -1,0 +1,193 @@
+// Wall sources and meson two-point contractions: the steps on either side of the
+// solves in the paper's propagator workflow (Sec. III.B).  Conventions: a
+// propagator is 12 fields S_k (k = 3 s0 + c0) in the paper's fermion layout,
+// S(x)[3 s + c][k] = S_k(x)[s][c]; the wall source of component k on slice t0
+// with momentum n is e^{+i p.x} on that slice (p_i = 2 pi n_i / L_i); and
+//   C(t) = sum_{x: x_t = t} e^{-i p.x} Tr[G_snk S(x) G_src g5 S(x)^+ g5]
+// for the bitmask gammas Gamma(n) = g1^(n&1) g2^(n>>1&1) g3^(n>>2&1) g4^(n>>3&1).
+//
+// Every Gamma(n) in the DeGrand-Rossi basis has one nonzero entry per row,
+// G[s][perm(s)] = ph(s) with ph a power of i, so with A = G_snk, B = G_src:
+//   Tr[...] = sum_{s, s0} ph_A(s) ph_B(s0) g5(s) g5(perm_B(s0))
+//             sum_{c, c0} S_{3 s0 + c0}[perm_A(s)][c] conj(S_{3 perm_B(s0) + c0}[s][c]).
+// One lane per (s, s0) pair (16 per site) forms its colour sum; the lanes of a
+// site are summed by shuffles, and the sites of a slice in a fixed order.
+#include "internal.h"
+
+namespace qcdw {
+
+struct MesonArgs {
+    const double2* S;  // 12 fields, [12][V][4][3]
+    double2* site;     // per-site contribution (phase included), [V]
+    Geom g;
+    int perm_a[4], perm_b[4];
+    double2 ph_a[4], ph_b[4];
+    double px, py, pz;  // momentum components 2 pi n_i / L_i
+};
+
+__device__ __forceinline__ void site_xyzt(const Geom& g, long x, int& X, int& Y, int& Z, int& T)
+{
+    const int parity = (int)(x / g.Vh), site = (int)(x % g.Vh);
+    site_coords(g, site, parity, X, Y, Z, T);
+}
+
+__global__ __launch_bounds__(256) void k_wall_sources(double2* out, Geom g, int t0, double px, double py, double pz)
+{
+    const long V = 2L * g.Vh;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;  // element of the 12 fields
+    if (e >= 12L * V * 12) return;
+    const int sc = (int)(e % 12);
+    const long x = (e / 12) % V;
+    const int k = (int)(e / (12 * V));
+    double2 v = make_double2(0.0, 0.0);
+    if (sc == k) {
+        int X, Y, Z, T;
+        site_xyzt(g, x, X, Y, Z, T);
+        if (T == t0) {
+            double sn, cs;
+            sincos(px * X + py * Y + pz * Z, &sn, &cs);
+            v = make_double2(cs, sn);
+        }
+    }
+    out[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
+{
+    const long V = 2L * a.g.Vh;
+    const long x = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int lane = threadIdx.x & 15;
+    const int s = lane >> 2, s0 = lane & 3;
+    double re = 0.0, im = 0.0;
+    if (x < V) {
+        const int sa = a.perm_a[s], sb = a.perm_b[s0];
+#pragma unroll
+        for (int c0 = 0; c0 < 3; c0++) {
+            const double2* f1 = a.S + (((long)(3 * s0 + c0) * V + x) * 4 + sa) * 3;  // S_{3 s0 + c0}[perm_A(s)]
+            const double2* f2 = a.S + (((long)(3 * sb + c0) * V + x) * 4 + s) * 3;   // S_{3 perm_B(s0) + c0}[s]
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double2 u = f1[c], w = f2[c];  // u conj(w)
+                re += u.x * w.x + u.y * w.y;
+                im += u.y * w.x - u.x * w.y;
+            }
+        }
+        // ph_A(s) ph_B(s0) g5(s) g5(perm_B(s0))
+        const double2 pa = a.ph_a[s], pb = a.ph_b[s0];
+        double cr = pa.x * pb.x - pa.y * pb.y, ci = pa.x * pb.y + pa.y * pb.x;
+        const double sg = ((s < 2) == (sb < 2)) ? 1.0 : -1.0;
+        cr *= sg;
+        ci *= sg;
+        const double tr = cr * re - ci * im, ti = cr * im + ci * re;
+        re = tr;
+        im = ti;
+    }
+    // sum over the 16 lanes of the site, fixed order
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 16);
+        im += __shfl_xor(im, off, 16);
+    }
+    if (lane == 0 && x < V) {
+        int X, Y, Z, T;
+        site_xyzt(a.g, x, X, Y, Z, T);
+        double sn, cs;
+        sincos(-(a.px * X + a.py * Y + a.pz * Z), &sn, &cs);
+        a.site[x] = make_double2(cs * re - sn * im, cs * im + sn * re);
+    }
+}
+
+// out[t] = sum of the per-site values of slice t (both parities, eo order t St + c), one block per t
+__global__ __launch_bounds__(256) void k_slice_sum(const double2* site, double2* out, Geom g)
+{
+    const int t = blockIdx.x;
+    const long St = g.Vh / g.Lt;
+    double v[2] = {0.0, 0.0};
+    for (long i = threadIdx.x; i < 2 * St; i += 256) {
+        const long x = (i / St) * g.Vh + (long)t * St + (i % St);
+        const double2 z = site[x];
+        v[0] += z.x;
+        v[1] += z.y;
+    }
+    __shared__ double res[2];
+    block_sum_store<2>(v, res);
+    __syncthreads();
+    if (threadIdx.x == 0) out[t] = make_double2(res[0], res[1]);
+}
+
+static inline double mom_comp(int n, int L) { return 2.0 * 3.14159265358979323846 * n / L; }
+
+hipError_t launch_wall_sources(hipStream_t s, const Geom& g, int t0, const int mom[3], void* out)
+{
+    const long n = 12L * 2L * g.Vh * 12;
+    hipLaunchKernelGGL(k_wall_sources, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (double2*)out, g, t0,
+                       mom_comp(mom[0], g.Lx), mom_comp(mom[1], g.Ly), mom_comp(mom[2], g.Lz));
+    return hipGetLastError();
+}
+
+// Gamma(n) of the DeGrand-Rossi basis as (perm, phase) rows
+namespace {
+struct C4 {
+    double re[4][4], im[4][4];
+};
+C4 gamma_dr(int mu)
+{
+    // g1..g4 in the DeGrand-Rossi basis, entries (row, col, re, im)
+    static const int nz[4][4][4] = {
+        {{0, 3, 0, 1}, {1, 2, 0, 1}, {2, 1, 0, -1}, {3, 0, 0, -1}},
+        {{0, 3, -1, 0}, {1, 2, 1, 0}, {2, 1, 1, 0}, {3, 0, -1, 0}},
+        {{0, 2, 0, 1}, {1, 3, 0, -1}, {2, 0, 0, -1}, {3, 1, 0, 1}},
+        {{0, 2, 1, 0}, {1, 3, 1, 0}, {2, 0, 1, 0}, {3, 1, 1, 0}},
+    };
+    C4 m{};
+    for (const auto& e : nz[mu]) {
+        m.re[e[0]][e[1]] = e[2];
+        m.im[e[0]][e[1]] = e[3];
+    }
+    return m;
+}
+C4 mul(const C4& a, const C4& b)
+{
+    C4 c{};
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++)
+            for (int k = 0; k < 4; k++) {
+                c.re[i][j] += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
+                c.im[i][j] += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
+            }
+    return c;
+}
+void monomial(int n, int perm[4], double2 ph[4])
+{
+    C4 m{};
+    for (int i = 0; i < 4; i++) m.re[i][i] = 1.0;
+    for (int mu = 0; mu < 4; mu++)
+        if ((n >> mu) & 1) m = mul(m, gamma_dr(mu));
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++)
+            if (m.re[i][j] != 0.0 || m.im[i][j] != 0.0) {
+                perm[i] = j;
+                ph[i] = make_double2(m.re[i][j], m.im[i][j]);
+            }
+}
+}  // namespace
+
+hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, int g_snk, int g_src, const int mom[3],
+                            void* site_scratch, void* out)
+{
+    MesonArgs a{};
+    a.S = (const double2*)S;
+    a.site = (double2*)site_scratch;
+    a.g = g;
+    monomial(g_snk, a.perm_a, a.ph_a);
+    monomial(g_src, a.perm_b, a.ph_b);
+    a.px = mom_comp(mom[0], g.Lx);
+    a.py = mom_comp(mom[1], g.Ly);
+    a.pz = mom_comp(mom[2], g.Lz);
+    const long threads = 2L * g.Vh * 16;
+    hipLaunchKernelGGL(k_meson_sites, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_slice_sum, dim3(g.Lt), dim3(256), 0, s, (const double2*)site_scratch, (double2*)out, g);
+    return hipGetLastError();
+}
+
+}  // namespace qcdw

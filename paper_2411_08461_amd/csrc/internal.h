@@ -218,6 +218,11 @@ hipError_t launch_pack_gauge(hipStream_t s, int prec, int recon, const Geom& g, 
 hipError_t launch_pack_clover(hipStream_t s, int prec, const Geom& g, const void* paper, int parity, void* internal);
 
 // clover kernels on the paper layouts (FP64)
+// the 12 wall sources on slice t0 with spatial momentum mom (12 paper-layout fields into out)
+hipError_t launch_wall_sources(hipStream_t s, const Geom& g, int t0, const int mom[3], void* out);
+// meson two-point function of the 12-field propagator S into out[Lt] (complex FP64); site_scratch: V complex
+hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, int g_snk, int g_src, const int mom[3],
+                            void* site_scratch, void* out);
 // C = wt sum_i sigma_i4 F_i4 + ws sum_{i<j} sigma_ij F_ij (wt = ws = 1: the isotropic clover field)
 hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover, double wt = 1.0,
                                double ws = 1.0);

@@ -1,0 +1,97 @@
+"""GPU parity of the wall sources and the meson two-point contraction (the propagator workflow of
+Sec. III.B) against the oracle's definitions (oracle/contract.py)."""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+from oracle import contract
+import paper_2411_08461_amd as q
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = q.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.mark.parametrize("L,t0,mom", [((4, 4, 4, 8), 0, (0, 0, 0)), ((6, 4, 2, 6), 5, (1, 2, 1)),
+                                      ((10, 6, 4, 6), 3, (3, 0, 1))])
+def test_wall_sources_match_oracle(ctx, L, t0, mom):
+    V = int(np.prod(L))
+    out = torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_wall_sources(ctx, q.make_lattice(L), t0, mom, out)
+    expect = contract.wall_sources(L, t0, mom)
+    assert np.abs(host(out) - expect).max() < 1e-15
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 8), (6, 4, 2, 6), (10, 6, 4, 6)])
+@pytest.mark.parametrize("g_snk,g_src,mom", [(15, 15, (0, 0, 0)), (15, 15, (1, 0, 2)), (4, 4, (0, 1, 0)),
+                                             (8, 7, (0, 0, 0)), (1, 14, (2, 1, 1)), (0, 0, (0, 0, 1)),
+                                             (13, 11, (1, 1, 1))])
+def test_meson_2pt_matches_oracle(ctx, L, g_snk, g_src, mom):
+    """Random 12-field S: C(t) equals the oracle's full-matrix definition to 1e-12 (relative to the
+    largest |C|), for pairs of bitmask gammas and momenta, lattices with ragged slices."""
+    V = int(np.prod(L))
+    rng = np.random.default_rng(hash((L, g_snk, g_src, mom)) % 2 ** 32)
+    S = rng.standard_normal((12, V, 4, 3)) + 1j * rng.standard_normal((12, V, 4, 3))
+    out = torch.empty(L[3], dtype=torch.complex128, device="cuda")
+    q.qcdw_meson_2pt(ctx, q.make_lattice(L), dev(S), g_snk, g_src, mom, out)
+    expect = contract.meson_2pt(L, S, g_snk, g_src, mom)
+    assert np.abs(host(out) - expect).max() < 1e-12 * np.abs(expect).max()
+
+
+def test_pion_from_wall_source_propagator(ctx):
+    """The workflow: 12 wall sources, one lockstep 12-RHS solve (true residuals <= 1e-10 by the
+    oracle), the pion correlator on the GPU equals the oracle's contraction of the same propagator,
+    and it is real and positive (the pion is sum_x ||S(x)||^2)."""
+    L, t0 = (6, 4, 4, 8), 2
+    V = int(np.prod(L))
+    U = li.random_gauge(L, 0.25, 95)
+    kappa, csw = 0.118, 1.0
+    lat = q.make_lattice(L)
+    src = torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_wall_sources(ctx, lat, t0, (0, 0, 0), src)
+    op = q.Operator(ctx, lat, dev(U), kappa, csw, "bf16")
+    S = torch.zeros_like(src)
+    infos = q.qcdw_invert_multi(op, src.reshape(12, *li.fermion_shape(L)), S.reshape(12, *li.fermion_shape(L)),
+                                q.make_params(tol=1e-10, inner="bf16"))
+    op.close()
+    assert all(i.status == q.QCDW_OK for i in infos)
+    Sh, bh = host(S), host(src)
+    C = oracle.clover_build(L, U)
+    for k in (0, 7, 11):
+        r = bh[k].reshape(li.fermion_shape(L)) - oracle.dirac(L, U, C, Sh[k].reshape(li.fermion_shape(L)), kappa, csw)
+        assert np.linalg.norm(r) / np.linalg.norm(bh[k]) <= 1e-10
+    out = torch.empty(L[3], dtype=torch.complex128, device="cuda")
+    q.qcdw_meson_2pt(ctx, lat, S, 15, 15, (0, 0, 0), out)
+    got = host(out)
+    expect = contract.meson_2pt(L, Sh, 15, 15)
+    assert np.abs(got - expect).max() < 1e-12 * np.abs(expect).max()
+    assert np.abs(got.imag).max() < 1e-12 * got.real.max() and (got.real > 0).all()
+
+
+def test_contract_argument_errors(ctx):
+    L = (4, 4, 4, 4)
+    V = int(np.prod(L))
+    S = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    out = torch.empty(L[3], dtype=torch.complex128, device="cuda")
+    with pytest.raises(q.QcdwError):
+        q.qcdw_meson_2pt(ctx, q.make_lattice(L), S, 16, 15, (0, 0, 0), out)
+    with pytest.raises(q.QcdwError):
+        q.qcdw_wall_sources(ctx, q.make_lattice(L), 4, (0, 0, 0), S)
+    with pytest.raises(ValueError):
+        q.qcdw_meson_2pt(ctx, q.make_lattice(L), S[:11], 15, 15, (0, 0, 0), out)
