@@ -6,6 +6,7 @@ import pytest
 import oracle
 from oracle import contract
 from tests import geometry as geo
+import lattice_inputs as li
 
 
 def _identity_prop(L):
@@ -78,3 +79,34 @@ def test_wall_sources_closed_form():
         assert np.abs(f.reshape(-1, 12)[:, others]).max() == 0
         v = f.reshape(-1, 12)[:, k]
         assert abs(np.sum(v * np.exp(-1j * c[:, :3] @ p)) - L[0] * L[1] * L[2]) < 1e-12
+
+
+def test_three_point_sequential_matches_dense_double_sum():
+    """The sequential route (eta from S on the sink slice, T = M^{-1} eta, then one trace per y) equals
+    the explicit double sum over the sink and insertion slices of Tr[Gamma_f D^{-1}(x,y) G_ins
+    D^{-1}(y,0) G_src D^{-1}(0,x)], with D^{-1} the dense inverse of the Dirac matrix (2^2 x 4^2)."""
+    L = (2, 2, 4, 4)
+    V = int(np.prod(L))
+    U = li.random_gauge(L, 0.3, 61)
+    C = oracle.clover_build(L, U)
+    kappa, csw = 0.11, 1.0
+    Dinv = np.linalg.inv(oracle.dense_matrix(L, U, C, kappa, csw))
+    # S(y <- 0): the 12 columns of the origin (eo index 0)
+    S = Dinv[:, :12].T.reshape(12, V, 4, 3)
+    c = geo.coords(L)
+    t_f, g_f, g_ins, g_src, pf, q = 3, 15, 8, 15, (0, 1, 1), (1, 0, 0)
+    eta = contract.seq_sources(L, S, t_f, g_f, pf)
+    T = (Dinv @ eta.reshape(12, V * 12).T).T.reshape(12, V, 4, 3)
+    got = contract.contract(L, S, T, g_ins, g_src, q)
+    G = [oracle.gamma_bitmask(n) for n in (g_f, g_ins, g_src)]
+    blk = lambda a, b: Dinv[12 * a:12 * a + 12, 12 * b:12 * b + 12]  # noqa: E731
+    I3 = np.eye(3)
+    Gf, Gi, Gs = (np.kron(g, I3) for g in G)
+    pp = 2 * np.pi * np.asarray(pf) / np.asarray(L[:3])
+    qq = 2 * np.pi * np.asarray(q) / np.asarray(L[:3])
+    expect = np.zeros(L[3], dtype=complex)
+    for x in np.nonzero(c[:, 3] == t_f)[0]:
+        for y in range(V):
+            expect[c[y, 3]] += np.exp(-1j * (c[x, :3] @ pp)) * np.exp(-1j * (c[y, :3] @ qq)) * np.trace(
+                Gf @ blk(x, y) @ Gi @ blk(y, 0) @ Gs @ blk(0, x))
+    assert np.abs(got - expect).max() < 1e-11 * np.abs(expect).max()
