@@ -149,6 +149,24 @@ qcdw_status qcdw_wall_sources(qcdw_ctx *ctx, const qcdw_lattice *lat, int t0, co
 qcdw_status qcdw_meson_2pt(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *S, int gamma_snk, int gamma_src,
                            const int *mom, void *out);
 
+/* The same trace with a second propagator T in the backward leg:
+     out[t] = sum_{x: x_t = t} e^{-i p.x} Tr[Gamma(gamma_snk) S(x) Gamma(gamma_src) g5 T(x)^+ g5].
+   With T the sequential propagator (M^{-1} of qcdw_seq_sources) and gamma_snk the insertion this
+   is the three-point function of the paper's workflow (Sec. III.B); T = S gives qcdw_meson_2pt.
+   S, T: 12 device fields each (read); out: Lt complex FP64 on the device.  QCDW_EINVAL as above. */
+qcdw_status qcdw_meson_contract(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *S, const void *T, int gamma_snk,
+                                int gamma_src, const int *mom, void *out);
+
+/* Sequential sources through the sink (Sec. III.B, the sequential propagator of the three-point
+   function): out_k(x) = delta(x_t, t_f) e^{+i p.x} G S_k(x) with G = g5 Gamma(gamma_f)^+ g5 acting on
+   the sink spin, p_i = 2 pi mom[i] / L_i.  Solving M T_k = out_k and contracting
+   qcdw_meson_contract(S, T, g_ins, g_src, q) gives sum_{x_t = t_f, y_t = t} e^{-i p.x} e^{-i q.y}
+   Tr[Gamma(gamma_f) S(x<-y) Gamma(g_ins) S(y<-0) Gamma(g_src) S(0<-x)].  S, out: 12 device fields
+   (S read, out written, no aliasing).  QCDW_EINVAL for t_f outside [0, Lt) or a bitmask outside
+   [0, 15]. */
+qcdw_status qcdw_seq_sources(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *S, int t_f, int gamma_f,
+                             const int *mom, void *out);
+
 /* Clover field construction when the gauge field is loaded (Sec. III.B, the
    clover term of Eq. "clover"): clover = C = sum_{mu<nu} sigma F, without
    kappa or csw.  U: gauge layout (read); clover: clover layout (written). */

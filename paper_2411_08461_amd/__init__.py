@@ -38,7 +38,7 @@ EXPORTED = (
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
     "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
-    "qcdw_wall_sources", "qcdw_meson_2pt",
+    "qcdw_wall_sources", "qcdw_meson_2pt", "qcdw_meson_contract", "qcdw_seq_sources",
 )
 
 
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
         "qcdw_op_create_aniso": (i, [p, lat, p, d, d, d, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_wall_sources": (i, [p, lat, i, ctypes.POINTER(i), p]),
         "qcdw_meson_2pt": (i, [p, lat, p, i, i, ctypes.POINTER(i), p]),
+        "qcdw_meson_contract": (i, [p, lat, p, p, i, i, ctypes.POINTER(i), p]),
+        "qcdw_seq_sources": (i, [p, lat, p, i, i, ctypes.POINTER(i), p]),
         "qcdw_op_destroy": (None, [p]),
         "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
@@ -418,6 +420,27 @@ def qcdw_meson_2pt(ctx: Context, lat: qcdw_lattice, S, gamma_snk: int, gamma_src
     _check(ctx.handle, load_library().qcdw_meson_2pt(ctx.handle, ctypes.byref(lat), _ptr(S, torch.complex128, "S"),
                                                      int(gamma_snk), int(gamma_src), m,
                                                      _ptr(out, torch.complex128, "out")))
+
+
+def qcdw_meson_contract(ctx: Context, lat: qcdw_lattice, S, T, gamma_snk: int, gamma_src: int, mom, out):
+    """C(t) with the propagator S forward and T in the backward leg into out (Lt complex128 on the device)."""
+    _need(S, 12 * 12 * _volume(lat), "S")
+    _need(T, 12 * 12 * _volume(lat), "T")
+    _need(out, lat.L[3], "out")
+    m = (ctypes.c_int * 3)(*[int(v) for v in mom])
+    _check(ctx.handle, load_library().qcdw_meson_contract(ctx.handle, ctypes.byref(lat),
+                                                          _ptr(S, torch.complex128, "S"), _ptr(T, torch.complex128, "T"),
+                                                          int(gamma_snk), int(gamma_src), m,
+                                                          _ptr(out, torch.complex128, "out")))
+
+
+def qcdw_seq_sources(ctx: Context, lat: qcdw_lattice, S, t_f: int, gamma_f: int, mom, out):
+    """The 12 sequential sources through the sink slice t_f from the propagator S into out."""
+    _need(S, 12 * 12 * _volume(lat), "S")
+    _need(out, 12 * 12 * _volume(lat), "out")
+    m = (ctypes.c_int * 3)(*[int(v) for v in mom])
+    _check(ctx.handle, load_library().qcdw_seq_sources(ctx.handle, ctypes.byref(lat), _ptr(S, torch.complex128, "S"),
+                                                       int(t_f), int(gamma_f), m, _ptr(out, torch.complex128, "out")))
 
 
 def qcdw_invert(op: Operator, b, x, params: qcdw_solver_params | None = None, raise_on_error: bool = False):

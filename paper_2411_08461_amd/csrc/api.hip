@@ -84,8 +84,8 @@ qcdw_status qcdw_wall_sources(qcdw_ctx* ctx, const qcdw_lattice* lat, int t0, co
     return QCDW_OK;
 }
 
-qcdw_status qcdw_meson_2pt(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* S, int gamma_snk, int gamma_src,
-                           const int* mom, void* out)
+qcdw_status qcdw_meson_contract(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* S, const void* T, int gamma_snk,
+                                int gamma_src, const int* mom, void* out)
 {
     if (!ctx) return QCDW_EINVAL;
     DeviceGuard dg(ctx->device);
@@ -95,10 +95,35 @@ qcdw_status qcdw_meson_2pt(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* S
     if (gamma_snk < 0 || gamma_snk > 15 || gamma_src < 0 || gamma_src > 15)
         return fail(ctx, QCDW_EINVAL, "gamma bitmasks must lie in [0, 15], got %d and %d", gamma_snk, gamma_src);
     CHK(check_dev(ctx, S, "S"));
+    CHK(check_dev(ctx, T, "T"));
     CHK(check_dev(ctx, out, "out"));
     DevBuf site;  // per-site contributions
     HIPCHK(ctx, site.alloc(2UL * g.Vh * 16));
-    HIPCHK(ctx, launch_meson_2pt(ctx->stream, g, S, gamma_snk, gamma_src, mom, site.p, out));
+    HIPCHK(ctx, launch_meson_2pt(ctx->stream, g, S, T, gamma_snk, gamma_src, mom, site.p, out));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return QCDW_OK;
+}
+
+qcdw_status qcdw_meson_2pt(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* S, int gamma_snk, int gamma_src,
+                           const int* mom, void* out)
+{
+    return qcdw_meson_contract(ctx, lat, S, S, gamma_snk, gamma_src, mom, out);
+}
+
+qcdw_status qcdw_seq_sources(qcdw_ctx* ctx, const qcdw_lattice* lat, const void* S, int t_f, int gamma_f,
+                             const int* mom, void* out)
+{
+    if (!ctx) return QCDW_EINVAL;
+    DeviceGuard dg(ctx->device);
+    Geom g;
+    CHK(check_lattice(ctx, lat, g));
+    if (!mom) return fail(ctx, QCDW_EINVAL, "mom is NULL");
+    if (t_f < 0 || t_f >= g.Lt) return fail(ctx, QCDW_EINVAL, "t_f = %d outside [0, %d)", t_f, g.Lt);
+    if (gamma_f < 0 || gamma_f > 15) return fail(ctx, QCDW_EINVAL, "gamma bitmask must lie in [0, 15], got %d", gamma_f);
+    CHK(check_dev(ctx, S, "S"));
+    CHK(check_dev(ctx, out, "out"));
+    if (S == out) return fail(ctx, QCDW_EINVAL, "out must not alias S");
+    HIPCHK(ctx, launch_seq_sources(ctx->stream, g, S, t_f, gamma_f, mom, out));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return QCDW_OK;
 }

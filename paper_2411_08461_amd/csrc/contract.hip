@@ -1,15 +1,17 @@
-// Wall sources and meson two-point contractions: the steps on either side of the
-// solves in the paper's propagator workflow (Sec. III.B).  Conventions: a
+// Wall sources, sequential sources and meson contractions: the steps on either
+// side of the solves in the paper's propagator workflow (Sec. III.B).  Conventions: a
 // propagator is 12 fields S_k (k = 3 s0 + c0) in the paper's fermion layout,
 // S(x)[3 s + c][k] = S_k(x)[s][c]; the wall source of component k on slice t0
 // with momentum n is e^{+i p.x} on that slice (p_i = 2 pi n_i / L_i); and
 //   C(t) = sum_{x: x_t = t} e^{-i p.x} Tr[G_snk S(x) G_src g5 S(x)^+ g5]
-// for the bitmask gammas Gamma(n) = g1^(n&1) g2^(n>>1&1) g3^(n>>2&1) g4^(n>>3&1).
+// for the bitmask gammas Gamma(n) = g1^(n&1) g2^(n>>1&1) g3^(n>>2&1) g4^(n>>3&1); with a
+// second propagator T in place of S in the backward leg (T = M^-1 of the sequential sources
+// delta(x_t, t_f) e^{+i p.x} g5 Gamma_f^+ g5 S) the same trace is the three-point function.
 //
 // Every Gamma(n) in the DeGrand-Rossi basis has one nonzero entry per row,
 // G[s][perm(s)] = ph(s) with ph a power of i, so with A = G_snk, B = G_src:
 //   Tr[...] = sum_{s, s0} ph_A(s) ph_B(s0) g5(s) g5(perm_B(s0))
-//             sum_{c, c0} S_{3 s0 + c0}[perm_A(s)][c] conj(S_{3 perm_B(s0) + c0}[s][c]).
+//             sum_{c, c0} S_{3 s0 + c0}[perm_A(s)][c] conj(T_{3 perm_B(s0) + c0}[s][c]).
 // One lane per (s, s0) pair (16 per site) forms its colour sum; the lanes of a
 // site are summed by shuffles, and the sites of a slice in a fixed order.
 #include "internal.h"
@@ -18,6 +20,7 @@ namespace qcdw {
 
 struct MesonArgs {
     const double2* S;  // 12 fields, [12][V][4][3]
+    const double2* T;  // second propagator (T = S: the two-point function; a sequential one: three-point)
     double2* site;     // per-site contribution (phase included), [V]
     Geom g;
     int perm_a[4], perm_b[4];
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
 #pragma unroll
         for (int c0 = 0; c0 < 3; c0++) {
             const double2* f1 = a.S + (((long)(3 * s0 + c0) * V + x) * 4 + sa) * 3;  // S_{3 s0 + c0}[perm_A(s)]
-            const double2* f2 = a.S + (((long)(3 * sb + c0) * V + x) * 4 + s) * 3;   // S_{3 perm_B(s0) + c0}[s]
+            const double2* f2 = a.T + (((long)(3 * sb + c0) * V + x) * 4 + s) * 3;   // T_{3 perm_B(s0) + c0}[s]
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 const double2 u = f1[c], w = f2[c];  // u conj(w)
@@ -95,6 +98,33 @@ __global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
         sincos(-(a.px * X + a.py * Y + a.pz * Z), &sn, &cs);
         a.site[x] = make_double2(cs * re - sn * im, cs * im + sn * re);
     }
+}
+
+// Sequential sources: out_k(x)[s][c] = delta(x_t, t_f) e^{+i p.x} G[s][perm(s)] S_k(x)[perm(s)][c] with the
+// monomial spin matrix G = g5 Gamma_f^+ g5 (perm, ph); one thread per output element
+__global__ __launch_bounds__(256) void k_seq_sources(const double2* S, double2* out, Geom g, int t_f, double px,
+                                                     double py, double pz, int4 perm, double4 ph_re, double4 ph_im)
+{
+    const long V = 2L * g.Vh;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 12L * V * 12) return;
+    const int c = (int)(e % 3), s = (int)((e / 3) % 4);
+    const long x = (e / 12) % V;
+    const int k = (int)(e / (12 * V));
+    double2 v = make_double2(0.0, 0.0);
+    int X, Y, Z, T;
+    site_xyzt(g, x, X, Y, Z, T);
+    if (T == t_f) {
+        const int ps = s == 0 ? perm.x : s == 1 ? perm.y : s == 2 ? perm.z : perm.w;
+        const double gr = s == 0 ? ph_re.x : s == 1 ? ph_re.y : s == 2 ? ph_re.z : ph_re.w;
+        const double gi = s == 0 ? ph_im.x : s == 1 ? ph_im.y : s == 2 ? ph_im.z : ph_im.w;
+        const double2 u = S[(((long)k * V + x) * 4 + ps) * 3 + c];
+        double sn, cs;
+        sincos(px * X + py * Y + pz * Z, &sn, &cs);
+        const double wr = cs * gr - sn * gi, wi = cs * gi + sn * gr;  // phase times G entry
+        v = make_double2(wr * u.x - wi * u.y, wr * u.y + wi * u.x);
+    }
+    out[e] = v;
 }
 
 // out[t] = sum of the per-site values of slice t (both parities, eo order t St + c), one block per t
@@ -172,11 +202,42 @@ void monomial(int n, int perm[4], double2 ph[4])
 }
 }  // namespace
 
-hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, int g_snk, int g_src, const int mom[3],
-                            void* site_scratch, void* out)
+hipError_t launch_seq_sources(hipStream_t s, const Geom& g, const void* S, int t_f, int g_f, const int mom[3],
+                              void* out)
+{
+    // G = g5 Gamma_f^+ g5: row i has its entry at column perm_f(i)^{-1}... built as a matrix, then read by rows
+    int pf[4];
+    double2 phf[4];
+    monomial(g_f, pf, phf);
+    C4 G{};
+    for (int i = 0; i < 4; i++) {  // (Gamma^+)[perm(i)][i] = conj(ph(i)); g5 on both sides: sign g5(row) g5(col)
+        const int r = pf[i], col = i;
+        const double sg = ((r < 2) == (col < 2)) ? 1.0 : -1.0;
+        G.re[r][col] = sg * phf[i].x;
+        G.im[r][col] = -sg * phf[i].y;
+    }
+    int perm[4];
+    double2 ph[4];
+    for (int r = 0; r < 4; r++)
+        for (int col = 0; col < 4; col++)
+            if (G.re[r][col] != 0.0 || G.im[r][col] != 0.0) {
+                perm[r] = col;
+                ph[r] = make_double2(G.re[r][col], G.im[r][col]);
+            }
+    const long n = 12L * 2L * g.Vh * 12;
+    hipLaunchKernelGGL(k_seq_sources, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const double2*)S,
+                       (double2*)out, g, t_f, mom_comp(mom[0], g.Lx), mom_comp(mom[1], g.Ly), mom_comp(mom[2], g.Lz),
+                       make_int4(perm[0], perm[1], perm[2], perm[3]), make_double4(ph[0].x, ph[1].x, ph[2].x, ph[3].x),
+                       make_double4(ph[0].y, ph[1].y, ph[2].y, ph[3].y));
+    return hipGetLastError();
+}
+
+hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, const void* T, int g_snk, int g_src,
+                            const int mom[3], void* site_scratch, void* out)
 {
     MesonArgs a{};
     a.S = (const double2*)S;
+    a.T = (const double2*)T;
     a.site = (double2*)site_scratch;
     a.g = g;
     monomial(g_snk, a.perm_a, a.ph_a);

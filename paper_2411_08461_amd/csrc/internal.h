@@ -220,9 +220,13 @@ hipError_t launch_pack_clover(hipStream_t s, int prec, const Geom& g, const void
 // clover kernels on the paper layouts (FP64)
 // the 12 wall sources on slice t0 with spatial momentum mom (12 paper-layout fields into out)
 hipError_t launch_wall_sources(hipStream_t s, const Geom& g, int t0, const int mom[3], void* out);
-// meson two-point function of the 12-field propagator S into out[Lt] (complex FP64); site_scratch: V complex
-hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, int g_snk, int g_src, const int mom[3],
-                            void* site_scratch, void* out);
+// meson contraction of the 12-field propagators S and T (T = S: the two-point function) into out[Lt]
+// (complex FP64); site_scratch: V complex
+hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, const void* T, int g_snk, int g_src,
+                            const int mom[3], void* site_scratch, void* out);
+// sequential sources through the sink slice t_f from the propagator S (12 fields into out)
+hipError_t launch_seq_sources(hipStream_t s, const Geom& g, const void* S, int t_f, int g_f, const int mom[3],
+                              void* out);
 // C = wt sum_i sigma_i4 F_i4 + ws sum_{i<j} sigma_ij F_ij (wt = ws = 1: the isotropic clover field)
 hipError_t launch_clover_build(hipStream_t s, const Geom& g, const void* U, void* clover, double wt = 1.0,
                                double ws = 1.0);

@@ -1,5 +1,6 @@
-"""GPU parity of the wall sources and the meson two-point contraction (the propagator workflow of
-Sec. III.B) against the oracle's definitions (oracle/contract.py)."""
+"""GPU parity of the wall and sequential sources and the meson two- and three-point contractions (the
+propagator workflow of Sec. III.B) against the oracle's definitions (oracle/contract.py) and, for the
+three-point function, the dense inverse of the Dirac matrix."""
 import numpy as np
 import pytest
 import torch
@@ -95,3 +96,62 @@ def test_contract_argument_errors(ctx):
         q.qcdw_wall_sources(ctx, q.make_lattice(L), 4, (0, 0, 0), S)
     with pytest.raises(ValueError):
         q.qcdw_meson_2pt(ctx, q.make_lattice(L), S[:11], 15, 15, (0, 0, 0), out)
+
+
+@pytest.mark.parametrize("L,t_f,g_f,mom", [((4, 4, 4, 8), 5, 15, (0, 0, 0)), ((6, 4, 2, 6), 0, 8, (1, 0, 1)),
+                                           ((10, 6, 4, 6), 3, 7, (2, 1, 0))])
+def test_seq_sources_and_contraction_match_oracle(ctx, L, t_f, g_f, mom):
+    """Sequential sources (g5 Gamma_f^+ g5 S on the sink slice with its phase) and the contraction with a
+    second propagator equal the oracle's definitions on random fields."""
+    V = int(np.prod(L))
+    rng = np.random.default_rng(t_f * 100 + g_f)
+    S = rng.standard_normal((12, V, 4, 3)) + 1j * rng.standard_normal((12, V, 4, 3))
+    T = rng.standard_normal((12, V, 4, 3)) + 1j * rng.standard_normal((12, V, 4, 3))
+    lat = q.make_lattice(L)
+    eta = torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    q.qcdw_seq_sources(ctx, lat, dev(S), t_f, g_f, mom, eta)
+    assert np.abs(host(eta) - contract.seq_sources(L, S, t_f, g_f, mom)).max() < 1e-14 * np.abs(S).max()
+    out = torch.empty(L[3], dtype=torch.complex128, device="cuda")
+    q.qcdw_meson_contract(ctx, lat, dev(S), dev(T), 8, 15, mom, out)
+    expect = contract.contract(L, S, T, 8, 15, mom)
+    assert np.abs(host(out) - expect).max() < 1e-12 * np.abs(expect).max()
+
+
+def test_three_point_workflow_matches_dense_double_sum(ctx):
+    """Point-source propagator, sequential sources through the sink, a second 12-RHS solve, and the
+    three-point contraction on the GPU equal the explicit double sum of Tr[Gamma_f D^-1(x,y) G_ins
+    D^-1(y,0) G_src D^-1(0,x)] over the dense inverse (2^2 x 4^2), to the solver tolerance."""
+    L = (2, 2, 4, 4)
+    V = int(np.prod(L))
+    U = li.random_gauge(L, 0.3, 96)
+    kappa, csw = 0.11, 1.0
+    lat = q.make_lattice(L)
+    pt = np.zeros((12, V, 4, 3), dtype=np.complex128)
+    for k in range(12):
+        pt[k, 0, k // 3, k % 3] = 1.0  # origin, eo index 0
+    op = q.Operator(ctx, lat, dev(U), kappa, csw)
+    shape = (12,) + li.fermion_shape(L)
+    prm = q.make_params(tol=1e-12)
+    S = torch.zeros(shape, dtype=torch.complex128, device="cuda")
+    assert all(i.status == q.QCDW_OK for i in q.qcdw_invert_multi(op, dev(pt).reshape(shape), S, prm))
+    t_f, g_f, g_ins, g_src, pf, qm = 3, 15, 8, 15, (0, 1, 1), (1, 0, 0)
+    eta = torch.empty_like(S)
+    q.qcdw_seq_sources(ctx, lat, S, t_f, g_f, pf, eta)
+    T = torch.zeros_like(S)
+    assert all(i.status == q.QCDW_OK for i in q.qcdw_invert_multi(op, eta, T, prm))
+    op.close()
+    out = torch.empty(L[3], dtype=torch.complex128, device="cuda")
+    q.qcdw_meson_contract(ctx, lat, S, T, g_ins, g_src, qm, out)
+    Dinv = np.linalg.inv(oracle.dense_matrix(L, U, oracle.clover_build(L, U), kappa, csw))
+    c = oracle.coords_table(L)
+    I3 = np.eye(3)
+    Gf, Gi, Gs = (np.kron(oracle.gamma_bitmask(n), I3) for n in (g_f, g_ins, g_src))
+    blk = lambda a, b: Dinv[12 * a:12 * a + 12, 12 * b:12 * b + 12]  # noqa: E731
+    pp = 2 * np.pi * np.asarray(pf) / np.asarray(L[:3])
+    qq = 2 * np.pi * np.asarray(qm) / np.asarray(L[:3])
+    expect = np.zeros(L[3], dtype=complex)
+    for x in np.nonzero(c[:, 3] == t_f)[0]:
+        for y in range(V):
+            expect[c[y, 3]] += np.exp(-1j * (c[x, :3] @ pp)) * np.exp(-1j * (c[y, :3] @ qq)) * np.trace(
+                Gf @ blk(x, y) @ Gi @ blk(y, 0) @ Gs @ blk(0, x))
+    assert np.abs(host(out) - expect).max() < 1e-9 * np.abs(expect).max()
