@@ -133,6 +133,16 @@ void qcdw_ctx_destroy(qcdw_ctx *ctx);
 const char *qcdw_last_error(const qcdw_ctx *ctx);
 qcdw_status qcdw_ctx_set_stream(qcdw_ctx *ctx, void *hip_stream);
 
+/* Multi-shift CG on the normal even-odd operator (the solves of a rational approximation in RHMC,
+   paper Sec. IV; the shifted solver reuses the hot path): (M_hat^+ M_hat + shifts[i]) x_i = b for
+   i < n_shifts (1 .. 64, every shift finite and >= 0) in one Krylov space, FP64.  b_e, x_e[i]:
+   even-site fields in the layout of qcdw_op_matpc (b read; x written, not aliasing b).  Stops when
+   every shifted residual (tracked by the recurrence) is <= tol ||b||; *iters and res[i] (host:
+   the relative residual estimates) are filled.  QCDW_ENOCONV after maxiter, QCDW_EBREAKDOWN if
+   (p, N p) is not positive, QCDW_ENAN for a non-finite residual, QCDW_EINVAL for bad arguments. */
+qcdw_status qcdw_invert_multishift(qcdw_op *op, const void *b_e, void *const *x_e, const double *shifts, int n_shifts,
+                                   double tol, int maxiter, int *iters, double *res);
+
 /* The 12 wall sources of the propagator workflow (Sec. III.B, the sources of the 12
    inversions): field k = 3 s0 + c0 is e^{+i p.x} on time slice t0 in spin s0, colour c0 and zero
    elsewhere, p_i = 2 pi mom[i] / L_i (mom: 3 host ints, x, y, z).  out: 12 consecutive device

@@ -369,3 +369,25 @@ def dense_matrix(L, U, clover, kappa: float, csw: float, t_bc: int = 1) -> np.nd
         e[k] = 1
         M[:, k] = dirac(L, U, clover, e.reshape(fermion_shape(L)), kappa, csw, t_bc).reshape(n)
     return M
+
+
+def schur_dense(L, U, clover_inv, kappa: float, t_bc: int = 1) -> np.ndarray:
+    """M_hat as a dense (12 Vh x 12 Vh) matrix, assembled column by column from schur_matpc."""
+    Vh = int(np.prod(L)) // 2
+    n = 12 * Vh
+    M = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for k in range(n):
+        e[:] = 0
+        e[k] = 1
+        M[:, k] = schur_matpc(L, U, clover_inv, e.reshape(Vh, 4, 3), kappa, t_bc).reshape(n)
+    return M
+
+
+def normal_shifted_solve(L, U, clover_inv, b_e, kappa: float, shifts, t_bc: int = 1):
+    """x_i = (M_hat^+ M_hat + shifts[i])^{-1} b_e by dense solves: the definition the multi-shift solver
+    reaches (RHMC's rational approximation needs these solves, Sec. IV)."""
+    M = schur_dense(L, U, clover_inv, kappa, t_bc)
+    N = M.conj().T @ M
+    b = np.asarray(b_e, dtype=np.complex128).reshape(-1)
+    return [np.linalg.solve(N + s * np.eye(N.shape[0]), b).reshape(-1, 4, 3) for s in shifts]

@@ -38,7 +38,7 @@ EXPORTED = (
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
     "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
-    "qcdw_wall_sources", "qcdw_meson_2pt", "qcdw_meson_contract", "qcdw_seq_sources",
+    "qcdw_wall_sources", "qcdw_meson_2pt", "qcdw_meson_contract", "qcdw_seq_sources", "qcdw_invert_multishift",
 )
 
 
@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
         "qcdw_meson_2pt": (i, [p, lat, p, i, i, ctypes.POINTER(i), p]),
         "qcdw_meson_contract": (i, [p, lat, p, p, i, i, ctypes.POINTER(i), p]),
         "qcdw_seq_sources": (i, [p, lat, p, i, i, ctypes.POINTER(i), p]),
+        "qcdw_invert_multishift": (i, [p, p, ctypes.POINTER(p), ctypes.POINTER(d), i, d, i, ctypes.POINTER(i),
+                                       ctypes.POINTER(d)]),
         "qcdw_op_destroy": (None, [p]),
         "qcdw_op_hop_form": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qcdw_op_matpc": (i, [p, i, p, p]),
@@ -441,6 +443,22 @@ def qcdw_seq_sources(ctx: Context, lat: qcdw_lattice, S, t_f: int, gamma_f: int,
     m = (ctypes.c_int * 3)(*[int(v) for v in mom])
     _check(ctx.handle, load_library().qcdw_seq_sources(ctx.handle, ctypes.byref(lat), _ptr(S, torch.complex128, "S"),
                                                        int(t_f), int(gamma_f), m, _ptr(out, torch.complex128, "out")))
+
+
+def qcdw_invert_multishift(op: Operator, b_e, xs, shifts, tol: float = 1e-10, maxiter: int = 10000):
+    """(M_hat^+ M_hat + shifts[i]) xs[i] = b_e on even sites; returns (iterations, residual estimates)."""
+    n = len(shifts)
+    _need(b_e, 12 * op.volume // 2, "b_e")
+    if len(xs) != n:
+        raise ValueError("one output field per shift")
+    for x in xs:
+        _need(x, 12 * op.volume // 2, "x")
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(x, torch.complex128, "x") for x in xs])
+    sh = (ctypes.c_double * n)(*[float(v) for v in shifts])
+    it, res = ctypes.c_int(), (ctypes.c_double * n)()
+    _check(op.ctx.handle, load_library().qcdw_invert_multishift(op.handle, _ptr(b_e, torch.complex128, "b_e"), ptrs, sh,
+                                                                n, float(tol), int(maxiter), ctypes.byref(it), res))
+    return it.value, list(res)
 
 
 def qcdw_invert(op: Operator, b, x, params: qcdw_solver_params | None = None, raise_on_error: bool = False):

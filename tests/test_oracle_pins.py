@@ -340,3 +340,31 @@ def test_solver_statuses():
     # residual history starts at 1 (zero guess) and ends at or below tol
     r = oracle.bicgstab(L, U, C, b, 0.12, 1.0, tol=1e-10, maxiter=500)
     assert r.status == 0 and r.res_hist[0] == pytest.approx(1.0) and r.res_hist[-1] <= 1e-10
+
+
+def test_schur_adjoint_identity():
+    """M_hat^+ = g5 A_ee M_hat g5 A_ee^{-1} on even sites (M^+ = g5 M g5 and [A, g5] = 0): the identity the
+    GPU normal operator uses, checked on the dense matrices."""
+    L = (4, 2, 2, 4)
+    U = li.random_gauge(L, 0.4, seed=27)
+    kappa, csw = 0.12, 1.2
+    C = oracle.clover_build(L, U)
+    Ainv, _ = oracle.clover_invert(L, C, kappa, csw)
+    M = oracle.schur_dense(L, U, Ainv, kappa)
+    Vh = int(np.prod(L)) // 2
+    n = 12 * Vh
+
+    def blockwise(packed):  # dense block-diagonal matrix of the even-site packed blocks
+        full = oracle.unpack_blocks(np.asarray(packed).reshape(-1, 2, 36))[:Vh]
+        D = np.zeros((n, n), dtype=complex)
+        for i in range(Vh):
+            for chi in range(2):
+                # block rows/cols: spins 2 chi, 2 chi + 1 (colour inner) of site i
+                idx = 12 * i + 6 * chi + np.arange(6)
+                D[np.ix_(idx, idx)] = full[i, chi]
+        return D
+
+    Ai = blockwise(Ainv)
+    A = np.linalg.inv(Ai)
+    g5 = np.kron(np.eye(Vh), np.kron(np.diag([1.0, 1.0, -1.0, -1.0]), np.eye(3)))
+    assert np.abs(M.conj().T - g5 @ A @ M @ g5 @ Ai).max() < 1e-12 * np.abs(M).max()
