@@ -16,8 +16,9 @@ together with the multi-RHS hop in BF16 against 12 separate FP64 solves),
 "batch" (48 uneven problems in one persistent batched solve against a loop of
 single solves, solves/s), "learned" (32^3 x 64 near the critical kappa:
 FGMRES(32) with the trained gauge-covariant preconditioner against plain FP64
-and mixed BiCGStab) and "aniso" (the paper's anisotropic example action on
-16^3 x 32 with antiperiodic time).  ``--bisect-kappa`` finds that kappa.
+and mixed BiCGStab), "aniso" (the paper's anisotropic example action on
+16^3 x 32 with antiperiodic time) and "multishift" (8 shifted normal-equation
+solves in one Krylov space against separate solves).  ``--bisect-kappa`` finds that kappa.
 
 Printed line (rank 0): metric/value = algorithmic bytes of the Krylov
 iterations (byte model per iteration and precision, counted with the actual
@@ -81,7 +82,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-lattice", default="24,24,24,64",
                     help="also time the hop kernel on this lattice (empty to skip)")
-    ap.add_argument("--sections", default="propagator,batch,learned,aniso",
+    ap.add_argument("--sections", default="propagator,batch,learned,aniso,multishift",
                     help="comma-separated extra workloads to run after the timed steps (empty: none)")
     ap.add_argument("--bisect-kappa", action="store_true",
                     help="find the 32^3x64 kappa at which FP64 BiCGStab first needs >= 2000 iterations, then exit")
@@ -625,8 +626,41 @@ def aniso(q, li, np, torch, ctx, fields, args):
     return out
 
 
+def multishift_jobs(li):
+    w = li.WORKLOADS["wc16x32"]
+    return [(w["L"], w["eps"], w["seed"])]
+
+
+def multishift(q, li, np, torch, ctx, fields, args):
+    """Multi-shift CG on the normal even-odd operator (RHMC's rational-approximation solves) at 16^3x32:
+    8 shifts spread over four decades, FP64, one Krylov space against 8 separate single-shift solves."""
+    w = li.WORKLOADS["wc16x32"]
+    L = w["L"]
+    Vh = int(np.prod(L)) // 2
+    op = q.Operator(ctx, q.make_lattice(L), torch.from_numpy(fields[0]).cuda(), w["kappa"], w["csw"])
+    b = torch.from_numpy(li.gaussian_source(L, 1009).reshape(-1, 4, 3)[:Vh].copy()).cuda()
+    shifts = [1e-4 * 4 ** k for k in range(8)]
+    xs = [torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda") for _ in shifts]
+    q.qcdw_invert_multishift(op, b, xs, shifts)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, res = q.qcdw_invert_multishift(op, b, xs, shifts)
+    torch.cuda.synchronize()
+    t_ms = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    its1 = [q.qcdw_invert_multishift(op, b, [xs[k]], [shifts[k]])[0] for k in range(len(shifts))]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    op.close()
+    return {"workload": "16^3x32, kappa 0.124, csw 1.0, eps 0.2, Gaussian even-site source, shifts 1e-4 * 4^k, k < 8",
+            "multishift": {"iters": it, "max_res": max(res), "time_ms": round(1e3 * t_ms, 2)},
+            "separate": {"iters_sum": sum(its1), "time_ms": round(1e3 * t_sep, 2)},
+            "speedup": round(t_sep / t_ms, 3)}
+
+
 SECTIONS = {"propagator": (propagator_jobs, propagator), "batch": (batch_jobs, batch),
-            "learned": (learned_jobs, learned), "aniso": (aniso_jobs, aniso)}
+            "learned": (learned_jobs, learned), "aniso": (aniso_jobs, aniso),
+            "multishift": (multishift_jobs, multishift)}
 
 
 def bisect_kappa(q, li, np, torch):
