@@ -11,6 +11,29 @@
 
 namespace {
 
+// All shifted updates of one iteration in one pass, reading each old p_i once:
+//   x_i += alpha_i p_i,  p_i = zeta_i' r + beta_i p_i  (i < nshift),  p = r + beta p.
+// c = [alpha_i, zeta_i', beta_i] per shift, then beta; vectors X_i, P_i at stride n (complex elements).
+__global__ __launch_bounds__(256) void k_shift_update(double2* X, double2* P, double2* p, const double2* r, long n,
+                                                      int nshift, const double* c)
+{
+    const double beta = c[3 * nshift];
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+        const double2 rv = r[e];
+        for (int i = 0; i < nshift; i++) {
+            const double a = c[3 * i], z = c[3 * i + 1], b = c[3 * i + 2];
+            const double2 pv = P[(long)i * n + e];
+            double2 xv = X[(long)i * n + e];
+            xv.x += a * pv.x;
+            xv.y += a * pv.y;
+            X[(long)i * n + e] = xv;
+            P[(long)i * n + e] = make_double2(z * rv.x + b * pv.x, z * rv.y + b * pv.y);
+        }
+        const double2 pb = p[e];
+        p[e] = make_double2(rv.x + beta * pb.x, rv.y + beta * pb.y);
+    }
+}
+
 // g5 in the internal layout [4 spin][Vh][3]: negate spins 2 and 3 (the second half)
 hipError_t apply_g5(hipStream_t s, void* v, const Geom& g)
 {
@@ -46,12 +69,12 @@ extern "C" qcdw_status qcdw_invert_multishift(qcdw_op* op, const void* b_e, void
     DevBuf buf, part, dev;
     HIPCHK(ctx, buf.alloc(vb * (6 + 2 * (size_t)n_shifts)));
     HIPCHK(ctx, part.alloc(16UL * 2048 * sizeof(double)));
-    // device scalars: [0, 2) a dot product; then the coefficients of the axpys (complex pairs):
-    // [2, 4) the base shift, [4, 4 + 2n) alpha_i, [4 + 2n, 6 + 2n) alpha, [6 + 2n, 6 + 4n) zeta_i', [6 + 4n, 8 + 4n) 1.
-    // Each block is staged at the same offset of the pinned host buffer and copied once, after the
+    // device scalars: [0, 2) a dot product; [2, 4) the base shift and [4, 6) alpha as complex pairs for
+    // the axpys; [6, 7 + 3n) the shifted-update coefficients [alpha_i, zeta_i', beta_i] and beta.  Each
+    // block is staged at the same offset of the pinned host buffer and copied once, after the
     // synchronisation that precedes it, so no staged value is overwritten before its copy has run.
-    const int nsc = 8 + 4 * n_shifts;
-    static_assert(HOST_D_N >= 8 + 4 * 64, "pinned host staging too small for 64 shifts");
+    const int nsc = 7 + 3 * n_shifts;
+    static_assert(HOST_D_N >= 7 + 3 * 64, "pinned host staging too small for 64 shifts");
     HIPCHK(ctx, dev.alloc(nsc * sizeof(double)));
     char* base = (char*)buf.p;
     void *r = base, *p = base + vb, *w = base + 2 * vb, *t1 = base + 3 * vb, *t2 = base + 4 * vb, *tmpo = base + 5 * vb;
@@ -59,7 +82,7 @@ extern "C" qcdw_status qcdw_invert_multishift(qcdw_op* op, const void* b_e, void
     auto P = [&](int i) { return (void*)(base + (6 + n_shifts + i) * vb); };
     double* dd = (double*)dev.p;  // device scalars
     double* hd = ctx->host_d;     // pinned staging, same offsets
-    const int c_s0 = 2, c_ai = 4, c_a = 4 + 2 * n_shifts, c_zi = 6 + 2 * n_shifts, c_one = 6 + 4 * n_shifts;
+    const int c_s0 = 2, c_a = 4, c_up = 6;
     double s0 = shifts[0];
     for (int i = 1; i < n_shifts; i++) s0 = std::min(s0, shifts[i]);
     auto stage = [&](int off, int count) -> qcdw_status {  // copy hd[off, off + count) to the device
@@ -82,10 +105,7 @@ extern "C" qcdw_status qcdw_invert_multishift(qcdw_op* op, const void* b_e, void
     }
     hd[c_s0] = s0;
     hd[c_s0 + 1] = 0.0;
-    hd[c_one] = 1.0;
-    hd[c_one + 1] = 0.0;
     CHK(stage(c_s0, 2));
-    CHK(stage(c_one, 2));
     double bb;
     CHK(read_dot(r, r, bb));  // synchronises: the staged constants are on the device
     std::vector<double> z(n_shifts, 1.0), z_old(n_shifts, 1.0), z_new(n_shifts);
@@ -109,30 +129,24 @@ extern "C" qcdw_status qcdw_invert_multishift(qcdw_op* op, const void* b_e, void
         for (int i = 0; i < n_shifts; i++) {
             const double d = shifts[i] - s0;
             z_new[i] = z[i] * z_old[i] * a_old / (a * b_old * (z_old[i] - z[i]) + z_old[i] * a_old * (1.0 + d * a));
-            hd[c_ai + 2 * i] = a * z_new[i] / z[i];  // alpha_i
-            hd[c_ai + 2 * i + 1] = 0.0;
         }
         hd[c_a] = a;
         hd[c_a + 1] = 0.0;
-        CHK(stage(c_ai, 2 * n_shifts + 2));
-        for (int i = 0; i < n_shifts; i++)  // x_i += alpha_i p_i
-            HIPCHK(ctx, launch_multiaxpy(s, P(i), 0, 1, dd + c_ai + 2 * i, X(i), n, 1.0));
+        CHK(stage(c_a, 2));
         HIPCHK(ctx, launch_multiaxpy(s, w, 0, 1, dd + c_a, r, n, -1.0));  // r -= alpha w
         double rr_new;
         CHK(read_dot(r, r, rr_new));
         const double beta = rr_new / rr;
         for (int i = 0; i < n_shifts; i++) {
-            hd[c_zi + 2 * i] = z_new[i];
-            hd[c_zi + 2 * i + 1] = 0.0;
+            hd[c_up + 3 * i] = a * z_new[i] / z[i];                                    // alpha_i
+            hd[c_up + 3 * i + 1] = z_new[i];                                           // zeta_i'
+            hd[c_up + 3 * i + 2] = beta * (z_new[i] / z[i]) * (z_new[i] / z[i]);      // beta_i
         }
-        CHK(stage(c_zi, 2 * n_shifts));
-        for (int i = 0; i < n_shifts; i++) {  // p_i = zeta_i' r + beta_i p_i
-            const double bi = beta * (z_new[i] / z[i]) * (z_new[i] / z[i]);
-            HIPCHK(ctx, launch_convert(s, F64, F64, P(i), P(i), n, bi, nullptr));
-            HIPCHK(ctx, launch_multiaxpy(s, r, 0, 1, dd + c_zi + 2 * i, P(i), n, 1.0));
-        }
-        HIPCHK(ctx, launch_convert(s, F64, F64, p, p, n, beta, nullptr));  // p = r + beta p
-        HIPCHK(ctx, launch_multiaxpy(s, r, 0, 1, dd + c_one, p, n, 1.0));
+        hd[c_up + 3 * n_shifts] = beta;
+        CHK(stage(c_up, 3 * n_shifts + 1));
+        hipLaunchKernelGGL(k_shift_update, dim3(blas_blocks(n)), dim3(256), 0, s, (double2*)X(0), (double2*)P(0),
+                           (double2*)p, (const double2*)r, n, n_shifts, dd + c_up);
+        HIPCHK(ctx, hipGetLastError());
         z_old = z;
         z = z_new;
         a_old = a;
