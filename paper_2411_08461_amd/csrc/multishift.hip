@@ -6,22 +6,189 @@
 // axpy pair per iteration, the operator is applied once.  M_hat^+ needs no kernel of its own: with
 // M^+ = g5 M g5 on the full lattice and A commuting with g5, the Schur complement S = A_ee M_hat
 // satisfies S^+ = g5 S g5, so M_hat^+ psi = g5 A_ee M_hat (g5 A_ee^-1 psi).  FP64 throughout; the
-// scalars are formed on the host (one synchronisation per dot product).
+// scalars live on the device (two one-block step kernels per iteration), shifts that have converged
+// drop out of the vector updates, and the host synchronises only to read the done flag.
+#include <cstddef>
+
 #include "host.h"
 
 namespace {
 
+constexpr int MS_MAX = 64;  // shifts per solve
+
+// Solver state on the device; wave 0 of the two step kernels owns it, every other kernel reads it.
+struct MsState {
+    double rr;            // (r, r) of the base system
+    double a;             // alpha of the current iteration (0 once done: r stays put)
+    double a_old, b_old;  // alpha and beta of the previous iteration
+    double stop;          // tol^2 (b, b)
+    int it, done, status, pad;  // status: 1 breakdown, 2 non-finite residual
+    double z[MS_MAX], z_old[MS_MAX], z_new[MS_MAX], d[MS_MAX], res2[MS_MAX];
+    int act[MS_MAX];            // shift still iterating
+    double c[4 * MS_MAX + 1];   // per shift [alpha_i, zeta_i', beta_i, active], then beta
+};
+
+// Sum the per-block partials of a dot product over a 256-thread block; every thread gets the sum.
+__device__ double sum_partials(const double* partials, int nb)
+{
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += 256) v[0] += partials[b];
+    __shared__ double tot[1];
+    block_sum_store<1>(v, tot);
+    __syncthreads();
+    return tot[0];
+}
+
+// partials of (r, r), and their total
+__global__ __launch_bounds__(256) void k_ms_norm(const double2* r, long n, double* partials)
+{
+    double acc[1] = {0.0};
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+        const double2 rv = r[e];
+        acc[0] += rv.x * rv.x + rv.y * rv.y;
+    }
+    block_sum_store<1>(acc, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_ms_total(const double* partials, int nb, double* out)
+{
+    const double v = sum_partials(partials, nb);
+    if (threadIdx.x == 0) *out = v;
+}
+
+// w = g5 w + s0 p (g5 negates the elements from `half` on: spins 2 and 3) and the partials of (p, w)
+__global__ __launch_bounds__(256) void k_ms_w_dot(double2* w, const double2* p, long n, long half, double s0,
+                                                  double* partials)
+{
+    double acc[1] = {0.0};
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+        const double2 pv = p[e];
+        double2 v = w[e];
+        const double sg = e < half ? 1.0 : -1.0;
+        v.x = sg * v.x + s0 * pv.x;
+        v.y = sg * v.y + s0 * pv.y;
+        w[e] = v;
+        acc[0] += pv.x * v.x + pv.y * v.y;
+    }
+    block_sum_store<1>(acc, partials + blockIdx.x);
+}
+
+// r -= alpha w and the partials of (r, r)
+__global__ __launch_bounds__(256) void k_ms_axpy_norm(double2* r, const double2* w, const MsState* st, long n,
+                                                      double* partials)
+{
+    const double a = st->a;
+    double acc[1] = {0.0};
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+        const double2 wv = w[e];
+        double2 rv = r[e];
+        rv.x -= a * wv.x;
+        rv.y -= a * wv.y;
+        r[e] = rv;
+        acc[0] += rv.x * rv.x + rv.y * rv.y;
+    }
+    block_sum_store<1>(acc, partials + blockIdx.x);
+}
+
+// alpha = (r, r) / (p, N p) and the next zeta of every live shift (Jegerlehner's recurrence with the
+// shift relative to the base shift, d_i = sigma_i - sigma_0)
+__global__ __launch_bounds__(256) void k_ms_alpha(MsState* st, const double* partials, int nb, int nshift)
+{
+    const double pw = sum_partials(partials, nb);
+    const int t = threadIdx.x;
+    if (t >= 64) return;
+    const int done = st->done;
+    double a = 0.0;
+    bool brk = false;
+    if (!done) {
+        if (!(pw > 0.0) || !isfinite(pw))
+            brk = true;
+        else
+            a = st->rr / pw;
+    }
+    if (t < nshift && !done && !brk && st->act[t]) {
+        const double z = st->z[t], zo = st->z_old[t], d = st->d[t];
+        const double ao = st->a_old, bo = st->b_old;
+        st->z_new[t] = z * zo * ao / (a * bo * (zo - z) + zo * ao * (1.0 + d * a));
+    }
+    if (t == 0) {
+        st->a = a;
+        if (brk) {
+            st->status = 1;
+            st->done = 1;
+        }
+    }
+}
+
+// beta = (r', r') / (r, r), the update coefficients of every shift, the shifted residuals |zeta_i'| |r'|;
+// a shift whose residual reaches the stopping value takes this last update and then stays put
+__global__ __launch_bounds__(256) void k_ms_beta(MsState* st, const double* partials, int nb, int nshift)
+{
+    const double rn = sum_partials(partials, nb);
+    const int t = threadIdx.x;
+    if (t >= 64) return;
+    double* c = st->c + 4 * t;
+    if (st->done) {
+        if (t < nshift) c[0] = c[1] = c[2] = c[3] = 0.0;
+        if (t == 0) st->c[4 * nshift] = 0.0;
+        return;
+    }
+    const double a = st->a;
+    bool bad = !isfinite(rn);
+    const double beta = bad ? 0.0 : rn / st->rr;
+    bool live = false;
+    if (t < nshift) {
+        if (st->act[t] && !bad) {
+            const double zn = st->z_new[t], z = st->z[t];
+            const double q = zn / z;
+            if (!isfinite(q)) {
+                bad = true;
+            } else {
+                c[0] = a * q;
+                c[1] = zn;
+                c[2] = beta * q * q;
+                c[3] = 1.0;
+                st->z_old[t] = z;
+                st->z[t] = zn;
+                const double r2 = zn * zn * rn;
+                if (r2 <= st->stop) {
+                    st->act[t] = 0;
+                    st->res2[t] = r2;
+                } else {
+                    live = true;
+                }
+            }
+        }
+        if (bad) c[0] = c[1] = c[2] = c[3] = 0.0;
+    }
+    const unsigned long long any_live = __ballot(live), any_bad = __ballot(bad);
+    if (t == 0) {
+        st->c[4 * nshift] = beta;
+        if (any_bad) {
+            st->status = 2;
+            st->done = 1;
+        } else {
+            st->a_old = a;
+            st->b_old = beta;
+            st->rr = rn;
+            st->it += 1;
+            if (!any_live) st->done = 1;
+        }
+    }
+}
+
 // All shifted updates of one iteration in one pass, reading each old p_i once:
-//   x_i += alpha_i p_i,  p_i = zeta_i' r + beta_i p_i  (i < nshift),  p = r + beta p.
-// c = [alpha_i, zeta_i', beta_i] per shift, then beta; vectors X_i, P_i at stride n (complex elements).
+//   x_i += alpha_i p_i,  p_i = zeta_i' r + beta_i p_i  (live shifts only),  p = r + beta p.
+// c = [alpha_i, zeta_i', beta_i, active] per shift, then beta; vectors X_i, P_i at stride n (complex).
 __global__ __launch_bounds__(256) void k_shift_update(double2* X, double2* P, double2* p, const double2* r, long n,
                                                       int nshift, const double* c)
 {
-    const double beta = c[3 * nshift];
+    const double beta = c[4 * nshift];
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
         const double2 rv = r[e];
         for (int i = 0; i < nshift; i++) {
-            const double a = c[3 * i], z = c[3 * i + 1], b = c[3 * i + 2];
+            if (c[4 * i + 3] == 0.0) continue;
+            const double a = c[4 * i], z = c[4 * i + 1], b = c[4 * i + 2];
             const double2 pv = P[(long)i * n + e];
             double2 xv = X[(long)i * n + e];
             xv.x += a * pv.x;
@@ -40,6 +207,12 @@ hipError_t apply_g5(hipStream_t s, void* v, const Geom& g)
     void* hi = (char*)v + 6L * g.Vh * 16;
     return launch_convert(s, F64, F64, hi, hi, 6L * g.Vh, -1.0, nullptr);
 }
+
+// Drains the stream when the solve returns, so pooled buffers go back to the cache idle.
+struct DrainOnExit {
+    hipStream_t s;
+    ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+};
 
 }  // namespace
 
@@ -65,37 +238,20 @@ extern "C" qcdw_status qcdw_invert_multishift(qcdw_op* op, const void* b_e, void
     const size_t vb = (size_t)n * 16;
     const PrecView v = view(op, F64);
     hipStream_t s = ctx->stream;
-    // r, p, w, t1, t2, tmp_o, then X_i, P_i
-    DevBuf buf, part, dev;
+    const int nb = blas_blocks(n);
+    // r, p, w, t1, t2, tmp_o, then X_i, P_i; the partials of one dot product; the solver state
+    PoolBuf buf, part, state;
     HIPCHK(ctx, buf.alloc(vb * (6 + 2 * (size_t)n_shifts)));
-    HIPCHK(ctx, part.alloc(16UL * 2048 * sizeof(double)));
-    // device scalars: [0, 2) a dot product; [2, 4) the base shift and [4, 6) alpha as complex pairs for
-    // the axpys; [6, 7 + 3n) the shifted-update coefficients [alpha_i, zeta_i', beta_i] and beta.  Each
-    // block is staged at the same offset of the pinned host buffer and copied once, after the
-    // synchronisation that precedes it, so no staged value is overwritten before its copy has run.
-    const int nsc = 7 + 3 * n_shifts;
-    static_assert(HOST_D_N >= 7 + 3 * 64, "pinned host staging too small for 64 shifts");
-    HIPCHK(ctx, dev.alloc(nsc * sizeof(double)));
+    HIPCHK(ctx, part.alloc((size_t)nb * sizeof(double)));
+    HIPCHK(ctx, state.alloc(sizeof(MsState)));
+    DrainOnExit drain{s};
     char* base = (char*)buf.p;
     void *r = base, *p = base + vb, *w = base + 2 * vb, *t1 = base + 3 * vb, *t2 = base + 4 * vb, *tmpo = base + 5 * vb;
     auto X = [&](int i) { return (void*)(base + (6 + i) * vb); };
     auto P = [&](int i) { return (void*)(base + (6 + n_shifts + i) * vb); };
-    double* dd = (double*)dev.p;  // device scalars
-    double* hd = ctx->host_d;     // pinned staging, same offsets
-    const int c_s0 = 2, c_a = 4, c_up = 6;
+    MsState* st = (MsState*)state.p;
     double s0 = shifts[0];
     for (int i = 1; i < n_shifts; i++) s0 = std::min(s0, shifts[i]);
-    auto stage = [&](int off, int count) -> qcdw_status {  // copy hd[off, off + count) to the device
-        HIPCHK(ctx, hipMemcpyAsync(dd + off, hd + off, count * sizeof(double), hipMemcpyHostToDevice, s));
-        return QCDW_OK;
-    };
-    auto read_dot = [&](const void* a, const void* b_, double& re) -> qcdw_status {
-        HIPCHK(ctx, launch_multidot(s, a, 0, 1, b_, n, (double*)part.p, dd));
-        HIPCHK(ctx, hipMemcpyAsync(hd, dd, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        re = hd[0];
-        return QCDW_OK;
-    };
 
     HIPCHK(ctx, launch_pack_spinor(s, F64, g, b_e, 0, r, 1.0));
     HIPCHK(ctx, launch_convert(s, F64, F64, r, p, n, 1.0, nullptr));
@@ -103,67 +259,61 @@ extern "C" qcdw_status qcdw_invert_multishift(qcdw_op* op, const void* b_e, void
         HIPCHK(ctx, launch_convert(s, F64, F64, r, P(i), n, 1.0, nullptr));
         HIPCHK(ctx, hipMemsetAsync(X(i), 0, vb, s));
     }
-    hd[c_s0] = s0;
-    hd[c_s0 + 1] = 0.0;
-    CHK(stage(c_s0, 2));
-    double bb;
-    CHK(read_dot(r, r, bb));  // synchronises: the staged constants are on the device
-    std::vector<double> z(n_shifts, 1.0), z_old(n_shifts, 1.0), z_new(n_shifts);
-    double a_old = 1.0, b_old = 0.0, rr = bb;
-    const double stop = tol * tol * bb;
-    int it = 0;
-    bool conv = bb == 0.0;
-    while (!conv && it < maxiter) {
-        // w = (M_hat^+ M_hat + s0) p
+    double* hd = ctx->host_d;  // pinned
+    hipLaunchKernelGGL(k_ms_norm, dim3(nb), dim3(256), 0, s, (const double2*)r, n, (double*)part.p);
+    hipLaunchKernelGGL(k_ms_total, dim3(1), dim3(256), 0, s, (const double*)part.p, nb, (double*)t1);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(hd, t1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const double bb = hd[0];
+    if (!std::isfinite(bb)) return fail(ctx, QCDW_ENAN, "multi-shift CG: non-finite source norm");
+    MsState h{};
+    h.rr = bb;
+    h.a_old = 1.0;
+    h.stop = tol * tol * bb;
+    h.done = bb == 0.0;
+    for (int i = 0; i < n_shifts; i++) {
+        h.z[i] = h.z_old[i] = 1.0;
+        h.d[i] = shifts[i] - s0;
+        h.act[i] = 1;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(st, &h, sizeof(MsState), hipMemcpyHostToDevice, s));
+    // The scalars stay on the device: the host enqueues iterations and reads the done flag every
+    // CHECK iterations; iterations enqueued after convergence change nothing (alpha = 0, no live shift).
+    constexpr int CHECK = 4;
+    const size_t flags_off = offsetof(MsState, it);
+    for (int k = 0; k < maxiter && !h.done; k++) {
+        // w = (M_hat^+ M_hat + s0) p, M_hat^+ = g5 A_ee M_hat g5 A_ee^-1
         HIPCHK(ctx, matpc(s, op, v, p, t1, tmpo, RED_NONE, nullptr, nullptr, nullptr));
         HIPCHK(ctx, launch_clov_apply_internal(s, F64, g, op->Ainv64[0].p, t1, t2));
         HIPCHK(ctx, apply_g5(s, t2, g));
         HIPCHK(ctx, matpc(s, op, v, t2, t1, tmpo, RED_NONE, nullptr, nullptr, nullptr));
         HIPCHK(ctx, launch_clov_apply_internal(s, F64, g, op->A64[0].p, t1, w));
-        HIPCHK(ctx, apply_g5(s, w, g));
-        if (s0 != 0.0) HIPCHK(ctx, launch_multiaxpy(s, p, 0, 1, dd + c_s0, w, n, 1.0));
-        double pw;
-        CHK(read_dot(p, w, pw));
-        if (!(pw > 0.0) || !std::isfinite(pw)) return fail(ctx, QCDW_EBREAKDOWN, "multi-shift CG: (p, N p) = %g", pw);
-        const double a = rr / pw;
-        for (int i = 0; i < n_shifts; i++) {
-            const double d = shifts[i] - s0;
-            z_new[i] = z[i] * z_old[i] * a_old / (a * b_old * (z_old[i] - z[i]) + z_old[i] * a_old * (1.0 + d * a));
-        }
-        hd[c_a] = a;
-        hd[c_a + 1] = 0.0;
-        CHK(stage(c_a, 2));
-        HIPCHK(ctx, launch_multiaxpy(s, w, 0, 1, dd + c_a, r, n, -1.0));  // r -= alpha w
-        double rr_new;
-        CHK(read_dot(r, r, rr_new));
-        const double beta = rr_new / rr;
-        for (int i = 0; i < n_shifts; i++) {
-            hd[c_up + 3 * i] = a * z_new[i] / z[i];                                    // alpha_i
-            hd[c_up + 3 * i + 1] = z_new[i];                                           // zeta_i'
-            hd[c_up + 3 * i + 2] = beta * (z_new[i] / z[i]) * (z_new[i] / z[i]);      // beta_i
-        }
-        hd[c_up + 3 * n_shifts] = beta;
-        CHK(stage(c_up, 3 * n_shifts + 1));
-        hipLaunchKernelGGL(k_shift_update, dim3(blas_blocks(n)), dim3(256), 0, s, (double2*)X(0), (double2*)P(0),
-                           (double2*)p, (const double2*)r, n, n_shifts, dd + c_up);
+        hipLaunchKernelGGL(k_ms_w_dot, dim3(nb), dim3(256), 0, s, (double2*)w, (const double2*)p, n, 6L * g.Vh, s0,
+                           (double*)part.p);
+        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(256), 0, s, st, (const double*)part.p, nb, n_shifts);
+        hipLaunchKernelGGL(k_ms_axpy_norm, dim3(nb), dim3(256), 0, s, (double2*)r, (const double2*)w,
+                           (const MsState*)st, n, (double*)part.p);
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(256), 0, s, st, (const double*)part.p, nb, n_shifts);
+        hipLaunchKernelGGL(k_shift_update, dim3(nb), dim3(256), 0, s, (double2*)X(0), (double2*)P(0), (double2*)p,
+                           (const double2*)r, n, n_shifts, (const double*)st->c);
         HIPCHK(ctx, hipGetLastError());
-        z_old = z;
-        z = z_new;
-        a_old = a;
-        b_old = beta;
-        rr = rr_new;
-        it++;
-        if (!std::isfinite(rr)) return fail(ctx, QCDW_ENAN, "multi-shift CG: non-finite residual");
-        conv = true;  // residual of shift i: |zeta_i| |r|
-        for (int i = 0; i < n_shifts; i++)
-            if (z[i] * z[i] * rr > stop) conv = false;
+        if ((k + 1) % CHECK == 0 || k + 1 == maxiter) {
+            HIPCHK(ctx, hipMemcpyAsync(hd, (char*)st + flags_off, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            std::memcpy(&h.it, hd, 4 * sizeof(int));
+        }
     }
-    for (int i = 0; i < n_shifts; i++) {
-        HIPCHK(ctx, launch_unpack_spinor(s, F64, g, X(i), 0, x_e[i], 1.0));
-        res[i] = bb > 0.0 ? std::fabs(z[i]) * std::sqrt(rr / bb) : 0.0;
-    }
+    HIPCHK(ctx, hipMemcpyAsync(&h, st, sizeof(MsState), hipMemcpyDeviceToHost, s));
+    for (int i = 0; i < n_shifts; i++) HIPCHK(ctx, launch_unpack_spinor(s, F64, g, X(i), 0, x_e[i], 1.0));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    *iters = it;
-    if (!conv) return fail(ctx, QCDW_ENOCONV, "multi-shift CG did not converge within %d iterations", maxiter);
+    *iters = h.it;
+    for (int i = 0; i < n_shifts; i++) {
+        const double r2 = h.act[i] ? h.z[i] * h.z[i] * h.rr : h.res2[i];
+        res[i] = bb > 0.0 ? std::sqrt(r2 / bb) : 0.0;
+    }
+    if (h.status == 1) return fail(ctx, QCDW_EBREAKDOWN, "multi-shift CG: (p, N p) is not positive");
+    if (h.status == 2) return fail(ctx, QCDW_ENAN, "multi-shift CG: non-finite residual");
+    if (!h.done) return fail(ctx, QCDW_ENOCONV, "multi-shift CG did not converge within %d iterations", maxiter);
     return QCDW_OK;
 }

@@ -61,3 +61,35 @@ def test_multishift_argument_errors(ctx):
     it, res = q.qcdw_invert_multishift(op, b, [x], [0.1])  # b = 0: x = 0 at once
     assert it == 0 and float(x.abs().max()) == 0.0
     op.close()
+
+
+def test_multishift_iteration_cap_and_repeat(ctx):
+    """maxiter below the need raises (QCDW_ENOCONV) for every cap, including caps that fall between
+    the solver's done-flag reads; a second solve on the same context reproduces the first bit for bit
+    (the device state is rebuilt per call); the largest shift alone converges in fewer iterations, and
+    in the joint solve its solution, frozen once converged, still equals the dense solve."""
+    L, t_bc = (6, 4, 2, 6), -1
+    U = li.random_gauge(L, 0.3, 101)
+    Vh = int(np.prod(L)) // 2
+    b = dev(li.gaussian_source(L, 102).reshape(-1, 4, 3)[:Vh].copy())
+    op = q.Operator(ctx, q.make_lattice(L, t_bc), dev(U), 0.12, 1.0)
+    for cap in (1, 3, 5):
+        xs = [torch.empty_like(b) for _ in range(2)]
+        with pytest.raises(q.QcdwError):
+            q.qcdw_invert_multishift(op, b, xs, [0.0, 0.5], maxiter=cap)
+    shifts = [0.0, 0.02, 4.0]
+    runs = []
+    for _ in range(2):
+        xs = [torch.empty_like(b) for _ in shifts]
+        it, res = q.qcdw_invert_multishift(op, b, xs, shifts, tol=1e-10)
+        runs.append((it, res, [x.cpu().numpy() for x in xs]))
+    assert runs[0][0] == runs[1][0] and runs[0][1] == runs[1][1]
+    for a, c in zip(runs[0][2], runs[1][2]):
+        assert np.array_equal(a, c)
+    it_big, _ = q.qcdw_invert_multishift(op, b, [torch.empty_like(b)], [4.0], tol=1e-10)
+    assert it_big < runs[0][0]
+    Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), 0.12, 1.0)
+    expect = oracle.normal_shifted_solve(L, U, Ainv, b.cpu().numpy(), 0.12, shifts, t_bc)
+    for x, e in zip(runs[0][2], expect):
+        assert np.linalg.norm(x.reshape(-1) - e.reshape(-1)) / np.linalg.norm(e) <= 1e-7
+    op.close()
