@@ -138,6 +138,7 @@ __global__ __launch_bounds__(256) void k_ms_beta(MsState* st, const double* part
     const double beta = bad ? 0.0 : rn / st->rr;
     bool live = false;
     if (t < nshift) {
+        bool upd = false;  // this shift takes an update in this iteration
         if (st->act[t] && !bad) {
             const double zn = st->z_new[t], z = st->z[t];
             const double q = zn / z;
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(256) void k_ms_beta(MsState* st, const double* part
                 c[1] = zn;
                 c[2] = beta * q * q;
                 c[3] = 1.0;
+                upd = true;
                 st->z_old[t] = z;
                 st->z[t] = zn;
                 const double r2 = zn * zn * rn;
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void k_ms_beta(MsState* st, const double* part
                 }
             }
         }
-        if (bad) c[0] = c[1] = c[2] = c[3] = 0.0;
+        if (!upd) c[0] = c[1] = c[2] = c[3] = 0.0;  // converged earlier (or failed): x_i and p_i stay put
     }
     const unsigned long long any_live = __ballot(live), any_bad = __ballot(bad);
     if (t == 0) {

@@ -67,7 +67,7 @@ def test_multishift_iteration_cap_and_repeat(ctx):
     """maxiter below the need raises (QCDW_ENOCONV) for every cap, including caps that fall between
     the solver's done-flag reads; a second solve on the same context reproduces the first bit for bit
     (the device state is rebuilt per call); the largest shift alone converges in fewer iterations, and
-    in the joint solve its solution, frozen once converged, still equals the dense solve."""
+    in the joint solve its solution is frozen once converged and equals the dense solve."""
     L, t_bc = (6, 4, 2, 6), -1
     U = li.random_gauge(L, 0.3, 101)
     Vh = int(np.prod(L)) // 2
@@ -87,7 +87,14 @@ def test_multishift_iteration_cap_and_repeat(ctx):
     for a, c in zip(runs[0][2], runs[1][2]):
         assert np.array_equal(a, c)
     it_big, _ = q.qcdw_invert_multishift(op, b, [torch.empty_like(b)], [4.0], tol=1e-10)
-    assert it_big < runs[0][0]
+    assert it_big + 4 < runs[0][0]
+    # stopped a few iterations after the shift 4.0 has converged: its solution is already the final one
+    # bit for bit, since a converged shift takes no further updates
+    xs_cap = [torch.empty_like(b) for _ in shifts]
+    with pytest.raises(q.QcdwError):
+        q.qcdw_invert_multishift(op, b, xs_cap, shifts, tol=1e-10, maxiter=it_big + 4)
+    assert np.array_equal(xs_cap[2].cpu().numpy(), runs[0][2][2])
+    assert not np.array_equal(xs_cap[0].cpu().numpy(), runs[0][2][0])
     Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), 0.12, 1.0)
     expect = oracle.normal_shifted_solve(L, U, Ainv, b.cpu().numpy(), 0.12, shifts, t_bc)
     for x, e in zip(runs[0][2], expect):
