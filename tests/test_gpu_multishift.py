@@ -100,3 +100,49 @@ def test_multishift_iteration_cap_and_repeat(ctx):
     for x, e in zip(runs[0][2], expect):
         assert np.linalg.norm(x.reshape(-1) - e.reshape(-1)) / np.linalg.norm(e) <= 1e-7
     op.close()
+
+
+def test_multishift_bench_workload_true_residuals(ctx):
+    """The benchmark's workload (16^3x32, 8 shifts 1e-4 * 4^k, Gaussian even-site source, tol 1e-10): every
+    shifted solution's true residual ||b - (M_hat^+ M_hat + s) x|| / ||b||, with M_hat and the adjoint composed
+    on the CPU from the oracle's Schur operator, clover term and clover inverse (M_hat^+ = g5 A_ee M_hat g5
+    A_ee^-1, the identity pinned on dense matrices), is within 5e-10."""
+    w = li.WORKLOADS["wc16x32"]
+    L, kappa, csw = w["L"], w["kappa"], w["csw"]
+    Vh = int(np.prod(L)) // 2
+    U = li.random_gauge(L, w["eps"], w["seed"])
+    b = li.gaussian_source(L, 1009).reshape(-1, 4, 3)[:Vh].copy()
+    shifts = [1e-4 * 4 ** k for k in range(8)]
+    op = q.Operator(ctx, q.make_lattice(L), dev(U), kappa, csw)
+    xs = [torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda") for _ in shifts]
+    it, res = q.qcdw_invert_multishift(op, dev(b), xs, shifts, tol=1e-10)
+    op.close()
+    assert max(res) <= 1e-10
+    C = oracle.clover_build(L, U)
+    Ainv, _ = oracle.clover_invert(L, C, kappa, csw)
+
+    def g5(v):
+        v = v.copy()
+        v[:, 2:, :] *= -1.0
+        return v
+
+    def even(full):
+        return np.asarray(full).reshape(-1, 4, 3)[:Vh]
+
+    def embed(v):
+        full = np.zeros((2 * Vh, 4, 3), dtype=np.complex128)
+        full[:Vh] = v
+        return full.reshape(li.fermion_shape(L))
+
+    def mhat(v):
+        return oracle.schur_matpc(L, U, Ainv, v, kappa)
+
+    def mhat_dag(v):
+        t = even(oracle.packed_apply(L, Ainv, embed(v)))
+        t = mhat(g5(t))
+        return g5(even(oracle.clover_apply(L, C, embed(t), kappa, csw)))
+
+    for x, s in zip(xs, shifts):
+        xh = x.cpu().numpy()
+        r = b - mhat_dag(mhat(xh)) - s * xh
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 5e-10, s
