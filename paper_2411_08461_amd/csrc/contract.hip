@@ -55,22 +55,23 @@ __global__ __launch_bounds__(256) void k_wall_sources(double2* out, Geom g, int 
     out[e] = v;
 }
 
-__global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
+// One lane (s, s0) of a site's 16: the (s, s0) term of Tr[G_snk S(x) G_src g5 T(x)^+ g5] with the monomial
+// gammas, summed over the site's lanes in a fixed order; lane 0 stores it with the momentum phase.
+// f1(k, sp) / f2(k, sp) give the 3 colours of field k, spin sp at this site, from memory or LDS.
+template <class F1, class F2>
+__device__ __forceinline__ void meson_site(const MesonArgs& a, long V, long x, int lane, F1 f1, F2 f2)
 {
-    const long V = 2L * a.g.Vh;
-    const long x = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    const int lane = threadIdx.x & 15;
     const int s = lane >> 2, s0 = lane & 3;
     double re = 0.0, im = 0.0;
     if (x < V) {
         const int sa = a.perm_a[s], sb = a.perm_b[s0];
 #pragma unroll
         for (int c0 = 0; c0 < 3; c0++) {
-            const double2* f1 = a.S + (((long)(3 * s0 + c0) * V + x) * 4 + sa) * 3;  // S_{3 s0 + c0}[perm_A(s)]
-            const double2* f2 = a.T + (((long)(3 * sb + c0) * V + x) * 4 + s) * 3;   // T_{3 perm_B(s0) + c0}[s]
+            const double2* u3 = f1(3 * s0 + c0, sa);  // S_{3 s0 + c0}[perm_A(s)]
+            const double2* w3 = f2(3 * sb + c0, s);   // T_{3 perm_B(s0) + c0}[s]
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const double2 u = f1[c], w = f2[c];  // u conj(w)
+                const double2 u = u3[c], w = w3[c];  // u conj(w)
                 re += u.x * w.x + u.y * w.y;
                 im += u.y * w.x - u.x * w.y;
             }
@@ -98,6 +99,39 @@ __global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
         sincos(-(a.px * X + a.py * Y + a.pz * Z), &sn, &cs);
         a.site[x] = make_double2(cs * re - sn * im, cs * im + sn * re);
     }
+}
+
+// 16 lanes per site, operands read from memory (two different propagators)
+__global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
+{
+    const long V = 2L * a.g.Vh;
+    const long x = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const long xs = x < V ? x : 0;
+    auto fS = [&](int k, int sp) { return a.S + (((long)k * V + xs) * 4 + sp) * 3; };
+    auto fT = [&](int k, int sp) { return a.T + (((long)k * V + xs) * 4 + sp) * 3; };
+    meson_site(a, V, x, threadIdx.x & 15, fS, fT);
+}
+
+// T = S (the two-point function): the 12 x 12 matrices of the block's 16 sites are staged in LDS with
+// coalesced loads (for each field the 16 sites' 192 complex numbers are contiguous), so every element is
+// read from HBM once; the lanes then take their rows and columns from LDS.
+constexpr int MESON_SITES = 16;                 // sites per 256-thread block
+constexpr int MESON_TILE = MESON_SITES * 12;    // complex numbers per field and block
+__global__ __launch_bounds__(256) void k_meson_sites_same(MesonArgs a)
+{
+    __shared__ double2 sm[12 * MESON_TILE];
+    const long V = 2L * a.g.Vh;
+    const long x0 = (long)blockIdx.x * MESON_SITES;
+    for (int idx = threadIdx.x; idx < 12 * MESON_TILE; idx += 256) {
+        const int k = idx / MESON_TILE, r = idx - k * MESON_TILE;  // r = 12 site + (3 spin + colour)
+        double2 v = make_double2(0.0, 0.0);
+        if (x0 + r / 12 < V) v = a.S[((long)k * V + x0) * 12 + r];
+        sm[idx] = v;
+    }
+    __syncthreads();
+    const int sl = threadIdx.x >> 4;
+    auto fL = [&](int k, int sp) { return (const double2*)sm + k * MESON_TILE + sl * 12 + sp * 3; };
+    meson_site(a, V, x0 + sl, threadIdx.x & 15, fL, fL);
 }
 
 // Sequential sources: out_k(x)[s][c] = delta(x_t, t_f) e^{+i p.x} G[s][perm(s)] S_k(x)[perm(s)][c] with the
@@ -245,8 +279,11 @@ hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, const v
     a.px = mom_comp(mom[0], g.Lx);
     a.py = mom_comp(mom[1], g.Ly);
     a.pz = mom_comp(mom[2], g.Lz);
-    const long threads = 2L * g.Vh * 16;
-    hipLaunchKernelGGL(k_meson_sites, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+    const long threads = 2L * g.Vh * 16;  // 16 lanes per site: one block per 16 sites
+    if (S == T)
+        hipLaunchKernelGGL(k_meson_sites_same, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_meson_sites, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_slice_sum, dim3(g.Lt), dim3(256), 0, s, (const double2*)site_scratch, (double2*)out, g);
     return hipGetLastError();
 }
