@@ -97,10 +97,12 @@ qcdw_status qcdw_meson_contract(qcdw_ctx* ctx, const qcdw_lattice* lat, const vo
     CHK(check_dev(ctx, S, "S"));
     CHK(check_dev(ctx, T, "T"));
     CHK(check_dev(ctx, out, "out"));
-    DevBuf site;  // per-site contributions
+    PoolBuf site;  // per-site contributions, from the block cache; the stream is drained before it goes back
     HIPCHK(ctx, site.alloc(2UL * g.Vh * 16));
-    HIPCHK(ctx, launch_meson_2pt(ctx->stream, g, S, T, gamma_snk, gamma_src, mom, site.p, out));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const hipError_t launched = launch_meson_2pt(ctx->stream, g, S, T, gamma_snk, gamma_src, mom, site.p, out);
+    const hipError_t drained = hipStreamSynchronize(ctx->stream);
+    HIPCHK(ctx, launched);
+    HIPCHK(ctx, drained);
     return QCDW_OK;
 }
 
