@@ -122,12 +122,17 @@ __global__ __launch_bounds__(256) void k_meson_sites_same(MesonArgs a)
     __shared__ double2 sm[12 * MESON_TILE];
     const long V = 2L * a.g.Vh;
     const long x0 = (long)blockIdx.x * MESON_SITES;
-    for (int idx = threadIdx.x; idx < 12 * MESON_TILE; idx += 256) {
+    constexpr int LOADS = 12 * MESON_TILE / 256;  // 9 per thread, all issued before the first LDS store
+    static_assert(LOADS * 256 == 12 * MESON_TILE, "staging loop must tile the block's matrices exactly");
+    double2 v[LOADS];
+#pragma unroll
+    for (int j = 0; j < LOADS; j++) {
+        const int idx = j * 256 + threadIdx.x;
         const int k = idx / MESON_TILE, r = idx - k * MESON_TILE;  // r = 12 site + (3 spin + colour)
-        double2 v = make_double2(0.0, 0.0);
-        if (x0 + r / 12 < V) v = a.S[((long)k * V + x0) * 12 + r];
-        sm[idx] = v;
+        v[j] = x0 + r / 12 < V ? a.S[((long)k * V + x0) * 12 + r] : make_double2(0.0, 0.0);
     }
+#pragma unroll
+    for (int j = 0; j < LOADS; j++) sm[j * 256 + threadIdx.x] = v[j];
     __syncthreads();
     const int sl = threadIdx.x >> 4;
     auto fL = [&](int k, int sp) { return (const double2*)sm + k * MESON_TILE + sl * 12 + sp * 3; };
