@@ -434,6 +434,19 @@ def propagator(q, li, np, torch, ctx, fields, args):
     torch.cuda.synchronize()
     t_con = (time.perf_counter() - t0) / 5
     pion = corr.cpu().numpy()
+    # the same trace through the two-propagator (three-point) kernel with a copy as the backward leg: it
+    # reads twice the bytes and must give the pion bit for bit (same per-site arithmetic and order)
+    x2 = x.clone()
+    corr2 = torch.empty_like(corr)
+    q.qcdw_meson_contract(ctx, lat, x, x2, 15, 15, (0, 0, 0), corr2)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        q.qcdw_meson_contract(ctx, lat, x, x2, 15, 15, (0, 0, 0), corr2)
+    torch.cuda.synchronize()
+    t_con2 = (time.perf_counter() - t0) / 5
+    same2 = bool(np.array_equal(corr2.cpu().numpy(), pion))
+    del x2
     # hop bandwidth of the multi-RHS kernel: a capped solve with every hop dispatch timed
     pt = q.make_params(tol=1e-10, maxiter=16, inner="bf16", collect_timing=True, check_every=8)
     xt = torch.zeros_like(bs)
@@ -452,7 +465,10 @@ def propagator(q, li, np, torch, ctx, fields, args):
             "pion_2pt": {"call_ms": round(1e3 * t_con, 3),
                          "gbs_incl_call": round(12 * 192 * 2 * Vh / t_con / 1e9, 1),
                          "c_t0": float(pion[0].real), "c_t_mid": float(pion[L[3] // 2].real),
-                         "positive": bool((pion.real > 0).all())}}
+                         "positive": bool((pion.real > 0).all())},
+            "two_propagator_contract": {"call_ms": round(1e3 * t_con2, 3),
+                                        "gbs_incl_call": round(2 * 12 * 192 * 2 * Vh / t_con2 / 1e9, 1),
+                                        "equals_pion": same2}}
 
 
 def batch_jobs(li):

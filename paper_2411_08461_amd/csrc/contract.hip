@@ -101,42 +101,37 @@ __device__ __forceinline__ void meson_site(const MesonArgs& a, long V, long x, i
     }
 }
 
-// 16 lanes per site, operands read from memory (two different propagators)
-__global__ __launch_bounds__(256) void k_meson_sites(MesonArgs a)
+// The 12 x 12 matrices of a block's SITES sites (of S, and of T unless SAME) are staged in LDS with coalesced
+// loads (for each field the sites' 12 SITES complex numbers are contiguous), so every element is read from HBM
+// once; each thread issues all its loads before its first LDS store, so they are in flight together.  The lanes
+// then take their rows and columns from LDS.  SAME (T = S, the two-point function): 16 sites per 256-thread
+// block; otherwise 8 sites per 128-thread block.  Either way the block holds 36 KB of LDS.
+template <int SITES, bool SAME>
+__global__ __launch_bounds__(SITES * 16) void k_meson_sites(MesonArgs a)
 {
+    constexpr int NT = SITES * 16, TILE = SITES * 12, NB = SAME ? 1 : 2;
+    constexpr int FIELDS = 12 * TILE;             // complex numbers of one propagator per block
+    constexpr int LOADS = NB * FIELDS / NT;       // per thread: 9 (SAME) or 18
+    static_assert(LOADS * NT == NB * FIELDS, "staging loop must tile the block's matrices exactly");
+    __shared__ double2 sm[NB * FIELDS];
     const long V = 2L * a.g.Vh;
-    const long x = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    const long xs = x < V ? x : 0;
-    auto fS = [&](int k, int sp) { return a.S + (((long)k * V + xs) * 4 + sp) * 3; };
-    auto fT = [&](int k, int sp) { return a.T + (((long)k * V + xs) * 4 + sp) * 3; };
-    meson_site(a, V, x, threadIdx.x & 15, fS, fT);
-}
-
-// T = S (the two-point function): the 12 x 12 matrices of the block's 16 sites are staged in LDS with
-// coalesced loads (for each field the 16 sites' 192 complex numbers are contiguous), so every element is
-// read from HBM once; the lanes then take their rows and columns from LDS.
-constexpr int MESON_SITES = 16;                 // sites per 256-thread block
-constexpr int MESON_TILE = MESON_SITES * 12;    // complex numbers per field and block
-__global__ __launch_bounds__(256) void k_meson_sites_same(MesonArgs a)
-{
-    __shared__ double2 sm[12 * MESON_TILE];
-    const long V = 2L * a.g.Vh;
-    const long x0 = (long)blockIdx.x * MESON_SITES;
-    constexpr int LOADS = 12 * MESON_TILE / 256;  // 9 per thread, all issued before the first LDS store
-    static_assert(LOADS * 256 == 12 * MESON_TILE, "staging loop must tile the block's matrices exactly");
+    const long x0 = (long)blockIdx.x * SITES;
     double2 v[LOADS];
 #pragma unroll
     for (int j = 0; j < LOADS; j++) {
-        const int idx = j * 256 + threadIdx.x;
-        const int k = idx / MESON_TILE, r = idx - k * MESON_TILE;  // r = 12 site + (3 spin + colour)
-        v[j] = x0 + r / 12 < V ? a.S[((long)k * V + x0) * 12 + r] : make_double2(0.0, 0.0);
+        const int idx = j * NT + threadIdx.x;
+        const int b = idx / FIELDS, rem = idx - b * FIELDS;
+        const int k = rem / TILE, r = rem - k * TILE;  // r = 12 site + (3 spin + colour)
+        const double2* src = b ? a.T : a.S;
+        v[j] = x0 + r / 12 < V ? src[((long)k * V + x0) * 12 + r] : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int j = 0; j < LOADS; j++) sm[j * 256 + threadIdx.x] = v[j];
+    for (int j = 0; j < LOADS; j++) sm[j * NT + threadIdx.x] = v[j];
     __syncthreads();
     const int sl = threadIdx.x >> 4;
-    auto fL = [&](int k, int sp) { return (const double2*)sm + k * MESON_TILE + sl * 12 + sp * 3; };
-    meson_site(a, V, x0 + sl, threadIdx.x & 15, fL, fL);
+    auto fS = [&](int k, int sp) { return (const double2*)sm + k * TILE + sl * 12 + sp * 3; };
+    auto fT = [&](int k, int sp) { return (const double2*)sm + (NB - 1) * FIELDS + k * TILE + sl * 12 + sp * 3; };
+    meson_site(a, V, x0 + sl, threadIdx.x & 15, fS, fT);
 }
 
 // Sequential sources: out_k(x)[s][c] = delta(x_t, t_f) e^{+i p.x} G[s][perm(s)] S_k(x)[perm(s)][c] with the
@@ -284,11 +279,11 @@ hipError_t launch_meson_2pt(hipStream_t s, const Geom& g, const void* S, const v
     a.px = mom_comp(mom[0], g.Lx);
     a.py = mom_comp(mom[1], g.Ly);
     a.pz = mom_comp(mom[2], g.Lz);
-    const long threads = 2L * g.Vh * 16;  // 16 lanes per site: one block per 16 sites
+    const long V = 2L * g.Vh;  // 16 lanes per site
     if (S == T)
-        hipLaunchKernelGGL(k_meson_sites_same, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_meson_sites<16, true>), dim3((unsigned)((V + 15) / 16)), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_meson_sites, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_meson_sites<8, false>), dim3((unsigned)((V + 7) / 8)), dim3(128), 0, s, a);
     hipLaunchKernelGGL(k_slice_sum, dim3(g.Lt), dim3(256), 0, s, (const double2*)site_scratch, (double2*)out, g);
     return hipGetLastError();
 }
