@@ -165,13 +165,15 @@ __global__ __launch_bounds__(256) void k_seq_sources(const double2* S, double2* 
 __global__ __launch_bounds__(256) void k_slice_sum(const double2* site, double2* out, Geom g)
 {
     const int t = blockIdx.x;
-    const long St = g.Vh / g.Lt;
+    const int St = g.Vh / g.Lt;  // sites of one parity on a time slice, contiguous in the eo order
     double v[2] = {0.0, 0.0};
-    for (long i = threadIdx.x; i < 2 * St; i += 256) {
-        const long x = (i / St) * g.Vh + (long)t * St + (i % St);
-        const double2 z = site[x];
-        v[0] += z.x;
-        v[1] += z.y;
+    for (int par = 0; par < 2; par++) {
+        const double2* slice = site + (long)par * g.Vh + (long)t * St;
+        for (int i = threadIdx.x; i < St; i += 256) {
+            const double2 z = slice[i];
+            v[0] += z.x;
+            v[1] += z.y;
+        }
     }
     __shared__ double res[2];
     block_sum_store<2>(v, res);
