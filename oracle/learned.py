@@ -26,6 +26,12 @@ Gradients (L real, W complex; dL/dW := dL/dRe W + i dL/dIm W):
 Parity unpinned with respect to the paper (it does not define the network);
 pinned by: a 4-channel layer whose weights are the Wilson projectors equals the
 oracle's hop term, gauge equivariance, and central finite differences.
+
+Training: Adam (Kingma and Ba 2015) on the real and imaginary parts of the
+weights, pinned by closed forms of its first steps (the first update is
+-lr g / (|g| + eps) per real parameter; a constant gradient gives that update at
+every step; a reversed second gradient gives +lr (1 - b1) / (1 + b1) per unit
+gradient direction) and by its invariance under a rescaling of the gradient.
 """
 from __future__ import annotations
 
@@ -153,3 +159,57 @@ def net_loss_and_grad(T: Transport, W1, W2, pairs):
         gh = layer_adjoint(T, W2, gz)
         G1 += layer_weight_grad(T, phi0, gh)
     return loss, G1, G2
+
+
+# ---------------------------------------------------------------------------
+# Training step: Adam (Kingma and Ba 2015, Algorithm 1), written out from the
+# published algorithm.  The complex weights are treated as pairs of independent
+# real parameters (Re W, Im W) with the gradient G = dL/dRe W + i dL/dIm W, so
+# every formula below acts on the real and the imaginary parts separately.
+# ---------------------------------------------------------------------------
+ADAM_BETA1 = 0.9
+ADAM_BETA2 = 0.999
+ADAM_EPS = 1e-8
+
+
+class AdamState:
+    """First and second moment estimates of one complex weight array, and the step count."""
+
+    def __init__(self, shape):
+        self.m_re = np.zeros(shape)
+        self.m_im = np.zeros(shape)
+        self.v_re = np.zeros(shape)
+        self.v_im = np.zeros(shape)
+        self.t = 0
+
+
+def _adam_real(theta, g, m, v, t, lr, b1, b2, eps):
+    # biased moment estimates, then their bias-corrected forms, then the step
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def adam_step(W, G, state: AdamState, lr, b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS):
+    """One Adam update of the complex weights W with gradient G; returns the new W (state updated)."""
+    state.t += 1
+    re, state.m_re, state.v_re = _adam_real(W.real, G.real, state.m_re, state.v_re, state.t, lr, b1, b2, eps)
+    im, state.m_im, state.v_im = _adam_real(W.imag, G.imag, state.m_im, state.v_im, state.t, lr, b1, b2, eps)
+    return re + 1j * im
+
+
+def train_full_batch(T: Transport, W1, W2, pairs, steps, lr):
+    """`steps` Adam steps, each on the mean gradient of the loss over all `pairs` (the batch is
+    the whole set, so the order of the pairs does not matter); returns W1, W2 and the mean loss
+    of each step (measured before its update)."""
+    s1, s2 = AdamState(W1.shape), AdamState(W2.shape)
+    losses = []
+    for _ in range(steps):
+        loss, G1, G2 = net_loss_and_grad(T, W1, W2, pairs)
+        n = len(pairs)
+        W1 = adam_step(W1, G1 / n, s1, lr)
+        W2 = adam_step(W2, G2 / n, s2, lr)
+        losses.append(loss / n)
+    return W1, W2, losses

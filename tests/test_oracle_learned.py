@@ -92,3 +92,85 @@ def test_identity_weights_give_identity_map():
     W1[0] = np.eye(4)
     r = li.gaussian_source(L, 14).reshape(V, 4, 3)[: V // 2]
     assert np.abs(ln.net_apply(T, W1, W1, r) - r).max() == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Adam (Kingma and Ba 2015): closed forms that follow from the algorithm's definition
+# ---------------------------------------------------------------------------
+def _adam_run(W0, grads, lr, eps=ln.ADAM_EPS):
+    st = ln.AdamState(W0.shape)
+    W = W0.copy()
+    out = []
+    for G in grads:
+        W = ln.adam_step(W, G, st, lr, eps=eps)
+        out.append(W.copy())
+    return out
+
+
+def test_adam_first_step_is_a_signed_step_of_size_lr():
+    """With bias correction m_hat = g and v_hat = g^2 after one step, so each real parameter moves
+    by -lr g / (|g| + eps), independently for the real and imaginary parts."""
+    rng = np.random.default_rng(20)
+    W0 = _rand(rng, 9, 4, 3)
+    G = _rand(rng, 9, 4, 3) * np.exp(rng.uniform(-6, 2, (9, 4, 3)))
+    lr = 3e-3
+    (W1,) = _adam_run(W0, [G], lr)
+    expect = W0 - lr * (G.real / (np.abs(G.real) + ln.ADAM_EPS) + 1j * G.imag / (np.abs(G.imag) + ln.ADAM_EPS))
+    assert np.abs(W1 - expect).max() < 1e-15
+
+
+def test_adam_constant_gradient_moves_linearly():
+    """For a constant gradient both bias-corrected moments equal g and g^2 at every step, so the
+    t-th iterate is W0 - t lr g / (|g| + eps): this fixes the powers of beta1 and beta2."""
+    rng = np.random.default_rng(21)
+    W0 = _rand(rng, 3, 5)
+    G = _rand(rng, 3, 5)
+    lr = 1e-3
+    Ws = _adam_run(W0, [G] * 7, lr)
+    unit = G.real / (np.abs(G.real) + ln.ADAM_EPS) + 1j * G.imag / (np.abs(G.imag) + ln.ADAM_EPS)
+    for t, W in enumerate(Ws, 1):
+        assert np.abs(W - (W0 - t * lr * unit)).max() < 1e-14, t
+
+
+def test_adam_reversed_second_gradient():
+    """Gradients g then -g: m_2 = -(1 - b1)^2 g, so m_hat = -(1 - b1) g / (1 + b1), and
+    v_2 = (1 - b2)(1 + b2) g^2, so v_hat = g^2; the second update is +lr (1 - b1)/(1 + b1) g/|g|
+    (eps = 0)."""
+    rng = np.random.default_rng(22)
+    W0 = _rand(rng, 4, 4)
+    G = _rand(rng, 4, 4)
+    lr = 2e-3
+    W1, W2 = _adam_run(W0, [G, -G], lr, eps=0.0)
+    b1 = ln.ADAM_BETA1
+    f = (1 - b1) / (1 + b1)
+    expect = W1 + lr * f * (np.sign(G.real) + 1j * np.sign(G.imag))
+    assert np.abs(W2 - expect).max() < 1e-15
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    """m_hat / sqrt(v_hat) does not change when every gradient is multiplied by c > 0 (eps = 0)."""
+    rng = np.random.default_rng(23)
+    W0 = _rand(rng, 6, 2)
+    grads = [_rand(rng, 6, 2) for _ in range(5)]
+    a = _adam_run(W0, grads, 1e-3, eps=0.0)
+    b = _adam_run(W0, [1e4 * G for G in grads], 1e-3, eps=0.0)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() < 1e-14
+
+
+def test_full_batch_training_lowers_the_loss():
+    """A few full-batch Adam steps of the two-layer net lower the relative-error loss."""
+    rng = np.random.default_rng(24)
+    L = (4, 2, 2, 4)
+    V = int(np.prod(L))
+    T = ln.Transport(L, li.random_gauge(L, 0.3, 25))
+    W1 = np.zeros((9, 6, 4), dtype=complex)
+    W2 = np.zeros((9, 4, 6), dtype=complex)
+    W1[0, :4, :4] = np.eye(4)
+    W2[0, :4, :4] = np.eye(4)
+    W1 += 0.05 * _rand(rng, *W1.shape)
+    W2 += 0.05 * _rand(rng, *W2.shape)
+    e = [_rand(rng, V // 2, 4, 3) for _ in range(3)]
+    r = [0.5 * x + 0.1 * _rand(rng, V // 2, 4, 3) for x in e]  # e is close to 2 r: learnable
+    _, _, losses = ln.train_full_batch(T, W1, W2, list(zip(r, e)), 30, 1e-2)
+    assert losses[-1] < 0.5 * losses[0], losses
