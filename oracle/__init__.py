@@ -28,6 +28,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# tests of the pins themselves load a deliberately broken build of oracle.c through this variable
+_LIB_OVERRIDE = os.environ.get("QCDW_ORACLE_LIB")
 
 
 def build(force: bool = True) -> str:
@@ -47,10 +49,15 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        _lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            _lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build(force=False)
+            _lib = ctypes.CDLL(_LIB)
         d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
         _lib.orc_hop.argtypes = [p, i, p, p, p, i]
+        _lib.orc_set_threads.argtypes = [i]
+        _lib.orc_set_threads.restype = None
         _lib.orc_hop_w.argtypes = [p, i, p, p, p, i, p]
         _lib.orc_clover_build.argtypes = [p, p, p]
         _lib.orc_clover_build.restype = d
@@ -113,6 +120,11 @@ def gamma_bitmask(n: int) -> np.ndarray:
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of the oracle's loops (timing on fewer cores)."""
+    lib().orc_set_threads(int(n))
 
 
 def site_index(L, c) -> int:

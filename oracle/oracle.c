@@ -78,6 +78,7 @@ static long neighbour(const int L[4], const int c[4], int mu, int step)
 
 long orc_site_index(const int L[4], const int c[4]) { return site_index(L, c); }
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 void orc_site_coords(const int L[4], long i, int c[4]) { site_coords(L, i, c); }
 
 /* ------------------------------------------------------------------ */

@@ -1,0 +1,59 @@
+"""The oracle's pins catch plausible mistakes: each planted mistake below, built into a copy of
+oracle.c, makes at least one pin of tests/test_oracle_pins.py fail (CPU only).
+
+A mistake that no pin catches would mean the oracle could carry it unnoticed; the list covers the
+hop (projector sign, link placement, neighbour offset, time boundary), the Dirac matrices, the
+clover (leaf sum and normalisation) and the clover inverse."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+MUTATIONS = {
+    "forward projector 1 + g instead of 1 - g": (
+        "double pm = dir == 0 ? -1.0 : +1.0;", "double pm = dir == 0 ? +1.0 : -1.0;"),
+    "backward link not conjugated": (
+        "mat3_dagger(link(U, V, mu, j), u);", "memcpy(u, link(U, V, mu, j), sizeof u);"),
+    "forward link taken at the neighbour": (
+        "memcpy(u, link(U, V, mu, i), sizeof u);", "memcpy(u, link(U, V, mu, j), sizeof u);"),
+    "neighbour two sites away": (
+        "d[mu] = (d[mu] + step + L[mu]) % L[mu];", "d[mu] = (d[mu] + 2 * step + 2 * L[mu]) % L[mu];"),
+    "antiperiodic sign missing on the forward t hop": (
+        "if (dir == 0 && c[3] == L[3] - 1) sign = -sign;", ""),
+    "gamma_1 entry with the wrong sign": (
+        "g[0][3] = I; g[1][2] = I; g[2][1] = -I; g[3][0] = -I;", "g[0][3] = I; g[1][2] = I; g[2][1] = I; g[3][0] = -I;"),
+    "field strength normalised by 1/4": (
+        "F[k] = (Q[k] - Qd[k]) / 8.0;", "F[k] = (Q[k] - Qd[k]) / 4.0;"),
+    "third clover leaf dropped": (
+        "mat3_mul(t1, link(U, V, nu, s_mn), leaf);\n    for (int k = 0; k < 9; k++) Q[k] += leaf[k];",
+        "mat3_mul(t1, link(U, V, nu, s_mn), leaf);"),
+    "Gauss-Jordan elimination adds instead of subtracting": (
+        "for (int k = 0; k < 12; k++) a[r][k] -= f * a[col][k];",
+        "for (int k = 0; k < 12; k++) a[r][k] += f * a[col][k];"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+@pytest.mark.parametrize("name", list(MUTATIONS))
+def test_planted_mistake_fails_a_pin(tmp_path, name):
+    old, new = MUTATIONS[name]
+    with open(os.path.join(ROOT, "oracle", "oracle.c")) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    mutant = tmp_path / "oracle_mutant.c"
+    mutant.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mutant.so"
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(mutant), "-lm"],
+                   check=True, capture_output=True, text=True)
+    env = dict(os.environ, QCDW_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(HERE, "test_oracle_pins.py"), "-x", "-q",
+                        "-p", "no:cacheprovider", "-k", "not dense_lu"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"no pin failed for the planted mistake '{name}':\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout
