@@ -82,8 +82,18 @@ def random_gauges(jobs, workers: int | None = None):
         workers = min(len(jobs), os.cpu_count() or 1, 16)
     if workers <= 1 or len(jobs) <= 1:
         return [_gauge_job(j) for j in jobs]
-    with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(_gauge_job, jobs, chunksize=1)
+    # close() + join() let the workers finish and exit on their own (the pool's context manager
+    # would terminate them with a signal)
+    pool = mp.get_context("fork").Pool(workers)
+    try:
+        out = pool.map(_gauge_job, jobs, chunksize=1)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return out
 
 
 def unit_gauge(L) -> np.ndarray:
