@@ -136,10 +136,14 @@ qcdw_status qcdw_ctx_set_stream(qcdw_ctx *ctx, void *hip_stream);
 /* Multi-shift CG on the normal even-odd operator (the solves of a rational approximation in RHMC,
    paper Sec. IV; the shifted solver reuses the hot path): (M_hat^+ M_hat + shifts[i]) x_i = b for
    i < n_shifts (1 .. 64, every shift finite and >= 0) in one Krylov space, FP64.  b_e, x_e[i]:
-   even-site fields in the layout of qcdw_op_matpc (b read; x written, not aliasing b).  Stops when
-   every shifted residual (tracked by the recurrence) is <= tol ||b||; *iters and res[i] (host:
-   the relative residual estimates) are filled.  QCDW_ENOCONV after maxiter, QCDW_EBREAKDOWN if
-   (p, N p) is not positive, QCDW_ENAN for a non-finite residual, QCDW_EINVAL for bad arguments. */
+   even-site fields in the layout of qcdw_op_matpc (b read; x written, not aliasing b).  The
+   shifted recurrence runs until every shifted residual it tracks is <= tol ||b|| / 2; then each
+   FP64 true residual ||b - (M_hat^+ M_hat + shifts[i]) x_i|| is recomputed on the GPU from x_i,
+   and a shift still above tol ||b|| is refined (at most three times) by a single-shift CG on its
+   residual.  *iters (all iterations, refinements included) and res[i] (host: the relative true
+   residuals) are filled.  QCDW_ENOCONV after maxiter or with a true residual above tol (res[i]
+   then holds the recurrence's estimates, resp. the true residuals), QCDW_EBREAKDOWN if (p, N p)
+   is not positive, QCDW_ENAN for a non-finite residual, QCDW_EINVAL for bad arguments. */
 qcdw_status qcdw_invert_multishift(qcdw_op *op, const void *b_e, void *const *x_e, const double *shifts, int n_shifts,
                                    double tol, int maxiter, int *iters, double *res);
 
@@ -187,14 +191,19 @@ qcdw_status qcdw_clover_build(qcdw_ctx *ctx, const qcdw_lattice *lat, const void
 qcdw_status qcdw_clover_apply(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *clover, const void *psi,
                               void *out, double kappa, double csw);
 
-/* clover_inv = A^-1 blockwise (Cholesky), same packed layout as the clover.
-   Returns QCDW_ENOTPD if some block of A is not positive definite. */
+/* Inverse of the site-local clover term A = 1 - kappa csw C of Eq. "clover" (Sec. III.B), which
+   even-odd preconditioning applies on each parity (Sec. II.A, II.D): clover_inv = A^-1 per
+   chirality block (Cholesky; the blocks are Hermitian), in the packed clover layout of Sec. II.A.
+   clover: C as written by qcdw_clover_build (read); clover_inv: caller-owned, same size (written).
+   Returns QCDW_ENOTPD if some block of A is not positive definite (clover_inv is then undefined). */
 qcdw_status qcdw_clover_invert(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *clover, double kappa,
                                double csw, void *clover_inv);
 
-/* Parity block of the hopping term: out = H psi on sites of parity out_parity,
-   zero on the other parity (psi's values on out_parity are not read).
-   psi, out: fermion layout (full lattice). */
+/* Parity block of the Wilson hopping term H of Eq. "clover" (Sec. III.B), written out with the
+   (1 -/+ gamma_mu) projectors as in the file header, in the even-odd split of Sec. II.A:
+   out = H psi on sites of parity out_parity, zero on the other parity (psi's values on
+   out_parity are not read).  U: gauge layout (read); psi, out: fermion layout (full lattice;
+   psi read, out written, no aliasing).  QCDW_EINVAL for out_parity outside {0, 1}. */
 qcdw_status qcdw_hop(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, const void *psi, void *out,
                      int out_parity);
 
@@ -233,10 +242,12 @@ void qcdw_op_destroy(qcdw_op *op);
    another precision. */
 qcdw_status qcdw_op_hop_form(const qcdw_op *op, qcdw_prec prec, int *nt, int *cgroup, int *fma);
 
-/* out_e = M_hat in_e on even sites.  in_e, out_e: [Lt, Lz, Ly, Lx/2, 4, 3]
-   complex FP64 (the even half of the fermion layout).  prec selects the
-   storage precision of the kernels used (F64, or the op's inner precision);
-   the result is returned in FP64. */
+/* The even-odd preconditioned operator of Sec. II.A / II.D (the Schur complement on even sites
+   of Eq. "clover"'s M): out_e = M_hat in_e = in_e - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe in_e.
+   in_e, out_e: [Lt, Lz, Ly, Lx/2, 4, 3] complex FP64 (the even half of the fermion layout; in_e
+   read, out_e written, no aliasing).  prec selects the storage precision of the kernels used
+   (F64, or the op's inner precision); the result is returned in FP64.  QCDW_EINVAL for another
+   precision. */
 qcdw_status qcdw_op_matpc(qcdw_op *op, qcdw_prec prec, const void *in_e, void *out_e);
 
 /* The same for nrhs (1..16) stacked even-site fields, with the multi-RHS hop
@@ -244,10 +255,12 @@ qcdw_status qcdw_op_matpc(qcdw_op *op, qcdw_prec prec, const void *in_e, void *o
    Reconstruct-12 operators only. */
 qcdw_status qcdw_op_matpc_multi(qcdw_op *op, qcdw_prec prec, int nrhs, const void *in_e, void *out_e);
 
-/* Solve M x = b (fermion layout).  x holds the initial guess on entry (zeros
-   for none) and the solution on exit; it is written on QCDW_OK and
-   QCDW_ENOCONV (best iterate).  info is always filled.  The acceptance test is
-   the FP64 true residual of the full system, recomputed from x. */
+/* Solve M x = b (fermion layout) for the Wilson-clover matrix of Eq. "clover" by BiCGStab, the
+   paper's solver for clover fermions (Sec. II.E), on the even-odd system of Sec. II.A / II.D,
+   with the tolerance and iteration cap of the paper's invert calls (Sec. III.B: tol, maxiter).
+   b: read; x holds the initial guess on entry (zeros for none) and the solution on exit; it is
+   written on QCDW_OK and QCDW_ENOCONV (best iterate).  info is always filled.  The acceptance
+   test is the FP64 true residual of the full system, recomputed from x. */
 qcdw_status qcdw_invert(qcdw_op *op, const void *b, void *x, const qcdw_solver_params *params,
                         qcdw_solve_info *info);
 
