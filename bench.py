@@ -1,31 +1,38 @@
 """Benchmark of the even-odd Wilson-clover inversion on one MI355X.
 
-One step = the whole hot path on one synthetic gauge field and source:
+One step = the whole single-RHS hot path on one synthetic gauge field and source:
   operator set-up (pack links to reconstruct-12, clover build, clover inverse
   in FP64 and in the inner precision), an FP64 even-odd BiCGStab solve to an
   FP64 true residual of 1e-10, and a mixed-precision solve (BF16 storage,
   FP32 arithmetic, FP64 reliable updates) of the same system to 1e-10.
 
-Workload: 16^3 x 32 lattice, kappa 0.124, csw 1.0, links exp(i 0.2 H), Z2
-source (seed 1000).  Inputs are generated on the host and copied to HBM
-before the timed region.
+Workload: 24^3 x 64 lattice, kappa 0.125, csw 1.1, links exp(i 0.2 H) (seed 0),
+point source (origin, spin 0, colour 0): the lattice on which the HBM claim is
+quoted (its working set is several times the 256 MB memory-side cache).  Inputs
+are generated on the host and copied to HBM before the timed region.
+
+Printed line (rank 0): metric/value = algorithmic GB/s of the dslash, the FP64
+hop into odd sites with fused A_oo^-1 (the dominant kernel, two launches per
+iteration), i.e. its bytes per launch (1728 B per odd site, inputs read once
+and the output written once) divided by its mean launch duration, timed with
+HIP events that every dispatch records on the library's stream during the
+timed steps; roofline = the same kernel against 8 TB/s; cpu_baseline = the
+FP64 CPU oracle's full operator on the same lattice, plus its 1-core figure and
+its FP64 solve at 16^3 x 32.
 
 Beside the timed steps (not part of them) the line carries the other
-workloads of the same metric: "propagator" (24^3 x 64, 12 point sources solved
-together with the multi-RHS hop in BF16 against 12 separate FP64 solves),
-"batch" (48 uneven problems in one persistent batched solve against a loop of
-single solves, solves/s), "learned" (32^3 x 64 near the critical kappa:
-FGMRES(32) with the trained gauge-covariant preconditioner against plain FP64
-and mixed BiCGStab), "aniso" (the paper's anisotropic example action on
-16^3 x 32 with antiperiodic time) and "multishift" (8 shifted normal-equation
-solves in one Krylov space against separate solves).  ``--bisect-kappa`` finds that kappa.
-
-Printed line (rank 0): metric/value = algorithmic bytes of the Krylov
-iterations (byte model per iteration and precision, counted with the actual
-iteration numbers) divided by the step's wall time; roofline = the dominant
-hop kernel (H_oe with fused A_oo^-1) timed with HIP events on the library's
-stream during the timed steps; cpu_baseline = the FP64 CPU oracle's full
-operator on the same lattice.
+workloads: "wc16x32_cache_resident" (the 16^3 x 32 Z2-source solves with
+graphs, whose working set fits the memory-side cache), "propagator"
+(24^3 x 64, 12 point sources solved together with the multi-RHS hop in BF16
+against 12 separate FP64 and 12 separate BF16-mixed solves), "batch" (48
+uneven problems in one persistent batched solve against a loop of single
+solves, solves/s), "learned" (32^3 x 64 near the critical kappa: FGMRES(32)
+with the trained gauge-covariant preconditioner against plain FP64 and mixed
+BiCGStab), "aniso" (the paper's anisotropic example action on 16^3 x 32 with
+antiperiodic time) and "multishift" (8 shifted normal-equation solves in one
+Krylov space against separate solves).  ``--bisect-kappa`` finds the learned
+section's kappa.  "solve_vs_oracle" states each solve's error against the
+oracle.
 """
 from __future__ import annotations
 
@@ -80,7 +87,7 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="launch the iteration kernels eagerly instead of "
                     "replaying captured hipGraphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extra-lattice", default="24,24,24,64",
+    ap.add_argument("--extra-lattice", default="",
                     help="also time the hop kernel on this lattice (empty to skip)")
     ap.add_argument("--sections", default="propagator,batch,learned,aniso,multishift",
                     help="comma-separated extra workloads to run after the timed steps (empty: none)")
@@ -158,24 +165,23 @@ def main():
         if sec not in SECTIONS:
             raise SystemExit(f"unknown section {sec}; choose from {', '.join(SECTIONS)}")
 
-    # every host input is drawn before the GPU is initialised (the field generator forks workers)
-    w = li.WORKLOADS["wc16x32"]
+    # every host input is drawn before the GPU is initialised (the field generator forks workers);
+    # a field that several sections use is drawn once
+    w = li.WORKLOADS["wc24x64"]
     L, kappa, csw = w["L"], w["kappa"], w["csw"]
     Vh = int(np.prod(L)) // 2
-    jobs = {"main": [(L, w["eps"], w["seed"])]}
+    w16 = li.WORKLOADS["wc16x32"]
+    jobs = {"main": [(tuple(L), w["eps"], w["seed"])], "cache16": [(tuple(w16["L"]), w16["eps"], w16["seed"])]}
     for sec in sections:
-        jobs[sec] = SECTIONS[sec][0](li)
-    flat = [j for js in jobs.values() for j in js]
+        jobs[sec] = [(tuple(j[0]), j[1], j[2]) for j in SECTIONS[sec][0](li)]
+    uniq = list(dict.fromkeys(j for js in jobs.values() for j in js))
     t_gen = time.perf_counter()
-    fields = li.random_gauges(flat)
+    by_job = dict(zip(uniq, li.random_gauges(uniq)))
     t_gen = time.perf_counter() - t_gen
-    host_fields, k = {}, 0
-    for name, js in jobs.items():
-        host_fields[name] = fields[k:k + len(js)]
-        k += len(js)
-    del fields
-    U = host_fields.pop("main")[0]
-    b = li.z2_source(L, w["source_seed"])
+    host_fields = {name: [by_job[j] for j in js] for name, js in jobs.items()}
+    del by_job
+    U = host_fields["main"][0]
+    b = li.point_source(L, 0, 0)
 
     ctx = q.Context(0)
     lat = q.make_lattice(L)
@@ -185,9 +191,11 @@ def main():
     xlo = torch.zeros_like(bd)
     torch.cuda.synchronize()
 
-    p64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", use_graph=not args.eager)
-    plo = q.make_params(tol=1e-10, maxiter=20000, inner=args.inner, delta=0.1 if args.inner != "f16" else 0.2,
-                        use_graph=not args.eager)
+    # every hop dispatch of the solves records HIP events on the library's stream (the solves then
+    # launch eagerly; at this size a launch is ~0.2 ms of work, so the graphs' saving is negligible)
+    delta = 0.1 if args.inner != "f16" else 0.2
+    p64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True)
+    plo = q.make_params(tol=1e-10, maxiter=20000, inner=args.inner, delta=delta, collect_timing=True)
 
     def step():
         op = q.Operator(ctx, lat, Ud, kappa, csw, args.inner, 12)
@@ -195,8 +203,9 @@ def main():
         xlo.zero_()
         i64 = q.qcdw_invert(op, bd, x64, p64, raise_on_error=True)
         ilo = q.qcdw_invert(op, bd, xlo, plo, raise_on_error=True)
+        form = q.qcdw_op_hop_form(op, "f64")
         op.close()
-        return i64, ilo
+        return i64, ilo, form
 
     for _ in range(args.warmup):
         step()
@@ -207,41 +216,25 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
 
-    total_bytes = sum(i64.iters * iter_bytes("f64") * Vh + ilo.iters * iter_bytes(args.inner) * Vh
-                      for i64, ilo in infos)
-    value = total_bytes / elapsed / 1e9
-
-    # roofline of the dominant kernel, the FP64 hop into odd sites with fused A_oo^-1 (two launches
-    # per iteration): the same solves again, launched eagerly, every hop dispatch timed by HIP events
-    # that the dispatch itself records on the library's stream
-    t64 = q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True)
-    tlo = q.make_params(tol=1e-10, maxiter=20000, inner=args.inner, delta=plo.delta, collect_timing=True)
-    op = q.Operator(ctx, lat, Ud, kappa, csw, args.inner, 12)
-    form = q.qcdw_op_hop_form(op, "f64")
-    timed = []
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        x64.zero_()
-        xlo.zero_()
-        timed.append((q.qcdw_invert(op, bd, x64, t64, raise_on_error=True),
-                      q.qcdw_invert(op, bd, xlo, tlo, raise_on_error=True)))
-    torch.cuda.synchronize()
-    eager_ms = 1e3 * (time.perf_counter() - t1) / args.steps
-    op.close()
-    ms_a = sum(i64.hop_ms[0] for i64, _ in timed)
-    n_a = sum(i64.n_hop[0] for i64, _ in timed)
+    forms = {f for _, _, f in infos}
+    form = infos[-1][2]
+    ms_a = sum(i64.hop_ms[0] for i64, _, _ in infos)
+    n_a = sum(i64.n_hop[0] for i64, _, _ in infos)
     avg_a_ms = ms_a / max(n_a, 1)
     achieved = hop_a_bytes("f64") * Vh / (avg_a_ms * 1e-3) / 1e9
-    ms_b = sum(i64.hop_ms[1] + i64.hop_ms[2] for i64, _ in timed)
-    n_b = sum(i64.n_hop[1] + i64.n_hop[2] for i64, _ in timed)
-    ms_alo = sum(ilo.hop_ms[0] for _, ilo in timed)
-    n_alo = sum(ilo.n_hop[0] for _, ilo in timed)
+    ms_b = sum(i64.hop_ms[1] + i64.hop_ms[2] for i64, _, _ in infos)
+    n_b = sum(i64.n_hop[1] + i64.n_hop[2] for i64, _, _ in infos)
+    ms_alo = sum(ilo.hop_ms[0] for _, ilo, _ in infos)
+    n_alo = sum(ilo.n_hop[0] for _, ilo, _ in infos)
     lo_gbs = hop_a_bytes(args.inner) * Vh / (ms_alo / max(n_alo, 1) * 1e-3) / 1e9
+    krylov_bytes = sum(i64.iters * iter_bytes("f64") * Vh + ilo.iters * iter_bytes(args.inner) * Vh
+                       for i64, ilo, _ in infos)
+    i64, ilo, _ = infos[-1]
+    host_x = {"wc24x64": {"f64": x64.cpu().numpy(), args.inner: xlo.cpu().numpy()}}
 
-    i64, ilo = infos[-1]
     result = {
         "metric": "dslash GB/s (% HBM peak); time to 1e-10 residual, plain FP64 vs mixed/ML",
-        "value": round(value, 1),
+        "value": round(achieved, 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -252,29 +245,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "wilson-clover even-odd BiCGStab 16^3x32, kappa 0.124, csw 1.0, eps 0.2, Z2 source",
+        "config": {"workload": "wilson-clover dslash (FP64 hop into odd sites with A_oo^-1) inside even-odd "
+                               "BiCGStab, 24^3x64, kappa 0.125, csw 1.1, eps 0.2, point source",
                    "lattice": list(L), "kappa": kappa, "csw": csw, "tol": 1e-10, "inner": args.inner},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form, L),
                      "kernel": hop_kernel_name(form), "form": {"nt": form[0], "cgroup": form[1], "fma": form[2]},
+                     "forms_in_timed_steps": len(forms),
                      "launches_timed": n_a, "bytes_per_launch": hop_a_bytes("f64") * Vh,
                      "avg_launch_us": round(avg_a_ms * 1e3, 2)},
         "solve": {
             "f64": {"iters": i64.iters, "true_res": i64.true_res, "time_ms": round(i64.time_ms, 3),
                     "reliable": i64.n_reliable},
             args.inner: {"iters": ilo.iters, "true_res": ilo.true_res, "time_ms": round(ilo.time_ms, 3),
-                         "reliable": ilo.n_reliable},
+                         "reliable": ilo.n_reliable, "fallback": ilo.fallback},
             "speedup_mixed": round(i64.time_ms / ilo.time_ms, 3),
-            "graph": not args.eager,
-            "eager_instrumented_ms_per_step": round(eager_ms, 3),
+            "krylov_gbs_step": round(krylov_bytes / elapsed / 1e9, 1),
+            "note": "solves launched eagerly with per-dispatch HIP events; step includes operator set-up",
         },
         "hop_gbs": {"f64_into_odd": round(achieved, 1),
                     "f64_into_even_xpay": round((hop_b_bytes("f64") + SPINOR["f64"] / 2) * Vh /
                                                 (ms_b / max(n_b, 1) * 1e-3) / 1e9, 1),
                     f"{args.inner}_into_odd": round(lo_gbs, 1)},
     }
+    del Ud, bd, x64, xlo
+    torch.cuda.empty_cache()
 
     result["stream_gbs"] = stream_probe(torch)
+    cres, host_x["wc16x32"] = cache_resident(q, li, np, torch, ctx, host_fields["cache16"][0], args)
+    result["wc16x32_cache_resident"] = cres
     if args.extra_lattice:
         result["hop_gbs_large"] = time_large_hop(q, li, np, torch, ctx, [int(v) for v in args.extra_lattice.split(",")])
 
@@ -282,13 +281,56 @@ def main():
         result[sec] = SECTIONS[sec][1](q, li, np, torch, ctx, host_fields.pop(sec), args)
         host_fields[sec] = None
     result["input_generation_s"] = round(t_gen, 1)
+    torch.cuda.synchronize()
+    ctx.close()
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(li, np, L, U, b, kappa, csw, args.cpu_seconds)
+        result["cpu_baseline"], result["solve_vs_oracle"] = cpu_baseline(
+            li, np, (L, U, b, kappa, csw), (w16, host_fields["cache16"][0]), host_x, args.cpu_seconds)
 
     print(json.dumps(result))
     sys.stdout.flush()
-    ctx.close()
+
+
+def cache_resident(q, li, np, torch, ctx, U, args):
+    """The 16^3x32 Z2-source system (kappa 0.124, csw 1.0): FP64 and mixed solves launched through the
+    captured hipGraphs, and the FP64 hop rate from an instrumented solve.  The hop's working set
+    (~113 MB) fits the 256 MB memory-side cache, so these are not HBM figures."""
+    w = li.WORKLOADS["wc16x32"]
+    L, kappa, csw = w["L"], w["kappa"], w["csw"]
+    Vh = int(np.prod(L)) // 2
+    lat = q.make_lattice(L)
+    bd = torch.from_numpy(li.z2_source(L, w["source_seed"])).cuda()
+    op = q.Operator(ctx, lat, torch.from_numpy(U).cuda(), kappa, csw, args.inner, 12)
+    delta = 0.1 if args.inner != "f16" else 0.2
+    out = {"workload": "16^3x32, kappa 0.124, csw 1.0, eps 0.2, Z2 source (cache-resident: not an HBM figure)"}
+    xs = {}
+    for prec in ("f64", args.inner):
+        prm = q.make_params(tol=1e-10, maxiter=20000, inner=prec, delta=delta, use_graph=not args.eager)
+        x = torch.zeros_like(bd)
+        q.qcdw_invert(op, bd, x, prm)  # warm-up: graph capture
+        ts = []
+        for _ in range(3):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = q.qcdw_invert(op, bd, x, prm, raise_on_error=True)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[1]
+        out[prec] = {"iters": info.iters, "true_res": info.true_res, "time_ms": round(1e3 * t, 3),
+                     "krylov_gbs": round(info.iters * iter_bytes(prec) * Vh / t / 1e9, 1)}
+        xs[prec] = x.cpu().numpy()
+    out["speedup_mixed"] = round(out["f64"]["time_ms"] / out[args.inner]["time_ms"], 3)
+    x = torch.zeros_like(bd)
+    info = q.qcdw_invert(op, bd, x, q.make_params(tol=1e-10, maxiter=20000, inner="f64", collect_timing=True))
+    us = 1e3 * info.hop_ms[0] / max(info.n_hop[0], 1)
+    out["hop_f64"] = {"gbs": round(hop_a_bytes("f64") * Vh / us / 1e3, 1), "avg_launch_us": round(us, 2),
+                      "form": q.qcdw_op_hop_form(op, "f64")}
+    op.close()
+    del bd, x
+    torch.cuda.empty_cache()
+    return out, xs
 
 
 def hop_kernel_name(form):
@@ -303,7 +345,8 @@ def hop_kernel_name(form):
 
 KERNEL_SOURCES = ("paper_2411_08461_amd/csrc/hop.hip", "paper_2411_08461_amd/csrc/hop_common.h",
                   "paper_2411_08461_amd/csrc/dev.h", "paper_2411_08461_amd/csrc/internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_wc16x32_traffic.md")
+TRAFFIC_FILES = {(16, 16, 16, 32): os.path.join(ROOT, "profiles", "hop_wc16x32_traffic.md"),
+                 (24, 24, 24, 64): os.path.join(ROOT, "profiles", "hop_wc24x64_traffic.md")}
 
 
 def kernel_sources_sha256():
@@ -316,12 +359,15 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(form):
+def measured_traffic(form, L):
     """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
-    profile of this workload: the record taken from the current kernel sources with the same hop
+    profile of this lattice: the record taken from the current kernel sources with the same hop
     form, if there is one; otherwise None."""
+    path = TRAFFIC_FILES.get(tuple(L))
+    if path is None:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             recs = [json.loads(ln[len("traffic-json: "):]) for ln in f if ln.startswith("traffic-json: ")]
     except (OSError, ValueError):
         return None
@@ -423,6 +469,17 @@ def propagator(q, li, np, torch, ctx, fields, args):
     torch.cuda.synchronize()
     t_sep = time.perf_counter() - t0
     diff = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+    # 12 separate BF16-mixed solves: what the lockstep multi-RHS solve saves over the same precision
+    plo = q.make_params(tol=1e-10, maxiter=20000, inner="bf16", delta=0.1)
+    xlo = torch.zeros_like(bs)
+    q.qcdw_invert(op, bs[0], xlo[0], plo)  # warm-up
+    xlo.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sep_lo = [q.qcdw_invert(op, bs[k], xlo[k], plo) for k in range(12)]
+    torch.cuda.synchronize()
+    t_sep_lo = time.perf_counter() - t0
+    del xlo
     # the contraction after the solves: pion two-point function of the propagator (reads the 12 fields once)
     lat = q.make_lattice(L)
     corr = torch.empty(L[3], dtype=torch.complex128, device="cuda")
@@ -459,7 +516,9 @@ def propagator(q, li, np, torch, ctx, fields, args):
     return {"workload": "24^3x64, kappa 0.125, csw 1.1, eps 0.2, 12 point sources",
             "multi_bf16": dict(_solve_summary(multi), time_ms=round(1e3 * t_multi, 1)),
             "separate_f64": dict(_solve_summary(sep), time_ms=round(1e3 * t_sep, 1)),
-            "speedup": round(t_sep / t_multi, 3), "rel_diff_multi_vs_f64": diff,
+            "separate_bf16": dict(_solve_summary(sep_lo), time_ms=round(1e3 * t_sep_lo, 1)),
+            "speedup": round(t_sep / t_multi, 3), "speedup_vs_separate_bf16": round(t_sep_lo / t_multi, 3),
+            "rel_diff_multi_vs_f64": diff,
             "multi_hop": {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                           "avg_launch_us": round(ms * 1e3, 1), "bytes_per_site_12rhs": hop_a_bytes_multi("bf16", 12)},
             "pion_2pt": {"call_ms": round(1e3 * t_con, 3),
@@ -720,13 +779,31 @@ def bisect_kappa(q, li, np, torch):
             "trail": trail}
 
 
-def cpu_baseline(li, np, L, U, b, kappa, csw, seconds):
-    """The FP64 oracle's full operator M on the same lattice, on the host cores."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(li, np, main, small, host_x, seconds):
+    """The FP64 oracle on the host cores: (1) its full operator M on the benchmark's 24^3x64 lattice, all
+    threads (the line's value, in the GPU hop's byte model), and on one core; (2) its FP64 BiCGStab solve
+    of the 16^3x32 Z2-source system to 1e-10 (full lattice, no even-odd).  Also returns each GPU solve's
+    error against the oracle: the oracle's true residual of the 24^3x64 solutions, and the distance of
+    the 16^3x32 solutions from the oracle's own solution."""
     import oracle
 
+    L, U, b, kappa, csw = main
     threads = oracle.num_threads()
-    C = oracle.clover_build(L, U)
     V = int(np.prod(L))
+    t0 = time.perf_counter()
+    C = oracle.clover_build(L, U)
+    t_clover = time.perf_counter() - t0
     oracle.dirac(L, U, C, b, kappa, csw)  # warm-up
     n = 0
     t0 = time.perf_counter()
@@ -736,11 +813,43 @@ def cpu_baseline(li, np, L, U, b, kappa, csw, seconds):
         if time.perf_counter() - t0 > seconds or n >= 500:
             break
     dt = (time.perf_counter() - t0) / n
-    # same byte model as the GPU hop with clover and xpay, FP64 reconstruct-12, per site
-    gbs = (hop_b_bytes("f64") - SPINOR["f64"]) * V / dt / 1e9
-    return {"value": round(gbs, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full-lattice applications of M (16^3x32, FP64) in {n * dt:.1f} s, "
-                      f"{dt * 1e3:.1f} ms each; bytes counted with the GPU hop byte model"}
+    # same byte model as the GPU hop with clover, FP64 reconstruct-12, per site of the full lattice
+    gbs = hop_a_bytes("f64") * V / dt / 1e9
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.dirac(L, U, C, b, kappa, csw)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    vs = {"wc24x64": {}}
+    bn = np.linalg.norm(b)
+    for prec, x in host_x["wc24x64"].items():
+        vs["wc24x64"][prec] = {"oracle_true_res": float(np.linalg.norm(b - oracle.dirac(L, U, C, x, kappa, csw)) / bn)}
+    del C
+    w16, U16 = small
+    L16 = w16["L"]
+    b16 = li.z2_source(L16, w16["source_seed"])
+    C16 = oracle.clover_build(L16, U16)
+    t0 = time.perf_counter()
+    sol = oracle.bicgstab(L16, U16, C16, b16, w16["kappa"], w16["csw"], tol=1e-10, maxiter=20000)
+    t_solve = time.perf_counter() - t0
+    xo = sol.x
+    vs["wc16x32"] = {"oracle": {"status": sol.status, "iters": sol.iters}}
+    for prec, x in host_x["wc16x32"].items():
+        vs["wc16x32"][prec] = {
+            "rel_err_vs_oracle_x": float(np.linalg.norm(x - xo) / np.linalg.norm(xo)),
+            "oracle_true_res": float(np.linalg.norm(b16 - oracle.dirac(L16, U16, C16, x, w16["kappa"], w16["csw"]))
+                                     / np.linalg.norm(b16))}
+    base = {"value": round(gbs, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{n} full-lattice applications of M (24^3x64, FP64, {threads} threads) in {n * dt:.1f} s, "
+                      f"{dt * 1e3:.1f} ms each; bytes counted with the GPU hop byte model (1728 B per site)",
+            "one_core": {"apply_ms": round(1e3 * dt1, 1), "gbs": round(hop_a_bytes("f64") * V / dt1 / 1e9, 2)},
+            "clover_build_s": round(t_clover, 2),
+            "solve_16x32_f64": {"time_s": round(t_solve, 2), "iters": sol.iters, "status": sol.status,
+                                "note": "textbook BiCGStab on the full lattice (no even-odd), Z2 source, tol 1e-10"}}
+    return base, vs
 
 
 if __name__ == "__main__":

@@ -32,3 +32,15 @@ def shift_table(L, mu, step):
     c = coords(L).copy()
     c[:, mu] = (c[:, mu] + step) % L[mu]
     return eo_index(L, c[:, 0], c[:, 1], c[:, 2], c[:, 3])
+
+
+def transform_gauge(L, U, Om):
+    """U'_mu(x) = Om(x) U_mu(x) Om(x+mu)^+ (Om: [V, 3, 3] in eo order)."""
+    V = int(np.prod(L))
+    Uf = U.reshape(4, V, 3, 3)
+    Of = Om.reshape(V, 3, 3)
+    out = np.empty_like(Uf)
+    for mu in range(4):
+        fw = shift_table(L, mu, +1)
+        out[mu] = Of @ Uf[mu] @ np.conj(np.swapaxes(Of[fw], -1, -2))
+    return out.reshape(U.shape)

@@ -115,18 +115,6 @@ def test_free_field_plane_wave(L, t_bc):
 # ---------------------------------------------------------------------------
 
 
-def _transform_gauge(L, U, Om):
-    """U'_mu(x) = Om(x) U_mu(x) Om(x+mu)^+."""
-    V = int(np.prod(L))
-    Uf = U.reshape(4, V, 3, 3)
-    Of = Om.reshape(V, 3, 3)
-    out = np.empty_like(Uf)
-    for mu in range(4):
-        fw = geo.shift_table(L, mu, +1)
-        out[mu] = Of @ Uf[mu] @ np.conj(np.swapaxes(Of[fw], -1, -2))
-    return out.reshape(U.shape)
-
-
 @pytest.mark.parametrize("L,t_bc", [((4, 4, 4, 4), 1), ((4, 2, 6, 4), -1)])
 def test_gauge_covariance(L, t_bc):
     """M[U'] (Om psi) = Om (M[U] psi) for U'_mu(x) = Om(x) U_mu(x) Om(x+mu)^+."""
@@ -134,7 +122,7 @@ def test_gauge_covariance(L, t_bc):
     U = li.random_gauge(L, 0.5, seed=11)
     Om = li.gauge_transform(L, seed=12).reshape(V, 3, 3)
     psi = li.gaussian_source(L, seed=13)
-    Up = _transform_gauge(L, U, Om)
+    Up = geo.transform_gauge(L, U, Om)
     kappa, csw = 0.121, 1.7
     C = oracle.clover_build(L, U)
     Cp = oracle.clover_build(L, Up)
