@@ -114,8 +114,8 @@ __global__ __launch_bounds__(256) void k_clov_apply(const void* clov, const void
     cx<T> vo[3], vx[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        vo[c] = P::ld(in, ((long)q * Vh + site) * 3 + c);
-        vx[c] = P::ld(in, ((long)partner * Vh + site) * 3 + c);
+        vo[c] = P::ld(in, sp_idx(q, site, c, Vh));
+        vx[c] = P::ld(in, sp_idx(partner, site, c, Vh));
     }
     // same row formula as the hop epilogue
     T d[3], lo[6], Xr[9], Xi[9];
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_clov_apply(const void* clov, const void
             cx<T> cb = h ? cx<T>{Xr[3 * a + b], Xi[3 * a + b]} : cx<T>{Xr[3 * b + a], -Xi[3 * b + a]};
             s = s + cb * vx[b];
         }
-        P::st(out, ((long)q * Vh + site) * 3 + a, s);
+        P::st(out, sp_idx(q, site, a, Vh), s);
     }
 }
 

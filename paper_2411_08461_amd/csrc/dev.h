@@ -173,6 +173,34 @@ constexpr int CLOV_STRIDE = 1;  // distance between consecutive entries of one m
 __host__ __device__ inline long clov_index(int site, int chi, int m) { return ((long)site * 2 + chi) * 36 + m; }
 __host__ __device__ inline long clov_reals(long Vh) { return 72L * Vh; }
 
+// Complex index of (spin s, site, colour c) in an internal spinor of one parity of Vh sites.  Fields
+// of several planes (stacks of parities, learned-net channels) use the same order with s the plane
+// index.  Spin-major with colour innermost ([4][Vh][3]: a lane's spin of one site is 3 contiguous
+// complex), or with QCDW_SPINOR_SOA=1 one plane per (spin, colour) ([4][3][Vh]: the sites of a wave
+// read one contiguous run per load instruction).
+#ifndef QCDW_SPINOR_SOA
+#define QCDW_SPINOR_SOA 0
+#endif
+__host__ __device__ inline long sp_idx(long s, long site, int c, long Vh)
+{
+    return QCDW_SPINOR_SOA ? (s * 3 + c) * Vh + site : (s * Vh + site) * 3 + c;
+}
+// inverse of sp_idx: (s, site, c) of complex element e
+__host__ __device__ inline void sp_coords(long e, long Vh, long& s, long& site, int& c)
+{
+    if (QCDW_SPINOR_SOA) {
+        site = e % Vh;
+        const long r = e / Vh;
+        c = (int)(r % 3);
+        s = r / 3;
+    } else {
+        c = (int)(e % 3);
+        const long r = e / 3;
+        site = r % Vh;
+        s = r / Vh;
+    }
+}
+
 // Internal gauge field of R complex entries per link (R = 6: the first two rows, R = 9: all), by
 // direction mu and parity p.  Entry j of link (mu, p, site) sits at link_base(mu, p, site) +
 // j * link_stride: link-major ([mu][p][Vh][R]), or site-fastest ([mu][p][R][Vh]) with

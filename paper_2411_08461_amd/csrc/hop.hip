@@ -70,7 +70,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
     cx<T> yv[3];
     if constexpr (EPI == EPI_CLOV_XPAY || EPI == EPI_XPAY_CLOVY || RED == RED_TS) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) yv[c] = valid ? P::ld(a.y, ((long)q * Vh + site) * 3 + c) : cx<T>{T(0), T(0)};
+        for (int c = 0; c < 3; c++) yv[c] = valid ? P::ld(a.y, sp_idx(q, site, c, Vh)) : cx<T>{T(0), T(0)};
     }
     if constexpr (EPI == EPI_NONE) {
 #pragma unroll
@@ -112,7 +112,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
     for (int c = 0; c < 3; c++) outv[c] = P::rt(outv[c]);
     if (valid) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) P::st(a.out, ((long)q * Vh + site) * 3 + c, outv[c]);
+        for (int c = 0; c < 3; c++) P::st(a.out, sp_idx(q, site, c, Vh), outv[c]);
     }
 
     if constexpr (RED != RED_NONE) {
@@ -121,7 +121,7 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
             for (int c = 0; c < 3; c++) {
                 const cx<T> o = outv[c];
                 if constexpr (RED == RED_WDOT) {
-                    const cx<T> wv = P::ld(a.w, ((long)q * Vh + site) * 3 + c);
+                    const cx<T> wv = P::ld(a.w, sp_idx(q, site, c, Vh));
                     v[0] += (double)wv.re * o.re + (double)wv.im * o.im;
                     v[1] += (double)wv.re * o.im - (double)wv.im * o.re;
                 } else {

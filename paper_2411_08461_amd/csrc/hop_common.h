@@ -186,8 +186,8 @@ __device__ __forceinline__ void load_pair(const void* psi, long Vh, int su, int 
 {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        pu[c] = P::ld(psi, ((long)su * Vh + nb) * 3 + c);
-        pl[c] = P::ld(psi, ((long)sl * Vh + nb) * 3 + c);
+        pu[c] = P::ld(psi, sp_idx(su, nb, c, Vh));
+        pl[c] = P::ld(psi, sp_idx(sl, nb, c, Vh));
     }
 }
 

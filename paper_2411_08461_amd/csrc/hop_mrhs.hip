@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
         if constexpr (EPI == EPI_CLOV_XPAY || RED == RED_TS) {
 #pragma unroll
             for (int c = 0; c < 3; c++)
-                yv[c] = valid ? P::ld(a.y, off + ((long)q * Vh + site) * 3 + c) : cx<T>{T(0), T(0)};
+                yv[c] = valid ? P::ld(a.y, off + sp_idx(q, site, c, Vh)) : cx<T>{T(0), T(0)};
         }
         if constexpr (EPI == EPI_NONE) {
 #pragma unroll
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
         for (int c = 0; c < 3; c++) outv[c] = P::rt(outv[c]);
         if (valid) {
 #pragma unroll
-            for (int c = 0; c < 3; c++) P::st(a.out, off + ((long)q * Vh + site) * 3 + c, outv[c]);
+            for (int c = 0; c < 3; c++) P::st(a.out, off + sp_idx(q, site, c, Vh), outv[c]);
         }
         if constexpr (RED != RED_NONE) {
             double v[3] = {0.0, 0.0, 0.0};
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
                 for (int c = 0; c < 3; c++) {
                     const cx<T> o = outv[c];
                     if constexpr (RED == RED_WDOT) {
-                        const cx<T> wv = P::ld(a.w, off + ((long)q * Vh + site) * 3 + c);
+                        const cx<T> wv = P::ld(a.w, off + sp_idx(q, site, c, Vh));
                         v[0] += (double)wv.re * o.re + (double)wv.im * o.im;
                         v[1] += (double)wv.re * o.im - (double)wv.im * o.re;
                     } else {

@@ -68,7 +68,7 @@ __device__ __forceinline__ void transport(const void* in, const void* gauge, con
         for (int c = 0; c < CIN; c++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const auto v = PI::ld(in, (((long)p * CIN + c) * Vh + i) * 3 + k);
+                const auto v = PI::ld(in, sp_idx((long)p * CIN + c, i, k, Vh));
                 Y[c][k] = {(float)v.re, (float)v.im};
             }
         return;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void transport(const void* in, const void* gauge, con
         cx<float> v[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const auto w = PI::ld(in, (((long)(1 - p) * CIN + c) * Vh + j) * 3 + k);
+            const auto w = PI::ld(in, sp_idx((long)(1 - p) * CIN + c, j, k, Vh));
             v[k] = {(float)w.re, (float)w.im};
         }
 #pragma unroll
@@ -157,14 +157,14 @@ __global__ __launch_bounds__(256) void k_net_layer_mfma(NetArgs n)
                 if (a == 0) {
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        const auto v = PI::ld(n.in, (((long)p * CIN + c) * Vh + i) * 3 + k);
+                        const auto v = PI::ld(n.in, sp_idx((long)p * CIN + c, i, k, Vh));
                         Y[k] = {(float)v.re, (float)v.im};
                     }
                 } else {
                     cx<float> v[3];
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        const auto w = PI::ld(n.in, (((long)(1 - p) * CIN + c) * Vh + nb) * 3 + k);
+                        const auto w = PI::ld(n.in, sp_idx((long)(1 - p) * CIN + c, nb, k, Vh));
                         v[k] = {(float)w.re, (float)w.im};
                     }
 #pragma unroll
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_net_layer_mfma(NetArgs n)
                 const long srow = wave * 16 + 4 * grp + e;
                 if ((col & 1) == 0 && d < COUT && srow < 2 * Vh) {
                     const int pp = (int)(srow / Vh), ii = (int)(srow % Vh);
-                    PO::st(n.out, (((long)pp * COUT + d) * Vh + ii) * 3 + k, cx<TO>{(TO)v, (TO)vp});
+                    PO::st(n.out, sp_idx((long)pp * COUT + d, ii, k, Vh), cx<TO>{(TO)v, (TO)vp});
                 }
             }
 }
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_net_layer(NetArgs n)
     for (int d = 0; d < COUT; d++)
 #pragma unroll
         for (int k = 0; k < 3; k++)
-            PO::st(n.out, (((long)p * COUT + d) * g.Vh + i) * 3 + k, cx<TO>{(TO)acc[d][k].re, (TO)acc[d][k].im});
+            PO::st(n.out, sp_idx((long)p * COUT + d, i, k, g.Vh), cx<TO>{(TO)acc[d][k].re, (TO)acc[d][k].im});
 }
 
 // per-block partials of G_a[c', c] = sum_x sum_k g_{c'}(x)_k conj((T_a phi_c)(x)_k), one hop a per launch;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const void* phi, const void* 
         cx<float> gd[3];
 #pragma unroll
         for (int k = 0; k < 3; k++)
-            gd[k] = valid ? P32::ld(gz, (((long)p * COUT + d) * g.Vh + i) * 3 + k) : cx<float>{0.f, 0.f};
+            gd[k] = valid ? P32::ld(gz, sp_idx((long)p * COUT + d, i, k, g.Vh)) : cx<float>{0.f, 0.f};
         double v[2 * CIN];
 #pragma unroll
         for (int c = 0; c < CIN; c++) {

@@ -5,16 +5,15 @@
 
 namespace qcdw {
 
-// spinor: paper [2][Vh][4][3] complex f64  <->  internal [4][Vh][3] complex P
+// spinor: paper [2][Vh][4][3] complex f64  <->  internal spinor (sp_idx order) complex P
 template <class P>
 __global__ void k_pack_spinor(const double2* __restrict__ paper, void* out, int Vh, int parity, double scale)
 {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;  // internal element
     if (e >= 12L * Vh) return;
-    const int c = (int)(e % 3);
-    const long r = e / 3;
-    const int site = (int)(r % Vh);
-    const int s = (int)(r / Vh);
+    long s, site;
+    int c;
+    sp_coords(e, Vh, s, site, c);
     const double2 v = paper[((long)parity * Vh + site) * 12 + s * 3 + c];
     using T = typename P::real;
     P::st(out, e, cx<T>{(T)(scale * v.x), (T)(scale * v.y)});
@@ -25,10 +24,9 @@ __global__ void k_unpack_spinor(const void* in, double2* __restrict__ paper, int
 {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 12L * Vh) return;
-    const int c = (int)(e % 3);
-    const long r = e / 3;
-    const int site = (int)(r % Vh);
-    const int s = (int)(r / Vh);
+    long s, site;
+    int c;
+    sp_coords(e, Vh, s, site, c);
     const auto v = P::ld(in, e);
     paper[((long)parity * Vh + site) * 12 + s * 3 + c] = make_double2(scale * (double)v.re, scale * (double)v.im);
 }
