@@ -57,3 +57,40 @@ def test_planted_mistake_fails_a_pin(tmp_path, name):
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"no pin failed for the planted mistake '{name}':\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout
+
+
+FGMRES_MUTATIONS = {
+    "Arnoldi coefficient without the conjugate": ("H[i, j] = np.vdot(V[i], w)", "H[i, j] = np.dot(V[i], w)"),
+    "last Gram-Schmidt projection dropped": ("for i in range(j + 1):", "for i in range(j):"),
+    "update built from the Arnoldi vectors instead of the preconditioned ones": (
+        "x = x + np.stack(Z[:k], axis=1) @ y", "x = x + np.stack(V[:k], axis=1) @ y"),
+    "restart keeps the old residual": ("        r = bf - op(x)\n        beta = float(np.linalg.norm(r))\n    return",
+                                       "    return"),
+    "least-squares right-hand side not scaled by beta": ("e1[0] = beta", "e1[0] = 1.0"),
+}
+
+
+@pytest.mark.parametrize("name", list(FGMRES_MUTATIONS))
+def test_planted_fgmres_mistake_fails_a_pin(monkeypatch, name):
+    """Each planted mistake in a copy of oracle/fgmres.py makes at least one FGMRES pin fail."""
+    from tests import test_oracle_fgmres as pins
+
+    old, new = FGMRES_MUTATIONS[name]
+    with open(os.path.join(ROOT, "oracle", "fgmres.py")) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    ns = {"__name__": "fgmres_mutant"}
+    exec(compile(src.replace(old, new), "fgmres_mutant.py", "exec"), ns)
+    monkeypatch.setattr(pins, "fgmres", ns["fgmres"])
+    checks = [pins.test_full_cycle_solves_a_dense_system_exactly,
+              *[(lambda k=k: pins.test_minimal_residual_over_the_krylov_space(k)) for k in (1, 3, 6)],
+              pins.test_flexible_arnoldi_relation_with_a_changing_preconditioner,
+              pins.test_exact_inverse_as_preconditioner_converges_in_one_step,
+              pins.test_restarts_reach_the_tolerance]
+    failed = 0
+    for check in checks:
+        try:
+            check()
+        except Exception:  # an assertion, or the mutant breaking outright
+            failed += 1
+    assert failed > 0, f"no FGMRES pin failed for the planted mistake '{name}'"
