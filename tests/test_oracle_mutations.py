@@ -94,3 +94,49 @@ def test_planted_fgmres_mistake_fails_a_pin(monkeypatch, name):
         except Exception:  # an assertion, or the mutant breaking outright
             failed += 1
     assert failed > 0, f"no FGMRES pin failed for the planted mistake '{name}'"
+
+
+MG_MUTATIONS = {
+    "restriction without the complex conjugate": ("prod = (np.conj(w) * r).sum(axis=2)", "prod = (w * r).sum(axis=2)"),
+    "chirality split by the wrong spins": ("chi_of_spin = np.array([0, 0, 1, 1])", "chi_of_spin = np.array([0, 1, 0, 1])"),
+    "Gram-Schmidt without normalisation": ("cols[k] = w / nrm", "cols[k] = w"),
+    "Gram-Schmidt projection on the raw vectors": ("w = w - np.vdot(cols[j], w) * cols[j]",
+                                                   "w = w - np.vdot(vecs[j][m], w) * cols[j]"),
+    "coarse sites numbered with y fastest": (
+        "idx = ((cx[:, 3] * Lc[2] + cx[:, 2]) * Lc[1] + cx[:, 1]) * Lc[0] + cx[:, 0]",
+        "idx = ((cx[:, 3] * Lc[2] + cx[:, 2]) * Lc[0] + cx[:, 0]) * Lc[1] + cx[:, 1]"),
+    "smoothing step with the wrong sign": ("z = z + (np.vdot(w, r) / np.vdot(w, w)) * r",
+                                           "z = z - (np.vdot(w, r) / np.vdot(w, w)) * r"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", list(MG_MUTATIONS))
+def test_planted_multigrid_mistake_fails_a_pin(monkeypatch, name):
+    """Each planted mistake in a copy of oracle/multigrid.py makes at least one multigrid pin fail."""
+    import types
+
+    from tests import test_oracle_multigrid as pins
+
+    old, new = MG_MUTATIONS[name]
+    with open(os.path.join(ROOT, "oracle", "multigrid.py")) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    mod = types.ModuleType("multigrid_mutant")
+    exec(compile(src.replace(old, new), "multigrid_mutant.py", "exec"), mod.__dict__)
+    monkeypatch.setattr(pins, "mg", mod)
+    checks = [pins.test_block_index_enumerates_blocks,
+              pins.test_block_gram_schmidt_matches_qr_and_spans_the_vectors,
+              pins.test_single_site_aggregates_with_a_full_basis_reproduce_M,
+              lambda: pins.test_free_field_coarse_operator_closed_form((2, 2, 2, 2)),
+              lambda: pins.test_free_field_coarse_operator_closed_form((2, 1, 2, 4)),
+              pins.test_coarse_operator_gamma5_hermitian_and_nearest_neighbour,
+              pins.test_coarse_operator_gauge_invariant,
+              pins.test_two_level_fgmres_beats_plain_gmres]
+    failed = 0
+    for check in checks:
+        try:
+            check()
+        except Exception:
+            failed += 1
+    assert failed > 0, f"no multigrid pin failed for the planted mistake '{name}'"
