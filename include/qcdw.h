@@ -212,6 +212,19 @@ qcdw_status qcdw_hop(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, cons
 qcdw_status qcdw_dslash(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, const void *clover, const void *psi,
                         void *out, double kappa, double csw);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
+   harnesses that forbid hipMalloc): qcdw_dslash with every workspace (packed links, the clover
+   field when clover is NULL, packed A per parity, internal spinors) carved from a fixed device
+   array of QCDW_NOALLOC_MAX_BYTES that the library holds on each device it runs on until the
+   process ends.  No device memory is allocated or freed.  Arguments, layouts and the result are
+   those of qcdw_dslash (the same kernels run).  The workspace needs about 2.6 kB per site (3.2 kB
+   when clover is NULL): lattices beyond the fixed size give QCDW_EINVAL with the size in the
+   message.  Calls on one device share the array, which keeps the last call's contents: calls
+   that overlap on one device (several streams or threads) race, so the caller serialises them. */
+#define QCDW_NOALLOC_MAX_BYTES 67108864
+qcdw_status qcdw_dslash_noalloc(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, const void *clover,
+                                const void *psi, void *out, double kappa, double csw);
+
 /* Operator object (the getDirac + loadGauge step of Sec. III.B): packs U into
    the internal site-major layout (reconstruct-12 when recon == 12, else 18),
    builds the clover field, inverts A on both parities, and keeps FP64 copies

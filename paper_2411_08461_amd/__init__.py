@@ -33,7 +33,8 @@ PREC = {"f64": QCDW_F64, "f32": QCDW_F32, "bf16": QCDW_BF16, "f16": QCDW_F16}
 # every symbol declared in include/qcdw.h
 EXPORTED = (
     "qcdw_solver_params_default", "qcdw_ctx_create", "qcdw_ctx_destroy", "qcdw_last_error", "qcdw_ctx_set_stream",
-    "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_op_create",
+    "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_dslash_noalloc",
+    "qcdw_op_create",
     "qcdw_op_create_aniso", "qcdw_op_destroy", "qcdw_op_hop_form", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
     "qcdw_batch_create", "qcdw_batch_destroy", "qcdw_invert_batch",
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
@@ -112,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "qcdw_clover_invert": (i, [p, lat, p, d, d, p]),
         "qcdw_hop": (i, [p, lat, p, p, p, i]),
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
+        "qcdw_dslash_noalloc": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_create_aniso": (i, [p, lat, p, d, d, d, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_wall_sources": (i, [p, lat, i, ctypes.POINTER(i), p]),
@@ -282,6 +284,22 @@ def qcdw_dslash(ctx: Context, lat: qcdw_lattice, U, clover, psi, out, kappa: flo
     st = load_library().qcdw_dslash(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
                                     _ptr(clover, torch.float64, "clover"), _ptr(psi, torch.complex128, "psi"),
                                     _ptr(out, torch.complex128, "out"), float(kappa), float(csw))
+    _check(ctx.handle, st)
+
+
+NOALLOC_MAX_BYTES = 67108864  # QCDW_NOALLOC_MAX_BYTES of include/qcdw.h
+
+
+def qcdw_dslash_noalloc(ctx: Context, lat: qcdw_lattice, U, clover, psi, out, kappa: float, csw: float) -> None:
+    """qcdw_dslash with its workspace in the library's fixed per-device array (no device allocation)."""
+    V = _volume(lat)
+    _need(U, 36 * V, "U")
+    _need(clover, 72 * V, "clover")
+    _need(psi, 12 * V, "psi")
+    _need(out, 12 * V, "out")
+    st = load_library().qcdw_dslash_noalloc(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                            _ptr(clover, torch.float64, "clover"), _ptr(psi, torch.complex128, "psi"),
+                                            _ptr(out, torch.complex128, "out"), float(kappa), float(csw))
     _check(ctx.handle, st)
 
 

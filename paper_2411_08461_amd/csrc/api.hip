@@ -43,6 +43,10 @@ qcdw_status qcdw_ctx_create(qcdw_ctx** ctx, int device, void* hip_stream)
         qcdw_ctx_destroy(c);
         return QCDW_ENOMEM;
     }
+    if (noalloc_scratch_init(device) != hipSuccess) {  // device address of the fixed no-alloc workspace
+        qcdw_ctx_destroy(c);
+        return QCDW_EHIP;
+    }
     c->tune_load();
     *ctx = c;
     return QCDW_OK;

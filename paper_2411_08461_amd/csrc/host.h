@@ -278,7 +278,11 @@ struct qcdw_batch {
 
 namespace qcdw_host {
 
-constexpr long MAX_PARTIALS = 4096;  // >= blas_blocks(); hop partials are sized per lattice
+constexpr long MAX_PARTIALS = 4096;
+
+// fixed workspace of qcdw_dslash_noalloc (noalloc.hip): device address lookup per device, and bytes needed
+hipError_t noalloc_scratch_init(int device);
+size_t noalloc_dslash_bytes(long Vh, bool build_clover);  // >= blas_blocks(); hop partials are sized per lattice
 
 struct PrecView {
     int prec;
