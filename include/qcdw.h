@@ -55,6 +55,7 @@ typedef struct qcdw_ctx qcdw_ctx;
 typedef struct qcdw_op qcdw_op;
 typedef struct qcdw_batch qcdw_batch;
 typedef struct qcdw_net qcdw_net;
+typedef struct qcdw_mg qcdw_mg;
 
 typedef struct {
     int32_t L[4];  /* Lx, Ly, Lz, Lt: each even and >= 2 */
@@ -356,6 +357,59 @@ qcdw_status qcdw_make_training_pairs(qcdw_op *op, const void *b, int npairs, int
    Returns OK, ENOCONV (x holds the best iterate), ENAN, or EINVAL/ENOMEM/EHIP. */
 qcdw_status qcdw_invert_fgmres(qcdw_op *op, qcdw_net *net, const void *b, void *x, const qcdw_solver_params *params,
                                qcdw_solve_info *info);
+
+/* Two-level aggregation multigrid, the paper's accelerator for Wilson/clover solves (Sec. II.E: the
+   multigrid solver is built from a block size per level, set up when the gauge field is loaded and
+   reusable for other masses; Sec. III.B: a 2^4 sublattice becomes one coarse site).  The lattice is cut
+   into blocks of block[] sites; each block, split by chirality (spins {0,1} and {2,3}), is an aggregate.
+   Near-null vectors v_0 .. v_{nvec-1} (given, or generated by relaxing M v = 0 from seeded Gaussian
+   fields eta_k: v_k = eta_k - y_k after setup_iters BiCGStab iterations on M y = M eta_k from zero) are
+   orthonormalised on every aggregate by modified Gram-Schmidt in the order k = 0, 1, ..: the
+   prolongator P (P^+ P = 1, P commutes with gamma_5; a vector left with less than 1e-10 of its norm
+   outside the span of the earlier ones on an aggregate counts as linearly dependent).  The
+   coarse operator is the Galerkin product D_c = P^+ M P, a nearest-neighbour stencil of (2 nvec)^2
+   complex blocks on the coarse lattice L / block (coarse sites numbered with x fastest).  As the
+   preconditioner of the even-odd system it maps v_e to [P D_c^-1 P^+ (A_ee v_e)]_e (M_hat^-1 =
+   (M^-1)_ee A_ee), the coarse system solved by at most coarse_iters BiCGStab iterations in FP32 (or to
+   coarse_tol relative), followed by smooth_iters minimal-residual steps on M_hat. */
+typedef struct {
+    int32_t block[4];      /* aggregate extents (each divides its lattice extent; their product even) */
+    int32_t nvec;          /* near-null vectors (1 .. 32, at most 6 |block|): 2 nvec unknowns per coarse site */
+    int32_t setup_iters;   /* BiCGStab iterations per generated near-null vector (>= 1) */
+    uint64_t seed;         /* seed of the Gaussian starting fields (counter-based generator) */
+    int32_t coarse_iters;  /* BiCGStab iterations of each coarse solve (>= 0) */
+    double coarse_tol;     /* relative residual at which a coarse solve stops early (> 0) */
+    int32_t smooth_iters;  /* minimal-residual steps on M_hat after the coarse correction (>= 0) */
+} qcdw_mg_params;
+
+/* Defaults: block 4^4, nvec 12, setup_iters 100, seed 1234, coarse_iters 24, coarse_tol 0.1,
+   smooth_iters 2. */
+void qcdw_mg_params_default(qcdw_mg_params *p);
+/* Set up the multigrid for op (the loadGauge step that builds it, Sec. III.B).  vecs: NULL (generate) or
+   nvec device fields in the fermion layout, read.  The object holds the block vectors (FP64 and FP32), the
+   coarse stencil (FP64 and FP32) and the coarse solver workspace; op must outlive it.  EINVAL for a block
+   that does not tile the lattice, nvec out of range or linearly dependent vectors on an aggregate. */
+qcdw_status qcdw_mg_create(qcdw_op *op, const qcdw_mg_params *params, const void *vecs, qcdw_mg **mg);
+void qcdw_mg_destroy(qcdw_mg *mg);
+/* coarse_dims: 4 host ints, L / block; nvec: host int */
+qcdw_status qcdw_mg_info(const qcdw_mg *mg, int *coarse_dims, int *nvec);
+/* The orthonormalised block vectors as nvec device fields in the fermion layout (written). */
+qcdw_status qcdw_mg_vectors(qcdw_mg *mg, void *vecs);
+/* coarse = P^+ fine (fine: device fermion field, read; coarse: device [Vc][2][nvec] complex FP64, written). */
+qcdw_status qcdw_mg_restrict(qcdw_mg *mg, const void *fine, void *coarse);
+/* fine = P coarse (layouts as qcdw_mg_restrict). */
+qcdw_status qcdw_mg_prolong(qcdw_mg *mg, const void *coarse, void *fine);
+/* out = D_c in on coarse vectors [Vc][2][nvec] complex FP64 (device, no aliasing). */
+qcdw_status qcdw_mg_coarse_apply(qcdw_mg *mg, const void *in, void *out);
+/* The coarse stencil as [Vc][9][2 nvec][2 nvec] complex FP64 (row-major blocks; entry 0 couples a coarse
+   site to itself, 1 + 2 mu to its +mu neighbour, 2 + 2 mu to its -mu neighbour): device, written. */
+qcdw_status qcdw_mg_coarse_op(qcdw_mg *mg, void *stencil);
+/* Solve M x = b by FGMRES(m) (m = params->gmres_restart) on the even-odd system with the multigrid
+   preconditioner; conventions of qcdw_invert_fgmres (FP64 true-residual acceptance, BiCGStab fallback).
+   op may be another operator of the same gauge field and lattice (another mass, reusing the set-up as
+   the paper does); EINVAL for another context or lattice. */
+qcdw_status qcdw_invert_mg(qcdw_op *op, qcdw_mg *mg, const void *b, void *x, const qcdw_solver_params *params,
+                           qcdw_solve_info *info);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,9 @@ the algorithm QUDA implements, Clark et al. 2016) written out plainly:
 * Prolongator.  Given near-null vectors v_0 .. v_{N-1} (full fermion fields), the restriction of the
   v_k to each aggregate is orthonormalised in the order k = 0, 1, .. by modified Gram-Schmidt; column
   (x^, chi, k) of P is the k-th orthonormal vector of aggregate (x^, chi), zero elsewhere.  So
-  P^+ P = 1, P commutes with gamma_5 and each v_k lies in the range of P.
+  P^+ P = 1, P commutes with gamma_5 and each v_k lies in the range of P.  A vector whose part
+  outside the span of the earlier ones is below 1e-10 of its norm on some aggregate is rejected
+  as linearly dependent.
 * Coarse vectors: [Vc][2][N] complex, index (x^ chi k) -> (x^ * 2 + chi) * N + k.
 * Coarse operator: D_c = P^+ M P (Galerkin), M the full Wilson-clover matrix of Eq. "clover".
 * Two-level preconditioner for M x = b (one application z = K(v)): coarse correction
@@ -32,6 +34,11 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
+
+
+# a vector whose part outside the span of the previous ones is below this fraction of its norm on an
+# aggregate counts as linearly dependent (rounding leaves ~1e-16 of an exactly dependent vector)
+DEPENDENT = 1e-10
 
 
 def coarse_dims(L, b):
@@ -76,10 +83,11 @@ def block_orthonormalize(L, b, vecs):
         cols = [vecs[k][m].copy() for k in range(N)]
         for k in range(N):
             w = cols[k]
+            n0 = np.linalg.norm(w)
             for j in range(k):
                 w = w - np.vdot(cols[j], w) * cols[j]
             nrm = np.linalg.norm(w)
-            if nrm == 0.0:
+            if not nrm > DEPENDENT * n0:  # (numerically) in the span of the previous vectors, or zero
                 raise ValueError("near-null vectors are linearly dependent on an aggregate")
             cols[k] = w / nrm
             W[k][m] = cols[k]
@@ -116,21 +124,23 @@ def restrict(L, b, W, r):
     return out
 
 
-def coarse_dense(L, b, W, U, clover, kappa: float, csw: float, t_bc: int = 1) -> np.ndarray:
-    """D_c = P^+ M P as a dense (2 N Vc) x (2 N Vc) matrix, column by column: P e_j, then M, then P^+."""
+def coarse_dense(L, b, W, U, clover, kappa: float, csw: float, t_bc: int = 1, weights=None) -> np.ndarray:
+    """D_c = P^+ M P as a dense (2 N Vc) x (2 N Vc) matrix, column by column: P e_j, then M, then P^+
+    (weights: the hop weights of oracle.dirac, for the anisotropic operator)."""
     N = W.shape[0]
     nc = int(np.prod(coarse_dims(L, b))) * 2 * N
     D = np.zeros((nc, nc), dtype=np.complex128)
     for j in range(nc):
         e = np.zeros(nc, dtype=np.complex128)
         e[j] = 1.0
-        D[:, j] = restrict(L, b, W, oracle.dirac(L, U, clover, prolong(L, b, W, e), kappa, csw, t_bc)).reshape(-1)
+        D[:, j] = restrict(L, b, W, oracle.dirac(L, U, clover, prolong(L, b, W, e), kappa, csw, t_bc,
+                                                 weights)).reshape(-1)
     return D
 
 
-def coarse_apply(L, b, W, U, clover, ec, kappa: float, csw: float, t_bc: int = 1):
+def coarse_apply(L, b, W, U, clover, ec, kappa: float, csw: float, t_bc: int = 1, weights=None):
     """D_c e_c = P^+ M P e_c without forming D_c (for lattices where the dense matrix is too large)."""
-    return restrict(L, b, W, oracle.dirac(L, U, clover, prolong(L, b, W, ec), kappa, csw, t_bc))
+    return restrict(L, b, W, oracle.dirac(L, U, clover, prolong(L, b, W, ec), kappa, csw, t_bc, weights))
 
 
 def two_level_precond(L, b, W, U, clover, kappa: float, csw: float, Dc_inv, nu: int = 0, t_bc: int = 1):

@@ -15,6 +15,7 @@ Field layouts follow arXiv 2411.08461, Sec. II.A (complex128 tensors):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import weakref
 
@@ -40,6 +41,8 @@ EXPORTED = (
     "qcdw_net_create", "qcdw_net_destroy", "qcdw_net_bind", "qcdw_net_get_weights", "qcdw_net_set_weights", "qcdw_net_apply",
     "qcdw_net_loss_grad", "qcdw_net_train", "qcdw_make_training_pairs", "qcdw_invert_fgmres",
     "qcdw_wall_sources", "qcdw_meson_2pt", "qcdw_meson_contract", "qcdw_seq_sources", "qcdw_invert_multishift",
+    "qcdw_mg_params_default", "qcdw_mg_create", "qcdw_mg_destroy", "qcdw_mg_info", "qcdw_mg_vectors",
+    "qcdw_mg_restrict", "qcdw_mg_prolong", "qcdw_mg_coarse_apply", "qcdw_mg_coarse_op", "qcdw_invert_mg",
 )
 
 
@@ -89,6 +92,18 @@ class qcdw_solve_info(ctypes.Structure):
     ]
 
 
+class qcdw_mg_params(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32 * 4),
+        ("nvec", ctypes.c_int32),
+        ("setup_iters", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("coarse_iters", ctypes.c_int32),
+        ("coarse_tol", ctypes.c_double),
+        ("smooth_iters", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -114,6 +129,16 @@ def load_library(path: str = LIB_PATH):
         "qcdw_hop": (i, [p, lat, p, p, p, i]),
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_dslash_noalloc": (i, [p, lat, p, p, p, p, d, d]),
+        "qcdw_mg_params_default": (None, [ctypes.POINTER(qcdw_mg_params)]),
+        "qcdw_mg_create": (i, [p, ctypes.POINTER(qcdw_mg_params), p, ctypes.POINTER(p)]),
+        "qcdw_mg_destroy": (None, [p]),
+        "qcdw_mg_info": (i, [p, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "qcdw_mg_vectors": (i, [p, p]),
+        "qcdw_mg_restrict": (i, [p, p, p]),
+        "qcdw_mg_prolong": (i, [p, p, p]),
+        "qcdw_mg_coarse_apply": (i, [p, p, p]),
+        "qcdw_mg_coarse_op": (i, [p, p]),
+        "qcdw_invert_mg": (i, [p, p, p, p, ctypes.POINTER(qcdw_solver_params), ctypes.POINTER(qcdw_solve_info)]),
         "qcdw_op_create": (i, [p, lat, p, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_op_create_aniso": (i, [p, lat, p, d, d, d, d, d, i, i, ctypes.POINTER(p)]),
         "qcdw_wall_sources": (i, [p, lat, i, ctypes.POINTER(i), p]),
@@ -726,6 +751,109 @@ def qcdw_invert_fgmres(op: Operator, net, b, x, params: qcdw_solver_params | Non
     st = load_library().qcdw_invert_fgmres(op.handle, net.handle if net is not None else None,
                                            _ptr(b, torch.complex128, "b"), _ptr(x, torch.complex128, "x"),
                                            ctypes.byref(params), ctypes.byref(info))
+    if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
+        _check(op.ctx.handle, st)
+    return SolveInfo(info, hist)
+
+
+# ---------------------------------------------------------------------------
+# multigrid
+# ---------------------------------------------------------------------------
+def make_mg_params(**kw) -> qcdw_mg_params:
+    """qcdw_mg_params with the library defaults, then the given fields (block: 4 ints)."""
+    prm = qcdw_mg_params()
+    load_library().qcdw_mg_params_default(ctypes.byref(prm))
+    for k, v in kw.items():
+        if k == "block":
+            for mu in range(4):
+                prm.block[mu] = int(v[mu])
+        elif not hasattr(prm, k):
+            raise AttributeError(k)
+        else:
+            setattr(prm, k, v)
+    return prm
+
+
+class Multigrid:
+    """qcdw_mg: two-level aggregation multigrid set up on one operator (vecs: None or nvec fermion fields)."""
+
+    _rank = 0
+
+    def __init__(self, op: Operator, params: qcdw_mg_params | None = None, vecs=None):
+        self.op = op
+        if params is None:
+            params = make_mg_params()
+        self.params = params
+        if vecs is not None:
+            _need(vecs, params.nvec * 12 * op.volume, "vecs")
+        h = ctypes.c_void_p()
+        st = load_library().qcdw_mg_create(op.handle, ctypes.byref(params),
+                                           _ptr(vecs, torch.complex128, "vecs") if vecs is not None else None,
+                                           ctypes.byref(h))
+        _check(op.ctx.handle, st)
+        self.handle = h
+        dims = (ctypes.c_int * 4)()
+        nv = ctypes.c_int()
+        _check(op.ctx.handle, load_library().qcdw_mg_info(h, dims, ctypes.byref(nv)))
+        self.coarse_dims = tuple(dims)
+        self.nvec = nv.value
+        self.coarse_sites = int(math.prod(self.coarse_dims))
+        op.ctx._adopt(self)
+        op._children.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().qcdw_mg_destroy(self.handle)
+            self.handle = None
+
+    def coarse_len(self) -> int:
+        return self.coarse_sites * 2 * self.nvec
+
+
+def qcdw_mg_vectors(mg: Multigrid, out) -> None:
+    _need(out, mg.nvec * 12 * mg.op.volume, "out")
+    _check(mg.op.ctx.handle, load_library().qcdw_mg_vectors(mg.handle, _ptr(out, torch.complex128, "out")))
+
+
+def qcdw_mg_restrict(mg: Multigrid, fine, coarse) -> None:
+    _need(fine, 12 * mg.op.volume, "fine")
+    _need(coarse, mg.coarse_len(), "coarse")
+    _check(mg.op.ctx.handle, load_library().qcdw_mg_restrict(mg.handle, _ptr(fine, torch.complex128, "fine"),
+                                                             _ptr(coarse, torch.complex128, "coarse")))
+
+
+def qcdw_mg_prolong(mg: Multigrid, coarse, fine) -> None:
+    _need(fine, 12 * mg.op.volume, "fine")
+    _need(coarse, mg.coarse_len(), "coarse")
+    _check(mg.op.ctx.handle, load_library().qcdw_mg_prolong(mg.handle, _ptr(coarse, torch.complex128, "coarse"),
+                                                            _ptr(fine, torch.complex128, "fine")))
+
+
+def qcdw_mg_coarse_apply(mg: Multigrid, cin, cout) -> None:
+    _need(cin, mg.coarse_len(), "in")
+    _need(cout, mg.coarse_len(), "out")
+    _check(mg.op.ctx.handle, load_library().qcdw_mg_coarse_apply(mg.handle, _ptr(cin, torch.complex128, "in"),
+                                                                 _ptr(cout, torch.complex128, "out")))
+
+
+def qcdw_mg_coarse_op(mg: Multigrid, stencil) -> None:
+    _need(stencil, mg.coarse_sites * 9 * (2 * mg.nvec) ** 2, "stencil")
+    _check(mg.op.ctx.handle, load_library().qcdw_mg_coarse_op(mg.handle, _ptr(stencil, torch.complex128, "stencil")))
+
+
+def qcdw_invert_mg(op: Operator, mg: Multigrid, b, x, params: qcdw_solver_params | None = None):
+    """FGMRES(m) with the multigrid preconditioner; returns a SolveInfo."""
+    if params is None:
+        params = make_params()
+    _need(b, 12 * op.volume, "b")
+    _need(x, 12 * op.volume, "x")
+    n_hist = max(1, params.maxiter + 2)
+    hist = (ctypes.c_double * n_hist)()
+    info = qcdw_solve_info()
+    info.hist_len = n_hist
+    info.res_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    st = load_library().qcdw_invert_mg(op.handle, mg.handle, _ptr(b, torch.complex128, "b"),
+                                       _ptr(x, torch.complex128, "x"), ctypes.byref(params), ctypes.byref(info))
     if st in (QCDW_EINVAL, QCDW_ENOMEM, QCDW_EHIP):
         _check(op.ctx.handle, st)
     return SolveInfo(info, hist)

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -339,6 +340,11 @@ inline hipError_t matpc(hipStream_t s, const qcdw_op* op, const PrecView& v, con
     b.stop = stop;
     return launch_hop(s, v.prec, v.recon, EPI_CLOV_XPAY, red, b);
 }
+
+// right preconditioner of FGMRES: z = K(v) on FP64 even-site internal fields
+using Precond = std::function<qcdw_status(const void* v, void* z)>;
+qcdw_status fgmres_run(qcdw_op* op, const Precond* precond, const void* b, void* x, const qcdw_solver_params* params,
+                       qcdw_solve_info* info);
 
 inline qcdw_status read_double(qcdw_ctx* ctx, const double* dev, double& out)
 {

@@ -464,8 +464,10 @@ extern "C" qcdw_status qcdw_make_training_pairs(qcdw_op* op, const void* b, int 
 // ---------------------------------------------------------------------------
 // flexible GMRES on the even-odd system
 // ---------------------------------------------------------------------------
-extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void* b, void* x,
-                                          const qcdw_solver_params* params, qcdw_solve_info* info)
+// FGMRES(m) on the even-odd system with right preconditioning z_j = precond(v_j) (FP64 even-site internal
+// fields; nullptr: none), shared by the learned net and the multigrid preconditioner
+qcdw_status qcdw_host::fgmres_run(qcdw_op* op, const Precond* precond, const void* b, void* x,
+                                  const qcdw_solver_params* params, qcdw_solve_info* info)
 {
     if (!op) return QCDW_EINVAL;
     qcdw_ctx* ctx = op->ctx;
@@ -485,7 +487,6 @@ extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void
     CHK(check_dev(ctx, b, "b"));
     CHK(check_dev(ctx, x, "x"));
     if (b == x) return fail(ctx, QCDW_EINVAL, "x must not alias b");
-    if (net && net->op != op) return fail(ctx, QCDW_EINVAL, "the net was built on another operator");
     if (!(prm.tol > 0.0)) return fail(ctx, QCDW_EINVAL, "tol must be positive");
     const int m = prm.gmres_restart;
     if (m < 1 || m > 64) return fail(ctx, QCDW_EINVAL, "gmres_restart must lie in [1, 64]");
@@ -508,7 +509,7 @@ extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void
     HIPCHK(ctx, tmp.alloc(vb));
     HIPCHK(ctx, tmpo.alloc(vb));
     HIPCHK(ctx, V.alloc(vb * (m + 1)));
-    if (net) HIPCHK(ctx, Z.alloc(vb * m));
+    if (precond) HIPCHK(ctx, Z.alloc(vb * m));
     const int ngroups = (m + 1 + 7) / 8;
     HIPCHK(ctx, part.alloc((size_t)16 * ngroups * blas_blocks(n) * sizeof(double) + 64));
     HIPCHK(ctx, coef.alloc(2 * 65 * sizeof(double)));
@@ -517,7 +518,7 @@ extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void
     double* dpart = (double*)part.p;
     double* dd = (double*)dres.p;
     auto Vk = [&](int k) { return (char*)V.p + (size_t)k * vb; };
-    auto Zk = [&](int k) { return net ? (char*)Z.p + (size_t)k * vb : Vk(k); };
+    auto Zk = [&](int k) { return precond ? (char*)Z.p + (size_t)k * vb : Vk(k); };
     auto rd = [&](int cnt, double* out) -> qcdw_status {
         HIPCHK(ctx, hipMemcpyAsync(ctx->host_d, dd, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
@@ -628,7 +629,7 @@ extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void
         int j = 0;
         for (; j < m && iters < prm.maxiter; j++) {
             // z_j = P(v_j), w = M_hat z_j
-            if (net) CHK(net_forward_internal(net, BF16, Vk(j), Zk(j)));
+            if (precond) CHK((*precond)(Vk(j), Zk(j)));
             HIPCHK(ctx, matpc(s, op, v64, Zk(j), w.p, tmpo.p, RED_NONE, nullptr, nullptr, nullptr));
             // block classical Gram-Schmidt against v_0..v_j, twice; the coefficients stay on the
             // device (dd[0..], dd[128..]), ||w||^2 lands in dd[256] and v_{j+1} = w / ||w|| is
@@ -685,7 +686,7 @@ extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void
             hy[2 * i + 1] = y[i].imag();
         }
         HIPCHK(ctx, hipMemcpyAsync(coef.p, hy, 2 * j * sizeof(double), hipMemcpyHostToDevice, s));
-        if (net) HIPCHK(ctx, launch_multiaxpy(s, Z.p, n, j, (const double*)coef.p, xe.p, n, 1.0));
+        if (precond) HIPCHK(ctx, launch_multiaxpy(s, Z.p, n, j, (const double*)coef.p, xe.p, n, 1.0));
         else HIPCHK(ctx, launch_multiaxpy(s, V.p, n, j, (const double*)coef.p, xe.p, n, 1.0));
         cycles++;
         const double rn_prev = rn;
@@ -734,4 +735,13 @@ extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void
     if (status != QCDW_OK)
         return fail(ctx, status, "FGMRES did not reach tol (iters %d, true residual %.3e)", iters, true_res);
     return QCDW_OK;
+}
+
+extern "C" qcdw_status qcdw_invert_fgmres(qcdw_op* op, qcdw_net* net, const void* b, void* x,
+                                          const qcdw_solver_params* params, qcdw_solve_info* info)
+{
+    if (!op) return QCDW_EINVAL;
+    if (net && net->op != op) return fail(op->ctx, QCDW_EINVAL, "the net was built on another operator");
+    const Precond pnet = [net](const void* v, void* z) { return net_forward_internal(net, BF16, v, z); };
+    return fgmres_run(op, net ? &pnet : nullptr, b, x, params, info);
 }

@@ -47,6 +47,8 @@ def test_struct_layout_matches_header(tmp_path):
         'printf("%zu %zu %zu\\n", sizeof(qcdw_lattice), sizeof(qcdw_solver_params), sizeof(qcdw_solve_info));\n'
         'printf("%zu %zu %zu %zu\\n", offsetof(qcdw_solver_params, delta), offsetof(qcdw_solver_params, fault_inject),'
         " offsetof(qcdw_solve_info, true_res), offsetof(qcdw_solve_info, res_hist));\n"
+        'printf("%zu %zu %zu %zu\\n", sizeof(qcdw_mg_params), offsetof(qcdw_mg_params, seed),'
+        " offsetof(qcdw_mg_params, coarse_tol), offsetof(qcdw_mg_params, smooth_iters));\n"
         "return 0;}\n"
     )
     exe = tmp_path / "layout"
@@ -58,6 +60,9 @@ def test_struct_layout_matches_header(tmp_path):
                      ctypes.sizeof(q.qcdw_solve_info)]
     assert offs == [q.qcdw_solver_params.delta.offset, q.qcdw_solver_params.fault_inject.offset,
                     q.qcdw_solve_info.true_res.offset, q.qcdw_solve_info.res_hist.offset]
+    mg = [int(v) for v in lines[2].split()]
+    assert mg == [ctypes.sizeof(q.qcdw_mg_params), q.qcdw_mg_params.seed.offset, q.qcdw_mg_params.coarse_tol.offset,
+                  q.qcdw_mg_params.smooth_iters.offset]
 
 
 def test_calls_without_gpu_fail_loudly():

@@ -186,3 +186,14 @@ def test_two_level_fgmres_beats_plain_gmres():
     x = np.linalg.solve(oracle.dense_matrix(L, U, C, kappa, csw), rhs.reshape(-1)).reshape(rhs.shape)
     assert _rel(pre.x, x) < 1e-8
     assert pre.iters < plain.iters / 2, (pre.iters, plain.iters)
+
+
+def test_dependent_vectors_are_rejected():
+    """A vector that is a multiple of an earlier one on an aggregate (here everywhere) has no part outside
+    their span beyond rounding and is rejected; an independent set is accepted."""
+    L, b = (4, 4, 2, 2), (2, 2, 2, 2)
+    V = _vecs(L, 2, 90)
+    mg.block_orthonormalize(L, b, V)
+    V[1] = (2.0 - 0.5j) * V[0]
+    with pytest.raises(ValueError, match="dependent"):
+        mg.block_orthonormalize(L, b, V)
