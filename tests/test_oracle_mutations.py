@@ -140,3 +140,44 @@ def test_planted_multigrid_mistake_fails_a_pin(monkeypatch, name):
         except Exception:
             failed += 1
     assert failed > 0, f"no multigrid pin failed for the planted mistake '{name}'"
+
+
+FORCE_MUTATIONS = {
+    "variation multiplied from the right": ("Up[mu, i] = Uf[mu, i] + 1j * T[a] @ Uf[mu, i]",
+                                           "Up[mu, i] = Uf[mu, i] + 1j * Uf[mu, i] @ T[a]"),
+    "variation without the factor i": ("Up[mu, i] = Uf[mu, i] + 1j * T[a] @ Uf[mu, i]",
+                                       "Up[mu, i] = Uf[mu, i] + T[a] @ Uf[mu, i]"),
+    "imaginary part of the bilinear": ("H[mu, i] += 2.0 * np.vdot(Y, d).real * T[a]",
+                                       "H[mu, i] += 2.0 * np.vdot(Y, d).imag * T[a]"),
+    "factor 2 of the real part dropped": ("H[mu, i] += 2.0 * np.vdot(Y, d).real * T[a]",
+                                          "H[mu, i] += np.vdot(Y, d).real * T[a]"),
+    "a generator with the wrong normalisation": ("lam[7] = np.diag([1, 1, -2]) / np.sqrt(3)",
+                                                 "lam[7] = np.diag([1, 1, -2]) / 3"),
+}
+
+
+@pytest.mark.parametrize("name", list(FORCE_MUTATIONS))
+def test_planted_force_mistake_fails_a_pin(monkeypatch, name):
+    """Each planted mistake in a copy of oracle/force.py makes at least one force pin fail."""
+    import types
+
+    from tests import test_oracle_force as pins
+
+    old, new = FORCE_MUTATIONS[name]
+    with open(os.path.join(ROOT, "oracle", "force.py")) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    mod = types.ModuleType("force_mutant")
+    exec(compile(src.replace(old, new), "force_mutant.py", "exec"), mod.__dict__)
+    monkeypatch.setattr(pins, "of", mod)
+    checks = [pins.test_generators_normalised,
+              lambda: pins.test_force_matches_group_finite_difference(1),
+              pins.test_two_flavour_hmc_force,
+              pins.test_force_gauge_covariant_and_hermitian_traceless]
+    failed = 0
+    for check in checks:
+        try:
+            check()
+        except Exception:
+            failed += 1
+    assert failed > 0, f"no force pin failed for the planted mistake '{name}'"
