@@ -275,9 +275,10 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
             if (nct % d == 0) return d;
         return 0;
     };
-    std::vector<int> cand;  // codes nt + 16 cg + 4096 fma
+    std::vector<int> cand;  // codes nt + 16 cg + 4096 fma (fma: bit 0 multiply-add form, bit 1 LDS staging)
     auto add = [&](int nt, int cg) {
-        for (int f : {0, 1}) {
+        for (int f : {0, 1, 2, 3}) {
+            if ((f & 2) && !(nt == 1 && cg > 0)) continue;  // staging needs slice groups, one site per thread group
             const int code = nt + 16 * cg + 4096 * f;
             if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && std::find(cand.begin(), cand.end(), code) == cand.end())
                 cand.push_back(code);
@@ -298,7 +299,7 @@ static qcdw_status tune_op_hop(qcdw_op* op, int prec)
     auto it = ctx->tune.find(key);
     if (it != ctx->tune.end()) {
         const int nt = it->second % 16, cg = (it->second / 16) % 256, f = it->second / 4096;
-        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && (f == 0 || f == 1)) {
+        if (hop_nt_fits(g, nt) && hop_cgroup_fits(g, cg) && f >= 0 && f <= 3 && (!(f & 2) || (nt == 1 && cg > 0))) {
             apply(it->second);
             return QCDW_OK;
         }

@@ -4,8 +4,8 @@
 //
 // Internal (library-owned) layouts, one parity of Vh sites each:
 //   spinor  [4 spin][Vh site][3 colour] complex        (spin-major, colour inner)
-//   gauge   [4 mu][2 parity][Vh site][R] complex, R = 6 (rows 0,1: reconstruct-12)
-//           or 9 (full link), row-major colour order
+//   gauge   [4 mu][2 parity][R][Vh site] complex in FP64, [4 mu][2 parity][Vh site][R] in FP32 and
+//           16-bit storage; R = 6 (rows 0,1: reconstruct-12) or 9 (full link), row-major colour order
 //   clover  [Vh site][2 chirality][36 entry] reals, entries in the reordered packing of
 //           hop.hip, so a lane's 27-entry window is contiguous (wide per-lane loads; layouts
 //           with sites fastest were measured slower on gfx950)
@@ -203,18 +203,23 @@ __host__ __device__ inline void sp_coords(long e, long Vh, long& s, long& site, 
 
 // Internal gauge field of R complex entries per link (R = 6: the first two rows, R = 9: all), by
 // direction mu and parity p.  Entry j of link (mu, p, site) sits at link_base(mu, p, site) +
-// j * link_stride: link-major ([mu][p][Vh][R]), or site-fastest ([mu][p][R][Vh]) with
-// QCDW_LINK_SOA=1, where the consecutive sites of a wave read one contiguous run per entry.  The
-// site-fastest form measured no faster in FP64 and slower in BF16 (the entries of a link can no
-// longer be fetched by one wide load), so link-major is the default.
+// j * link_stride: link-major ([mu][p][Vh][R]), or site-fastest ([mu][p][R][Vh]), where the 16 sites
+// of a wave read one contiguous run per entry instead of 16 records 6 entries apart.  The layout
+// follows the storage precision: site-fastest in FP64 (the hop measured 5-7 % faster at 24^3 x 64),
+// link-major in FP32 and 16-bit storage (a link's entries are fetched by wide per-lane loads there;
+// site-fastest measured 10-20 % slower in BF16).  QCDW_LINK_SOA = 0 / 1 forces one layout for all.
 #ifndef QCDW_LINK_SOA
-#define QCDW_LINK_SOA 0
+#define QCDW_LINK_SOA -1
 #endif
-__host__ __device__ inline long link_base(int mu, int p, long site, long Vh, int R)
+__host__ __device__ constexpr bool link_soa_for(int cbytes)
 {
-    return QCDW_LINK_SOA ? (long)(mu * 2 + p) * R * Vh + site : ((long)(mu * 2 + p) * Vh + site) * R;
+    return QCDW_LINK_SOA < 0 ? cbytes == 16 : QCDW_LINK_SOA != 0;
 }
-__host__ __device__ inline long link_stride(long Vh) { return QCDW_LINK_SOA ? Vh : 1; }
+__host__ __device__ inline long link_base(int mu, int p, long site, long Vh, int R, bool soa)
+{
+    return soa ? (long)(mu * 2 + p) * R * Vh + site : ((long)(mu * 2 + p) * Vh + site) * R;
+}
+__host__ __device__ inline long link_stride(long Vh, bool soa) { return soa ? Vh : 1; }
 
 // coordinates of checkerboard index i on parity p
 __device__ __forceinline__ void site_coords(const Geom& g, int i, int p, int& x, int& y, int& z, int& t)

@@ -138,8 +138,11 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
 // thread of the block calls it); `part` receives the block's reduction partials
 // (RED != RED_NONE).  F: the multiply-add form of the hop arithmetic (hop_rows);
 // which form is faster depends on the lattice, so the operator's tuner picks it.
-template <class P, int R, int EPI, int RED, bool F = false>
-__device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid, double* part)
+// STG: the t-neighbours of the block's 64 sites were staged in LDS by the caller (stg: [t+1 | t-1][spin]
+// [site in tile][colour]); the t-lanes read them from there.
+template <class P, int R, int EPI, int RED, bool F = false, bool STG = false>
+__device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid, double* part,
+                                         const cx<typename P::real>* stg = nullptr)
 {
     using T = typename P::real;
     const Geom g = a.g;
@@ -152,11 +155,21 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, int site, bool valid,
     for (int c = 0; c < 3; c++) acc_u[c] = acc_l[c] = {T(0), T(0)};
     if (valid) {
         LaneHops<T, R> L;
-        lane_hops<T, R>(g, site, a.parity, q, L);
+        lane_hops<T, R, link_soa_for(P::cbytes)>(g, site, a.parity, q, L);
 #pragma unroll
         for (int h = 0; h < 4; h++) {
             cx<T> pu[3], pl[3], hv[3];
-            load_pair<P>(a.psi, g.Vh, su, sl, L.nbh[h], pu, pl);
+            if (STG && gq == 1 && h >= 2) {
+                const int j = threadIdx.x >> 2;
+                const cx<T>* b = stg + (h - 2) * (4 * HOP_SITES_PER_BLOCK * 3);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    pu[c] = b[(su * HOP_SITES_PER_BLOCK + j) * 3 + c];
+                    pl[c] = b[(sl * HOP_SITES_PER_BLOCK + j) * 3 + c];
+                }
+            } else {
+                load_pair<P>(a.psi, g.Vh, su, sl, L.nbh[h], pu, pl);
+            }
             project<F>(pu, pl, L.cs[h], h < 2, hv);
             hop_apply<F, P, R>(a.gauge, L, h, hv, acc_u, acc_l);
         }
@@ -179,7 +192,12 @@ __device__ __forceinline__ void hop_tile(const HopArgs& a, int tile, double* par
 // t inside each group of G c-tiles: (c-tile in group, then t, then group).  The
 // input slice t is read by the output slices t - 1, t, t + 1, which then run
 // G tiles apart instead of a whole slice apart, so its spinors stay in L2.
-template <class P, int R, int EPI, int RED, bool F>
+//
+// STG (slice groups only): the tile's 64 sites share t, so their t-neighbours are the same 64 c of
+// slices t + 1 and t - 1.  The block first copies those two runs (all spins) into LDS, each thread
+// loading consecutive elements of the contiguous runs, and the t-lanes then read their neighbour
+// spins from LDS instead of with per-lane strided loads.
+template <class P, int R, int EPI, int RED, bool F, bool STG>
 __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
 {
     if (a.stop && *a.stop) return;
@@ -191,7 +209,24 @@ __global__ __launch_bounds__(256) QCDW_HOP_ATTR void hop_kernel(HopArgs a)
         const int grp = tile / (G * g.Lt), r = tile - grp * G * g.Lt;
         const int t = r / G, ct = grp * G + (r - t * G);
         const int c = ct * HOP_SITES_PER_BLOCK + (threadIdx.x >> 2);
-        hop_site<P, R, EPI, RED, F>(a, t * St + c, c < St, part);
+        if constexpr (STG) {
+            using T = typename P::real;
+            constexpr int RUN = 4 * HOP_SITES_PER_BLOCK * 3;  // complex per staged slice run
+            __shared__ cx<T> stg[2 * RUN];
+            const int c0 = ct * HOP_SITES_PER_BLOCK;
+            const int tp = t + 1 == g.Lt ? 0 : t + 1, tm = t == 0 ? g.Lt - 1 : t - 1;
+            for (int e = threadIdx.x; e < 2 * RUN; e += 256) {
+                const int d = e / RUN, rem = e - d * RUN;  // rem = (spin * 64 + j) * 3 + colour
+                const int col = rem % 3, sj = rem / 3, sp = sj / HOP_SITES_PER_BLOCK, j = sj % HOP_SITES_PER_BLOCK;
+                cx<T> v = {T(0), T(0)};
+                if (c0 + j < St) v = P::ld(a.psi, sp_idx(sp, (d == 0 ? tp : tm) * St + c0 + j, col, g.Vh));
+                stg[e] = v;
+            }
+            __syncthreads();
+            hop_site<P, R, EPI, RED, F, true>(a, t * St + c, c < St, part, stg);
+        } else {
+            hop_site<P, R, EPI, RED, F>(a, t * St + c, c < St, part);
+        }
     } else {
         hop_tile<P, R, EPI, RED, F>(a, tile, part);
     }
@@ -244,7 +279,7 @@ __global__ __launch_bounds__(256) QCDW_TKERNEL_ATTR void hop_tkernel(HopArgs a)
         for (int cc = 0; cc < 3; cc++) acc_u[cc] = acc_l[cc] = {T(0), T(0)};
         if (valid) {
             LaneHops<T, R> L;
-            lane_hops<T, R>(g, site, a.parity, q, L);
+            lane_hops<T, R, link_soa_for(P::cbytes)>(g, site, a.parity, q, L);
             cx<T> next[3];  // this step's forward t-neighbour, projected for the next step
 #pragma unroll
             for (int h = 0; h < 4; h++) {
@@ -324,12 +359,12 @@ __global__ __launch_bounds__(256) void hop_batch_kernel(BatchHopArgs b)
     }
 }
 
-template <class P, int R, int NT, bool F>
+template <class P, int R, int NT, bool F, bool STG = false>
 static hipError_t launch_hop_nt(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
     dim3 grid(hop_blocks_nt(a.g, NT, a.cgroup)), block(256);
     // with events, they are recorded by the dispatch itself (exact kernel time)
-#define QCDW_HOP_KERNEL(E, D) hop_kernel<P, R, E, D, F>
+#define QCDW_HOP_KERNEL(E, D) hop_kernel<P, R, E, D, F, STG>
 #define QCDW_TKERNEL(E, D) hop_tkernel<P, R, E, D, NT, F>
 #define QCDW_HOP_CASE(E, D)                                                                            \
     if (epi == E && red == D) {                                                                       \
@@ -357,6 +392,10 @@ static hipError_t launch_hop_nt(hipStream_t s, int epi, int red, const HopArgs& 
 template <class P, int R, bool F>
 static hipError_t launch_hop_prf(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
+    if (a.fma & 2) {  // LDS-staged t-neighbours: slice groups, one site per thread group
+        if (a.cgroup <= 0 || a.nt > 1) return hipErrorInvalidValue;
+        return launch_hop_nt<P, R, 1, F, true>(s, epi, red, a, e0, e1);
+    }
     switch (a.nt) {
     case 2: return launch_hop_nt<P, R, 2, F>(s, epi, red, a, e0, e1);
     case 4: return launch_hop_nt<P, R, 4, F>(s, epi, red, a, e0, e1);
@@ -369,7 +408,8 @@ template <class P, int R>
 static hipError_t launch_hop_pr(hipStream_t s, int epi, int red, const HopArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
     if (!hop_nt_fits(a.g, a.nt) || !hop_cgroup_fits(a.g, a.cgroup)) return hipErrorInvalidValue;
-    return a.fma ? launch_hop_prf<P, R, true>(s, epi, red, a, e0, e1) : launch_hop_prf<P, R, false>(s, epi, red, a, e0, e1);
+    return (a.fma & 1) ? launch_hop_prf<P, R, true>(s, epi, red, a, e0, e1)
+                       : launch_hop_prf<P, R, false>(s, epi, red, a, e0, e1);
 }
 
 template <class P>

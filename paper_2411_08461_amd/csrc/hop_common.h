@@ -122,12 +122,12 @@ struct LaneHops {
     T cs[4], fsg[4];
 };
 
-template <typename T, int R>
+template <typename T, int R, bool SOA>
 __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q, LaneHops<T, R>& L)
 {
     const int gq = q >> 1, k = q & 1;
     const long Vh = g.Vh;
-    L.lstr = link_stride(Vh);
+    L.lstr = link_stride(Vh, SOA);
     int x, y, z, t;
     site_coords(g, site, p, x, y, z, t);
     const int xh = site % g.Lxh;
@@ -168,8 +168,8 @@ __device__ __forceinline__ void lane_hops(const Geom& g, int site, int p, int q,
         // with (1 + g_mu), which flips the projection coefficient
         L.nbh[2 * j] = fwd;
         L.nbh[2 * j + 1] = bwd;
-        L.loff[2 * j] = link_base(mu, p, site, Vh, R);
-        L.loff[2 * j + 1] = link_base(mu, 1 - p, bwd, Vh, R);
+        L.loff[2 * j] = link_base(mu, p, site, Vh, R, SOA);
+        L.loff[2 * j + 1] = link_base(mu, 1 - p, bwd, Vh, R, SOA);
         L.cs[2 * j] = c_s;
         L.cs[2 * j + 1] = -c_s;
         // boundary sign times the direction's weight (spatial hops: g.xs)

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
 #pragma unroll
     for (int e = 0; e < 27; e++) win[e] = T(0);
     if (valid) {
-        lane_hops<T, 6>(g, site, a.parity, q, L);
+        lane_hops<T, 6, link_soa_for(P::cbytes)>(g, site, a.parity, q, L);
 #pragma unroll
         for (int h = 0; h < 4; h++) load_link<P, 6>(a.gauge, L.loff[h], L.lstr, ur[h]);
         if constexpr (EPI != EPI_NONE) load_window<P>(a.clov, Vh, site, q, win);

@@ -45,7 +45,8 @@ struct HopArgs {
     const int* stop;    // if non-null and *stop != 0 the launch does nothing
     int nt;             // single-RHS hop: output sites per thread along t (1, 2, 4 or 8; 0 means 1)
     int cgroup;         // single-RHS hop: c-tiles per group swept along t (0: no grouping)
-    int fma;            // single-RHS hop: multiply-add form of the hop arithmetic (0 or 1)
+    int fma;            // single-RHS hop: bit 0 the multiply-add form of the hop arithmetic, bit 1 the
+                        // t-neighbours staged in LDS (slice groups with one site per thread group only)
 };
 
 // one problem of a batched solve (device table entry); reconstruct-12 operators
@@ -235,6 +236,9 @@ hipError_t launch_clover_apply(hipStream_t s, const Geom& g, const void* clover,
 hipError_t launch_clover_invert(hipStream_t s, const Geom& g, const void* clover, double kappa, double csw,
                                 void* inv, int* notpd_count);
 // packed A = 1 - kappa csw C (paper clover layout) for the full-operator epilogue
+// clover fermion force of the bilinear 2 Re(Y^+ M X) (force.hip); Gam: scratch of 6 x 144 V bytes
+hipError_t launch_clover_force(hipStream_t s, const Geom& g, const void* U, const void* X, const void* Y,
+                               double kappa, double csw, void* Gam, void* H);
 hipError_t launch_clover_to_A(hipStream_t s, const Geom& g, const void* clover, double kappa, double csw, void* A);
 
 }  // namespace qcdw

@@ -78,7 +78,8 @@ __device__ __forceinline__ cx<double> herm6(const double* A, int site, int chi, 
 template <int R>
 __device__ __forceinline__ void link3(const void* gauge, int mu, int p, int site, int Vh, cx<double> (&u)[9])
 {
-    load_link<P64, R>(gauge, link_base(mu, p, site, Vh, R), link_stride(Vh), u);
+    constexpr bool soa = link_soa_for(P64::cbytes);
+    load_link<P64, R>(gauge, link_base(mu, p, site, Vh, R, soa), link_stride(Vh, soa), u);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,7 +16,7 @@ namespace qcdw {
 struct NetArgs {
     const void* in;
     void* out;
-    const void* gauge;  // P32 reconstruct-12 links (link_base, link_stride)
+    const void* gauge;  // reconstruct-12 links in FP32, in the layout of the FP64 links (link_base, link_stride)
     const float2* W;    // [9][COUT][CIN]
     Geom g;
 };
@@ -24,7 +24,8 @@ struct NetArgs {
 // link (mu, p, site) of an FP32 reconstruct-12 internal gauge field (two rows stored)
 __device__ __forceinline__ void su3_row3(const void* gauge, int mu, int p, int site, long Vh, cx<float> (&u)[9])
 {
-    const long off = link_base(mu, p, site, Vh, 6), st = link_stride(Vh);
+    constexpr bool soa = link_soa_for(P64::cbytes);  // an element-wise FP32 copy of the operator's FP64 links
+    const long off = link_base(mu, p, site, Vh, 6, soa), st = link_stride(Vh, soa);
 #pragma unroll
     for (int e = 0; e < 6; e++) u[e] = P32::ld(gauge, off + e * st);
     u[6] = conj(u[1] * u[5] - u[2] * u[4]);

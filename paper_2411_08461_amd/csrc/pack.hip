@@ -42,7 +42,8 @@ __global__ void k_pack_gauge(const double2* __restrict__ paper, void* out, int V
     const int site = (int)(link % Vh), mp = (int)(link / Vh);
     const double2 v = paper[link * 9 + j];
     using T = typename P::real;
-    P::st(out, link_base(mp >> 1, mp & 1, site, Vh, R) + j * link_stride(Vh), cx<T>{(T)v.x, (T)v.y});
+    constexpr bool soa = link_soa_for(P::cbytes);
+    P::st(out, link_base(mp >> 1, mp & 1, site, Vh, R, soa) + j * link_stride(Vh, soa), cx<T>{(T)v.x, (T)v.y});
 }
 
 // clover: paper [2][Vh][2][36] -> internal (one parity) [Vh][2][36] in the reordered packing

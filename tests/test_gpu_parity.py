@@ -164,7 +164,7 @@ def _forced_nt_context(tmp_path, monkeypatch, L, nt, cg=0, fma=0):
 
 @pytest.mark.parametrize("L", [(8, 8, 8, 16), (6, 4, 2, 8), (10, 6, 4, 8)])
 @pytest.mark.parametrize("nt,cg,fma", [(2, 0, 0), (4, 0, 0), (1, 1, 0), (1, 2, 0), (2, 1, 0), (4, 2, 0),
-                                       (1, 0, 1), (2, 0, 1), (4, 0, 1), (1, 1, 1), (2, 1, 1)])
+                                       (1, 0, 1), (2, 0, 1), (4, 0, 1), (1, 1, 1), (2, 1, 1), (1, 1, 2), (1, 2, 3)])
 def test_t_stepping_matpc(tmp_path, monkeypatch, L, nt, cg, fma):
     """M_hat through the other single-RHS hop forms (nt sites per thread along t; tiles of one
     t-slice swept along t in groups of cg c-tiles; the multiply-add arithmetic form) equals the
@@ -199,6 +199,34 @@ def test_t_stepping_matpc(tmp_path, monkeypatch, L, nt, cg, fma):
     for key, val in outs.items():
         if key[0] == code:
             assert rel(val, outs[(1,) + key[1:]]) < bound[key[2]], key
+
+
+@pytest.mark.parametrize("L", [(8, 8, 8, 16), (6, 4, 2, 8), (10, 6, 4, 8)])
+def test_lds_staged_hop_bitwise_equals_unstaged(tmp_path, monkeypatch, L):
+    """The slice-group hop with its t-neighbour spinors staged in LDS (fma bit 1) runs the same arithmetic
+    on the same values as the unstaged form: M_hat is bitwise equal in every precision, for both
+    arithmetic forms, on lattices whose t-slices hold several tiles, one partial tile and a ragged last
+    tile."""
+    U = _gauge(L, 0.3, 43)
+    kappa, csw = 0.124, 1.0
+    Vh = int(np.prod(L)) // 2
+    xe = dev(li.gaussian_source(L, 44).reshape(-1, 4, 3)[:Vh].copy())
+    outs = {}
+    for f in (0, 1, 2, 3):
+        c = _forced_nt_context(tmp_path, monkeypatch, L, 1, 1, f)
+        for prec in ("f32", "bf16", "f16"):
+            op = q.Operator(c, q.make_lattice(L), dev(U), kappa, csw, prec, 12)
+            assert q.qcdw_op_hop_form(op, "f64") == (1, 1, f)
+            for pr in ("f64", prec):
+                out = torch.empty((Vh, 4, 3), dtype=torch.complex128, device="cuda")
+                q.qcdw_op_matpc(op, pr, xe, out)
+                outs[(f, prec, pr)] = host(out)
+            op.close()
+        torch.cuda.synchronize()
+        c.close()
+    for (f, prec, pr), val in outs.items():
+        if f & 2:
+            assert np.array_equal(val, outs[(f & 1, prec, pr)]), (f, prec, pr)
 
 
 # ---------------------------------------------------------------------------
@@ -592,7 +620,8 @@ def test_mixed_solve_escalates_near_the_critical_kappa(ctx):
     op.close()
 
 
-@pytest.mark.parametrize("nt,cg,fma", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 0), (1, 0, 1), (2, 1, 1)])
+@pytest.mark.parametrize("nt,cg,fma", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (2, 1, 0), (1, 0, 1), (2, 1, 1),
+                                       (1, 1, 3)])
 def test_t_stepping_hop_in_solves(tmp_path, monkeypatch, nt, cg, fma):
     """Solves whose single-RHS hops take a forced form (nt sites per thread along t, slice groups,
     arithmetic form; through the tuning cache) reach an oracle-checked true residual <= 1e-10, in
