@@ -249,11 +249,12 @@ void qcdw_op_destroy(qcdw_op *op);
 /* The form of the operator's single-RHS parity hop in precision prec (F64 or the inner
    precision), chosen by timing when the operator was created or read from the tuning cache
    ($QCDW_TUNE_CACHE, the role of the paper's resource_path, Sec. III.B): *nt output sites per
-   thread along t (1, 2, 4 or 8), *cgroup c-tiles per group swept along t (0: none) and *fma the
-   arithmetic form (1: every complex multiply-add as real multiply-adds; fma may be NULL).  nt and
-   cgroup change only the order of memory accesses; fma changes the rounding of the result (within
-   a few units in the last place per site).  Returns QCDW_EINVAL for a NULL nt or cgroup or
-   another precision. */
+   thread along t (1, 2, 4 or 8), *cgroup c-tiles per group swept along t (0: none) and *fma (may be
+   NULL): bit 0 the arithmetic form (every complex multiply-add as real multiply-adds), bit 1 the
+   t-neighbour spinors of each 64-site tile staged in LDS (slice groups with nt = 1 only).  nt,
+   cgroup and the staging change only the order of memory accesses; bit 0 changes the rounding of
+   the result (within a few units in the last place per site).  Returns QCDW_EINVAL for a NULL nt
+   or cgroup or another precision. */
 qcdw_status qcdw_op_hop_form(const qcdw_op *op, qcdw_prec prec, int *nt, int *cgroup, int *fma);
 
 /* The even-odd preconditioned operator of Sec. II.A / II.D (the Schur complement on even sites
@@ -357,6 +358,17 @@ qcdw_status qcdw_make_training_pairs(qcdw_op *op, const void *b, int npairs, int
    Returns OK, ENOCONV (x holds the best iterate), ENAN, or EINVAL/ENOMEM/EHIP. */
 qcdw_status qcdw_invert_fgmres(qcdw_op *op, qcdw_net *net, const void *b, void *x, const qcdw_solver_params *params,
                                qcdw_solve_info *info);
+
+/* Clover fermion force, the link derivative that HMC with clover fermions integrates (Sec. IV):
+   for the operator M = A - kappa H of qcdw_dslash (isotropic, time boundary of lat) and fields X, Y,
+     H_mu(x) = sum_a T^a d/dw [2 Re(Y^+ M(U_w) X)] at w = 0,  U_w: U_mu(x) -> exp(i w T^a) U_mu(x),
+   T^a = lambda^a / 2 (Gell-Mann), every other link fixed; H_mu(x) is Hermitian and traceless.  For the
+   two-flavour action S = phi^+ (M^+ M)^-1 phi with X = (M^+ M)^-1 phi and Y = M X (two qcdw_invert
+   solves: Y = g5 M^-1 g5 phi, X = M^-1 Y), the derivative of S along T^a is -2 Tr(T^a H_mu(x)).
+   U: gauge layout (read; SU(3) not required); X, Y: fermion layout (read); H: gauge layout (written,
+   no aliasing).  Uses a scratch field of 6 x 144 V bytes. */
+qcdw_status qcdw_clover_force(qcdw_ctx *ctx, const qcdw_lattice *lat, const void *U, const void *X, const void *Y,
+                              double kappa, double csw, void *H);
 
 /* Two-level aggregation multigrid, the paper's accelerator for Wilson/clover solves (Sec. II.E: the
    multigrid solver is built from a block size per level, set up when the gauge field is loaded and

@@ -14,6 +14,7 @@ Field layouts follow arXiv 2411.08461, Sec. II.A (complex128 tensors):
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
 import os
@@ -43,6 +44,7 @@ EXPORTED = (
     "qcdw_wall_sources", "qcdw_meson_2pt", "qcdw_meson_contract", "qcdw_seq_sources", "qcdw_invert_multishift",
     "qcdw_mg_params_default", "qcdw_mg_create", "qcdw_mg_destroy", "qcdw_mg_info", "qcdw_mg_vectors",
     "qcdw_mg_restrict", "qcdw_mg_prolong", "qcdw_mg_coarse_apply", "qcdw_mg_coarse_op", "qcdw_invert_mg",
+    "qcdw_clover_force",
 )
 
 
@@ -129,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "qcdw_hop": (i, [p, lat, p, p, p, i]),
         "qcdw_dslash": (i, [p, lat, p, p, p, p, d, d]),
         "qcdw_dslash_noalloc": (i, [p, lat, p, p, p, p, d, d]),
+        "qcdw_clover_force": (i, [p, lat, p, p, p, d, d, p]),
         "qcdw_mg_params_default": (None, [ctypes.POINTER(qcdw_mg_params)]),
         "qcdw_mg_create": (i, [p, ctypes.POINTER(qcdw_mg_params), p, ctypes.POINTER(p)]),
         "qcdw_mg_destroy": (None, [p]),
@@ -215,6 +218,23 @@ def _check(ctx_handle, st: int):
         raise QcdwError(st, msg.decode() if msg else "")
 
 
+# Contexts still open when the interpreter exits (a caller that never closed them, or a failure that
+# left them referenced) are closed by an exit handler.  It is registered after torch's, so it runs
+# before torch releases its streams and device state, while the objects' streams are still valid.
+_live_contexts = weakref.WeakSet()
+
+
+def _close_live_contexts():
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_live_contexts)
+
+
 class Context:
     """qcdw_ctx bound to one device and one HIP stream (torch's current one by default)."""
 
@@ -232,6 +252,7 @@ class Context:
         if st != QCDW_OK:
             raise QcdwError(st, "qcdw_ctx_create failed")
         self.handle = h
+        _live_contexts.add(self)
 
     def _adopt(self, obj):
         self._children.add(obj)
@@ -309,6 +330,19 @@ def qcdw_dslash(ctx: Context, lat: qcdw_lattice, U, clover, psi, out, kappa: flo
     st = load_library().qcdw_dslash(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
                                     _ptr(clover, torch.float64, "clover"), _ptr(psi, torch.complex128, "psi"),
                                     _ptr(out, torch.complex128, "out"), float(kappa), float(csw))
+    _check(ctx.handle, st)
+
+
+def qcdw_clover_force(ctx: Context, lat: qcdw_lattice, U, X, Y, kappa: float, csw: float, H) -> None:
+    """H_mu(x) = sum_a T^a d/dw [2 Re(Y^+ M X)] along exp(i w T^a) U_mu(x) (gauge layout, Hermitian traceless)."""
+    V = _volume(lat)
+    _need(U, 36 * V, "U")
+    _need(X, 12 * V, "X")
+    _need(Y, 12 * V, "Y")
+    _need(H, 36 * V, "H")
+    st = load_library().qcdw_clover_force(ctx.handle, ctypes.byref(lat), _ptr(U, torch.complex128, "U"),
+                                          _ptr(X, torch.complex128, "X"), _ptr(Y, torch.complex128, "Y"),
+                                          float(kappa), float(csw), _ptr(H, torch.complex128, "H"))
     _check(ctx.handle, st)
 
 
