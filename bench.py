@@ -96,6 +96,13 @@ def parse():
     ap.add_argument("--matpc-only", default="",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then a few M_hat "
                          "applications in FP64 and BF16 on this lattice, e.g. 24,24,24,64; prints nothing else")
+    ap.add_argument("--net-only", default="",
+                    help="profiling mode: a 256 MiB device copy, then three applications of the learned net "
+                         "(12 hidden channels) in FP32 and in BF16 on this lattice, with its BF16 layers on "
+                         "the vector units and then on the matrix cores; prints one JSON line")
+    ap.add_argument("--mg-only", action="store_true",
+                    help="profiling mode: the learned section's multigrid set-up and FGMRES solve at 32^3x64 "
+                         "only; prints one JSON line")
     ap.add_argument("--forms", default="",
                     help="with --matpc-only: hop forms nt:cgroup[:fma] to run one after the other (each in a fresh "
                          "context whose tuning file fixes the form), e.g. 1:0,1:27,2:12")
@@ -141,8 +148,91 @@ def matpc_only(L, forms):
     print(json.dumps({"matpc_only": list(L), "copy_bytes": 2 * src.numel() * 8, "forms": runs}))
 
 
+def net_only(L):
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import lattice_inputs as li
+    import paper_2411_08461_amd as q
+
+    src = torch.empty(32 * 2 ** 20, dtype=torch.float64, device="cuda")  # 256 MiB
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    Vh = int(np.prod(L)) // 2
+    U = torch.from_numpy(li.random_gauge(L, 0.15, 0)).cuda()
+    xe = torch.from_numpy(li.gaussian_source(L, 1000).reshape(-1, 4, 3)[:Vh].copy()).cuda()
+    out = torch.empty_like(xe)
+    runs = []
+    for mfma in (0, 1):  # a fresh context reads the tuning file that fixes the layer kind
+        path = os.path.join(tempfile.gettempdir(), f"qcdw_net_mfma_{mfma}.txt")
+        with open(path, "w") as fh:
+            fh.write(f"net_mfma/h12/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {mfma}\n")
+        os.environ["QCDW_TUNE_CACHE"] = path
+        ctx = q.Context(0)
+        op = q.Operator(ctx, q.make_lattice(L), U, 0.12781, 1.0, "bf16", 12)
+        net = q.Net(op, 12, seed=5, init_scale=0.01)
+        ms = {}
+        for prec in ("f32", "bf16"):
+            q.qcdw_net_apply(net, prec, xe, out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                q.qcdw_net_apply(net, prec, xe, out)
+            torch.cuda.synchronize()
+            ms[prec] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+        runs.append({"mfma": mfma, "apply_ms": ms})
+        net.close()
+        op.close()
+        ctx.close()
+    print(json.dumps({"net_only": list(L), "copy_bytes": 2 * src.numel() * 8, "runs": runs}))
+
+
+# multigrid of the learned section at 32^3x64: 8^4 aggregates (a 4^3x8 coarse lattice), 12 near-null vectors
+# from 120 BF16 relaxation iterations each, at most 40 coarse BiCGStab iterations, 4 smoothing steps
+MG_PARAMS = dict(block=(8, 8, 8, 8), nvec=12, setup_iters=120, coarse_iters=40, smooth_iters=4)
+
+
+def mg_only():
+    import torch
+
+    import lattice_inputs as li
+    import paper_2411_08461_amd as q
+
+    w = li.WORKLOADS["wc32x64"]
+    L = w["L"]
+    U = li.random_gauge(L, w["eps"], w["seed"])
+    b = torch.from_numpy(li.gaussian_source(L, w["source_seed"])).cuda()
+    ctx = q.Context(0)
+    op = q.Operator(ctx, q.make_lattice(L), torch.from_numpy(U).cuda(), w["kappa"], w["csw"], "bf16", 12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = q.Multigrid(op, q.make_mg_params(**MG_PARAMS))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    x = torch.zeros_like(b)
+    t0 = time.perf_counter()
+    info = q.qcdw_invert_mg(op, mg, b, x, q.make_params(tol=1e-10, maxiter=4000))
+    torch.cuda.synchronize()
+    print(json.dumps({"mg_only": list(L), "params": MG_PARAMS, "setup_ms": round(1e3 * t_setup, 1),
+                      "status": info.status_name, "iters": info.iters, "true_res": info.true_res,
+                      "time_ms": round(1e3 * (time.perf_counter() - t0), 1)}))
+    mg.close()
+    op.close()
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.net_only:
+        net_only([int(v) for v in args.net_only.split(",")])
+        return
+    if args.mg_only:
+        mg_only()
+        return
     if args.matpc_only:
         forms = [tuple(int(x) for x in f.split(":")) for f in args.forms.split(",") if f]
         matpc_only([int(v) for v in args.matpc_only.split(",")], forms)
@@ -577,7 +667,8 @@ def batch(q, li, np, torch, ctx, fields, args):
     return out
 
 
-LEARNED_TRAIN_SEEDS = range(1, 9)
+LEARNED_TRAIN_SEEDS = range(1, 5)
+LEARNED_STRIDE = 20  # training pairs: errors of BiCGStab iterates restarted every 20 iterations
 
 
 def learned_jobs(li):
@@ -588,8 +679,9 @@ def learned_jobs(li):
 
 
 def learned(q, li, np, torch, ctx, fields, args):
-    """32^3x64 near the critical kappa: train the gauge-covariant net on 8 other fields of the ensemble
-    (32 random-error pairs each, 256 in all), then FGMRES(32)+net against plain FP64 and mixed BiCGStab
+    """32^3x64 near the critical kappa: train the gauge-covariant net on 4 other fields of the ensemble
+    (32 solver-generated pairs each: the errors of BiCGStab iterates against an FP64 solution of a Gaussian
+    source of that field, 128 in all), then FGMRES(32)+net against plain FP64 and mixed BiCGStab
     and FGMRES(32) without the net, all to an FP64 true residual of 1e-10 from the Gaussian source."""
     w = li.WORKLOADS["wc32x64"]
     if w["kappa"] is None:
@@ -597,7 +689,7 @@ def learned(q, li, np, torch, ctx, fields, args):
     L, kappa, csw = w["L"], w["kappa"], w["csw"]
     lat = q.make_lattice(L)
     out = {"workload": f"32^3x64, kappa {kappa} (bisected), csw 1.0, eps 0.15, Gaussian source"}
-    # training on fields 1..8
+    # training on fields 1..4
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net, losses, prev = None, [], None
@@ -610,10 +702,11 @@ def learned(q, li, np, torch, ctx, fields, args):
         if prev is not None:
             prev.close()
         prev = op
-        r, e = q.qcdw_make_training_pairs(op, None, 32, -(1000 + k))
-        h = q.qcdw_net_train(net, r, e, steps=40, batch=4, lr=2e-3, seed=k)
+        src = torch.from_numpy(li.gaussian_source(L, w["source_seed"] + k)).cuda()
+        r, e = q.qcdw_make_training_pairs(op, src, 32, LEARNED_STRIDE)
+        h = q.qcdw_net_train(net, r, e, steps=60, batch=4, lr=2e-3, seed=k)
         losses.append((float(np.mean(h[:4])), float(np.mean(h[-4:]))))
-        del r, e
+        del r, e, src
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     op = q.Operator(ctx, lat, torch.from_numpy(fields[0]).cuda(), kappa, csw, "bf16", 12)
@@ -633,7 +726,8 @@ def learned(q, li, np, torch, ctx, fields, args):
         out["hop_gbs"][prec] = {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                                 "avg_launch_us": round(ms * 1e3, 1), "form": q.qcdw_op_hop_form(op, prec)}
     del xt
-    out["training"] = {"fields": len(losses), "pairs": 32 * len(losses), "steps": 40 * len(losses),
+    out["training"] = {"fields": len(losses), "pairs": 32 * len(losses), "steps": 60 * len(losses),
+                       "pairs_from": f"BiCGStab iterates restarted every {LEARNED_STRIDE} iterations",
                        "time_s": round(t_train, 2), "loss_first_field": [round(v, 4) for v in losses[0]],
                        "loss_last_field": [round(v, 4) for v in losses[-1]]}
     runs = {
@@ -656,6 +750,27 @@ def learned(q, li, np, torch, ctx, fields, args):
             out[name].update(fallback=info.fallback, fallback_iters=info.fallback_iters, cycles=info.n_restarts)
         print(f"[learned] {name}: {out[name]}", file=sys.stderr, flush=True)
     out["speedup_net_vs_f64"] = round(out["bicgstab_f64"]["time_ms"] / out["fgmres32_net"]["time_ms"], 3)
+    # the paper's accelerator for clover solves: two-level aggregation multigrid (MG_PARAMS: aggregates,
+    # near-null vectors relaxed by BF16 iterations), set up on this operator, then FGMRES(32) with it
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = q.Multigrid(op, q.make_mg_params(**MG_PARAMS))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = q.qcdw_invert_mg(op, mg, b, x, q.make_params(tol=1e-10, maxiter=4000))
+    torch.cuda.synchronize()
+    out["fgmres32_mg"] = {"status": info.status_name, "iters": info.iters, "true_res": info.true_res,
+                          "time_ms": round(1e3 * (time.perf_counter() - t0), 1), "setup_ms": round(1e3 * t_setup, 1),
+                          "fallback": info.fallback, "params": MG_PARAMS}
+    print(f"[learned] fgmres32_mg: {out['fgmres32_mg']}", file=sys.stderr, flush=True)
+    out["speedup_mg_vs_f64"] = round(out["bicgstab_f64"]["time_ms"] / out["fgmres32_mg"]["time_ms"], 3)
+    out["speedup_mg_with_setup_vs_f64"] = round(out["bicgstab_f64"]["time_ms"] /
+                                                (out["fgmres32_mg"]["time_ms"] + out["fgmres32_mg"]["setup_ms"]), 3)
+    mg.close()
+    del x
     net.close()
     op.close()
     del b

@@ -393,7 +393,8 @@ __global__ __launch_bounds__(256) void k_mg_prolong(MgDev m, const void* W, cons
 
 // out = D_c in, one thread per (coarse site, row); red = RED_WDOT: partials of (w, out); RED_TS: partials
 // of (out, y) and ||out||^2; nothing when *stop != 0 (the solve has finished)
-template <class P, int RED>
+// (PY: storage of the stencil, P: of the vectors)
+template <class PY, class P, int RED>
 __global__ __launch_bounds__(256) void k_mg_coarse_apply(MgDev m, const void* Yt, const void* in, void* out,
                                                           const void* y, double* partials, const int* stop)
 {
@@ -410,7 +411,10 @@ __global__ __launch_bounds__(256) void k_mg_coarse_apply(MgDev m, const void* Yt
             const int nb = d == 0 ? cs : m.cnbr[(long)cs * 8 + (d - 1)];
             const long yb = ((long)cs * 9 + d) * ne + row;
             const long ib = (long)nb * nc;
-            for (int col = 0; col < nc; col++) cmac(acc, P::ld(Yt, yb + (long)col * nc), P::ld(in, ib + col));
+            for (int col = 0; col < nc; col++) {
+                const auto yv = PY::ld(Yt, yb + (long)col * nc);
+                cmac(acc, cx<T>{(T)yv.re, (T)yv.im}, P::ld(in, ib + col));
+            }
         }
         P::st(out, tid, acc);
     }
@@ -458,24 +462,25 @@ __global__ void k_mg_coarse_init(Scal* S, const double* norm2, double tol2, doub
     S->hist_norm = 1.0;
 }
 
-// minimal-residual step: partials of (w, r) and ||w||^2
-__global__ __launch_bounds__(256) void k_mg_mr_dots(const double2* __restrict__ w, const double2* __restrict__ r,
-                                                    long n, double* partials)
+// minimal-residual step: partials of (w, r) and ||w||^2 (vectors in storage precision P)
+template <class P>
+__global__ __launch_bounds__(256) void k_mg_mr_dots(const void* w, const void* r, long n, double* partials)
 {
     double v[3] = {0.0, 0.0, 0.0};
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
-        const double2 a = w[e], b = r[e];
-        v[0] += a.x * b.x + a.y * b.y;
-        v[1] += a.x * b.y - a.y * b.x;
-        v[2] += a.x * a.x + a.y * a.y;
+        const auto a = P::ld(w, e), b = P::ld(r, e);
+        v[0] += (double)a.re * b.re + (double)a.im * b.im;
+        v[1] += (double)a.re * b.im - (double)a.im * b.re;
+        v[2] += (double)a.re * a.re + (double)a.im * a.im;
     }
     block_sum_store<3>(v, partials + 3L * blockIdx.x);
 }
 
-// alpha = (w, r) / (w, w) from nb partials (every block sums them in the same order), z += alpha r,
-// r -= alpha w
-__global__ __launch_bounds__(256) void k_mg_mr_update(double2* z, double2* r, const double2* __restrict__ w, long n,
-                                                      const double* partials, int nb)
+// alpha = (w, r) / (w, w) from nb partials (every block sums them in the same order), z += alpha r (z in
+// PZ), r -= alpha w (r, w in P)
+template <class P, class PZ>
+__global__ __launch_bounds__(256) void k_mg_mr_update(void* z, void* r, const void* w, long n, const double* partials,
+                                                      int nb)
 {
     __shared__ double tot[3];
     double v[3] = {0.0, 0.0, 0.0};
@@ -485,13 +490,15 @@ __global__ __launch_bounds__(256) void k_mg_mr_update(double2* z, double2* r, co
     __syncthreads();
     const double ww = tot[2];
     const double ar = ww > 0.0 ? tot[0] / ww : 0.0, ai = ww > 0.0 ? tot[1] / ww : 0.0;
+    using T = typename P::real;
+    using TZ = typename PZ::real;
+    const cx<T> al = {(T)ar, (T)ai};
+    const cx<TZ> alz = {(TZ)ar, (TZ)ai};
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
-        const double2 rv = r[e], wv = w[e];
-        double2 zv = z[e];
-        zv.x += ar * rv.x - ai * rv.y;
-        zv.y += ar * rv.y + ai * rv.x;
-        z[e] = zv;
-        r[e] = make_double2(rv.x - (ar * wv.x - ai * wv.y), rv.y - (ar * wv.y + ai * wv.x));
+        const auto rv = P::ld(r, e), wv = P::ld(w, e);
+        const auto zv = PZ::ld(z, e);
+        PZ::st(z, e, zv + alz * cx<TZ>{(TZ)rv.re, (TZ)rv.im});
+        P::st(r, e, rv - al * wv);
     }
 }
 
@@ -500,6 +507,19 @@ __global__ __launch_bounds__(256) void k_mg_mr_update(double2* z, double2* r, co
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Storage of the coarse stencil in the preconditioner's coarse solve (QCDW_MG_YPREC: 0 FP32, 1 BF16,
+// 2 FP16) and the smoother's precision (QCDW_MG_SMOOTH_F64 = 1: FP64, else the operator's inner one).
+#ifndef QCDW_MG_YPREC
+#define QCDW_MG_YPREC 1
+#endif
+#ifndef QCDW_MG_SMOOTH_F64
+#define QCDW_MG_SMOOTH_F64 0
+#endif
+namespace qcdw {
+using MG_YP = std::conditional_t<QCDW_MG_YPREC == 0, P32, std::conditional_t<QCDW_MG_YPREC == 1, PBF16, PF16>>;
+constexpr int MG_YPREC = QCDW_MG_YPREC == 0 ? F32 : QCDW_MG_YPREC == 1 ? BF16 : F16;
+}  // namespace qcdw
+
 struct qcdw_mg {
     qcdw_op* op = nullptr;  // operator the set-up and the coarse operator were made with
     qcdw_ctx* ctx = nullptr;
@@ -507,11 +527,12 @@ struct qcdw_mg {
     MgDev md{};
     PoolBuf blk_sites, fine_loc, cnbr;
     PoolBuf W64, W32;        // block vectors
-    PoolBuf Yt64, Yt32;      // coarse stencil, column-major blocks
+    PoolBuf Yt64, Ylo;       // coarse stencil, column-major blocks: FP64 (API), MG_YP (the preconditioner's solve)
     PoolBuf rc, ec, ec64;    // coarse right-hand side (FP64), solution (FP32), FP64 scratch
     PoolBuf ck[6];           // coarse BiCGStab vectors r, r0, p, v, s, t (FP32)
     PoolBuf scal, dpart, dpart2, dnorm, dscale;
     PoolBuf t64, r64, w64, tmpo;  // fine even-site FP64 scratch of the preconditioner
+    PoolBuf rlo, wlo, zlo, tmplo;  // smoother vectors in the operator's inner precision (z accumulated in FP32)
     long n_c = 0;                  // complex entries of a coarse vector
     int nb_apply = 0, nb_blas = 0, nb_fine = 0;
 };
@@ -577,7 +598,7 @@ qcdw_status mg_build_coarse(qcdw_mg* mg, qcdw_op* op)
     const MgDev& m = mg->md;
     const long nst = (long)m.Vc * 9 * m.nc * m.nc;
     HIPCHK(ctx, mg->Yt64.alloc(nst * 16));
-    HIPCHK(ctx, mg->Yt32.alloc(nst * 8));
+    HIPCHK(ctx, mg->Ylo.alloc(nst * MG_YP::cbytes));
     const PrecView v = view(op, F64);
     if (v.recon == 12)
         hipLaunchKernelGGL(k_mg_coarse_build<6>, dim3(m.Vc * 9), dim3(256), 0, s, m, (const double2*)mg->W64.p,
@@ -588,15 +609,15 @@ qcdw_status mg_build_coarse(qcdw_mg* mg, qcdw_op* op)
                            v.gauge, (const double*)op->A64[0].p, (const double*)op->A64[1].p, op->kappa,
                            (double2*)mg->Yt64.p);
     HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, launch_convert(s, F64, F32, mg->Yt64.p, mg->Yt32.p, nst, 1.0));
+    HIPCHK(ctx, launch_convert(s, F64, MG_YPREC, mg->Yt64.p, mg->Ylo.p, nst, 1.0));
     return QCDW_OK;
 }
 
-template <class P, int RED>
+template <class PY, class P, int RED>
 hipError_t coarse_apply(hipStream_t s, const qcdw_mg* mg, const void* Yt, const void* in, void* out, const void* y,
                         double* partials, const int* stop)
 {
-    hipLaunchKernelGGL((k_mg_coarse_apply<P, RED>), dim3(mg->nb_apply), dim3(256), 0, s, mg->md, Yt, in, out, y,
+    hipLaunchKernelGGL((k_mg_coarse_apply<PY, P, RED>), dim3(mg->nb_apply), dim3(256), 0, s, mg->md, Yt, in, out, y,
                        partials, stop);
     return hipGetLastError();
 }
@@ -626,10 +647,10 @@ qcdw_status mg_precondition(qcdw_mg* mg, qcdw_op* op, const void* v, void* z)
     HIPCHK(ctx, launch_cycle_start(s, F32, mg->rc.p, r, r0, p, mg->ec.p, mg->n_c, (const double*)mg->dscale.p, S,
                                    dpart2, 1, nullptr, 0, false));
     for (int it = 0; it < mg->prm.coarse_iters; it++) {
-        HIPCHK(ctx, (coarse_apply<P32, RED_WDOT>(s, mg, mg->Yt32.p, p, vv, r0, dpart, &S->flags)));
+        HIPCHK(ctx, (coarse_apply<MG_YP, P32, RED_WDOT>(s, mg, mg->Ylo.p, p, vv, r0, dpart, &S->flags)));
         HIPCHK(ctx, launch_fin_alpha(s, S, dpart, mg->nb_apply, 1, nullptr));
         HIPCHK(ctx, launch_bicg_s(s, F32, sv, r, vv, mg->n_c, S, 1, nullptr, 0, nullptr, 0, nullptr));
-        HIPCHK(ctx, (coarse_apply<P32, RED_TS>(s, mg, mg->Yt32.p, sv, t, sv, dpart, &S->flags)));
+        HIPCHK(ctx, (coarse_apply<MG_YP, P32, RED_TS>(s, mg, mg->Ylo.p, sv, t, sv, dpart, &S->flags)));
         HIPCHK(ctx, launch_fin_omega(s, S, dpart, mg->nb_apply, 1, nullptr));
         HIPCHK(ctx, launch_bicg_xr(s, F32, F32, mg->ec.p, p, sv, r, t, r0, mg->n_c, S, dpart2, 1, nullptr, 0, nullptr,
                                    0, nullptr));
@@ -640,19 +661,36 @@ qcdw_status mg_precondition(qcdw_mg* mg, qcdw_op* op, const void* v, void* z)
     hipLaunchKernelGGL((k_mg_prolong<P32, P32, P64>), dim3(m.Vc), dim3(256), 0, s, m, mg->W32.p, mg->ec.p, dn2, z,
                        nullptr, 1);
     HIPCHK(ctx, hipGetLastError());
-    // minimal-residual smoothing on M_hat: r = v - M_hat z, then z += alpha r, r -= alpha w with w = M_hat r
+    // minimal-residual smoothing on M_hat in the operator's inner precision: r = v - M_hat z, then
+    // z_s += alpha r, r -= alpha w with w = M_hat r (alpha = (w, r) / (w, w)), and finally z += z_s
     if (mg->prm.smooth_iters > 0) {
-        const PrecView v64 = view(op, F64);
-        HIPCHK(ctx, matpc(s, op, v64, z, mg->w64.p, mg->tmpo.p, RED_NONE, nullptr, nullptr, nullptr));
+        const int lp = QCDW_MG_SMOOTH_F64 ? (int)F64 : op->inner;
+        const PrecView vl = view(op, lp);
+        HIPCHK(ctx, launch_convert(s, F64, lp, z, mg->zlo.p, n, 1.0));          // z in the inner precision
+        HIPCHK(ctx, matpc(s, op, vl, mg->zlo.p, mg->wlo.p, mg->tmplo.p, RED_NONE, nullptr, nullptr, nullptr));
+        HIPCHK(ctx, launch_convert(s, F64, lp, v, mg->rlo.p, n, 1.0));
+        HIPCHK(ctx, launch_convert(s, lp, F64, mg->wlo.p, mg->w64.p, n, 1.0));
         HIPCHK(ctx, launch_xmy_norm2(s, F64, F64, v, mg->w64.p, mg->r64.p, n, dpart2, dn2));
+        HIPCHK(ctx, launch_convert(s, F64, lp, mg->r64.p, mg->rlo.p, n, 1.0));  // r = v - M_hat z
+        HIPCHK(ctx, launch_convert(s, F64, F32, mg->r64.p, mg->zlo.p, n, 0.0));  // z_s = 0 (FP32)
         for (int it = 0; it < mg->prm.smooth_iters; it++) {
-            HIPCHK(ctx, matpc(s, op, v64, mg->r64.p, mg->w64.p, mg->tmpo.p, RED_NONE, nullptr, nullptr, nullptr));
-            hipLaunchKernelGGL(k_mg_mr_dots, dim3(mg->nb_fine), dim3(256), 0, s, (const double2*)mg->w64.p,
-                               (const double2*)mg->r64.p, n, dpart2);
-            hipLaunchKernelGGL(k_mg_mr_update, dim3(mg->nb_fine), dim3(256), 0, s, (double2*)z, (double2*)mg->r64.p,
-                               (const double2*)mg->w64.p, n, (const double*)dpart2, mg->nb_fine);
+            HIPCHK(ctx, matpc(s, op, vl, mg->rlo.p, mg->wlo.p, mg->tmplo.p, RED_NONE, nullptr, nullptr, nullptr));
+            switch (lp) {
+#define QCDW_MR_CASE(PREC, P)                                                                                      \
+    case PREC:                                                                                                     \
+        hipLaunchKernelGGL(k_mg_mr_dots<P>, dim3(mg->nb_fine), dim3(256), 0, s, mg->wlo.p, mg->rlo.p, n, dpart2);   \
+        hipLaunchKernelGGL((k_mg_mr_update<P, P32>), dim3(mg->nb_fine), dim3(256), 0, s, mg->zlo.p, mg->rlo.p,       \
+                           mg->wlo.p, n, (const double*)dpart2, mg->nb_fine);                                      \
+        break;
+                QCDW_MR_CASE(F64, P64)
+                QCDW_MR_CASE(F32, P32)
+                QCDW_MR_CASE(BF16, PBF16)
+                QCDW_MR_CASE(F16, PF16)
+#undef QCDW_MR_CASE
+            }
             HIPCHK(ctx, hipGetLastError());
         }
+        HIPCHK(ctx, launch_axpy_hi(s, F32, 1.0, nullptr, mg->zlo.p, z, n));  // z += z_s
     }
     return QCDW_OK;
 }
@@ -795,6 +833,10 @@ extern "C" qcdw_status qcdw_mg_create(qcdw_op* op, const qcdw_mg_params* params,
     HIPCHK(ctx, mg->r64.alloc(nfe * 16));
     HIPCHK(ctx, mg->w64.alloc(nfe * 16));
     HIPCHK(ctx, mg->tmpo.alloc(nfe * 16));
+    HIPCHK(ctx, mg->rlo.alloc(nfe * 16));
+    HIPCHK(ctx, mg->wlo.alloc(nfe * 16));
+    HIPCHK(ctx, mg->zlo.alloc(nfe * 16));
+    HIPCHK(ctx, mg->tmplo.alloc(nfe * 16));
     HIPCHK(ctx, hipStreamSynchronize(s));
     *out = mg.release();
     return QCDW_OK;
@@ -872,7 +914,7 @@ extern "C" qcdw_status qcdw_mg_coarse_apply(qcdw_mg* mg, const void* in, void* o
     CHK(check_dev(ctx, in, "in"));
     CHK(check_dev(ctx, out, "out"));
     if (in == out) return fail(ctx, QCDW_EINVAL, "out must not alias in");
-    HIPCHK(ctx, (coarse_apply<P64, RED_NONE>(ctx->stream, mg, mg->Yt64.p, in, out, nullptr, nullptr, nullptr)));
+    HIPCHK(ctx, (coarse_apply<P64, P64, RED_NONE>(ctx->stream, mg, mg->Yt64.p, in, out, nullptr, nullptr, nullptr)));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return QCDW_OK;
 }
