@@ -106,10 +106,14 @@ def parse():
     ap.add_argument("--forms", default="",
                     help="with --matpc-only: hop forms nt:cgroup[:fma] to run one after the other (each in a fresh "
                          "context whose tuning file fixes the form), e.g. 1:0,1:27,2:12")
+    ap.add_argument("--mrhs-forms", default="",
+                    help="with --matpc-only: instead of the single-RHS forms, M_hat on 12 BF16 right-hand sides "
+                         "with each of these multi-RHS hop forms (values of qcdw_ctx_tuned's mrhs_hop keys), "
+                         "e.g. 0,1024")
     return ap.parse_args()
 
 
-def matpc_only(L, forms):
+def matpc_only(L, forms, mrhs_forms=()):
     import tempfile
 
     import numpy as np
@@ -128,7 +132,24 @@ def matpc_only(L, forms):
     xe = torch.from_numpy(li.z2_source(L, 1000).reshape(-1, 4, 3)[:Vh].copy()).cuda()
     out = torch.empty_like(xe)
     runs = []
-    for f in forms or [None]:
+    if mrhs_forms:
+        xs = torch.from_numpy(np.stack([li.z2_source(L, 1000 + k).reshape(-1, 4, 3)[:Vh] for k in range(12)])).cuda()
+        outs = torch.empty_like(xs)
+        for v in mrhs_forms:
+            path = os.path.join(tempfile.gettempdir(), f"qcdw_mrhs_form_{v}.txt")
+            with open(path, "w") as fh:
+                fh.write(f"mrhs_hop/p2/L{L[0]}x{L[1]}x{L[2]}x{L[3]}/n12 {v}\n")
+            os.environ["QCDW_TUNE_CACHE"] = path
+            ctx = q.Context(0)
+            op = q.Operator(ctx, q.make_lattice(L), U, 0.125, 1.1, "bf16", 12)
+            for _ in range(3):
+                q.qcdw_op_matpc_multi(op, "bf16", xs, outs)
+            torch.cuda.synchronize()
+            runs.append({"mrhs_form": v})
+            op.close()
+            ctx.close()
+        forms = []
+    for f in forms or ([] if mrhs_forms else [None]):
         if f is not None:  # a fresh context reads the tuning file that fixes the form
             nt, cg, fma = (tuple(f) + (0,))[:3]
             path = os.path.join(tempfile.gettempdir(), f"qcdw_form_{nt}_{cg}_{fma}.txt")
@@ -235,7 +256,8 @@ def main():
         return
     if args.matpc_only:
         forms = [tuple(int(x) for x in f.split(":")) for f in args.forms.split(",") if f]
-        matpc_only([int(v) for v in args.matpc_only.split(",")], forms)
+        mrhs = [int(v) for v in args.mrhs_forms.split(",") if v]
+        matpc_only([int(v) for v in args.matpc_only.split(",")], forms, mrhs)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -600,6 +622,7 @@ def propagator(q, li, np, torch, ctx, fields, args):
     ti = q.qcdw_invert_multi(op, bs, xt, pt)[0]
     ms = ti.hop_ms[0] / max(ti.n_hop[0], 1)
     gbs = hop_a_bytes_multi("bf16", 12) * Vh / (ms * 1e-3) / 1e9
+    form = q.qcdw_ctx_tuned(ctx, f"mrhs_hop/p{q.QCDW_BF16}/L{L[0]}x{L[1]}x{L[2]}x{L[3]}/n12")
     op.close()
     del bs, x, x64, xt
     torch.cuda.empty_cache()
@@ -610,7 +633,8 @@ def propagator(q, li, np, torch, ctx, fields, args):
             "speedup": round(t_sep / t_multi, 3), "speedup_vs_separate_bf16": round(t_sep_lo / t_multi, 3),
             "rel_diff_multi_vs_f64": diff,
             "multi_hop": {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "avg_launch_us": round(ms * 1e3, 1), "bytes_per_site_12rhs": hop_a_bytes_multi("bf16", 12)},
+                          "avg_launch_us": round(ms * 1e3, 1), "bytes_per_site_12rhs": hop_a_bytes_multi("bf16", 12),
+                          "form": form, "matrix_cores": bool(form is not None and form & 1024)},
             "pion_2pt": {"call_ms": round(1e3 * t_con, 3),
                          "gbs_incl_call": round(12 * 192 * 2 * Vh / t_con / 1e9, 1),
                          "c_t0": float(pion[0].real), "c_t_mid": float(pion[L[3] // 2].real),

@@ -133,6 +133,13 @@ qcdw_status qcdw_ctx_create(qcdw_ctx **ctx, int device, void *hip_stream);
 void qcdw_ctx_destroy(qcdw_ctx *ctx);
 const char *qcdw_last_error(const qcdw_ctx *ctx);
 qcdw_status qcdw_ctx_set_stream(qcdw_ctx *ctx, void *hip_stream);
+/* The kernel form the context has chosen by timing (or read from the tuning file named by
+   $QCDW_TUNE_CACHE) for a tuning key, e.g. "mrhs_hop/p2/L24x24x24x64/n12" (multi-RHS hop, BF16
+   storage, 12 RHS: 0 register loop, 1 one block per RHS, 2 g the register loop in slice groups of g
+   c-tiles, plus 1024 for its matrix-core form) or "hop_nt/p0/L24x24x24x64" (single-RHS hop: nt +
+   16 cgroup + 4096 fma).  key: NUL-terminated host string; *value written on success.  QCDW_EINVAL
+   if the key has no entry (nothing tuned for that shape yet). */
+qcdw_status qcdw_ctx_tuned(const qcdw_ctx *ctx, const char *key, int *value);
 
 /* Multi-shift CG on the normal even-odd operator (the solves of a rational approximation in RHMC,
    paper Sec. IV; the shifted solver reuses the hot path): (M_hat^+ M_hat + shifts[i]) x_i = b for

@@ -35,6 +35,7 @@ PREC = {"f64": QCDW_F64, "f32": QCDW_F32, "bf16": QCDW_BF16, "f16": QCDW_F16}
 # every symbol declared in include/qcdw.h
 EXPORTED = (
     "qcdw_solver_params_default", "qcdw_ctx_create", "qcdw_ctx_destroy", "qcdw_last_error", "qcdw_ctx_set_stream",
+    "qcdw_ctx_tuned",
     "qcdw_clover_build", "qcdw_clover_apply", "qcdw_clover_invert", "qcdw_hop", "qcdw_dslash", "qcdw_dslash_noalloc",
     "qcdw_op_create",
     "qcdw_op_create_aniso", "qcdw_op_destroy", "qcdw_op_hop_form", "qcdw_op_matpc", "qcdw_op_matpc_multi", "qcdw_invert", "qcdw_invert_multi",
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "qcdw_ctx_destroy": (None, [p]),
         "qcdw_last_error": (ctypes.c_char_p, [p]),
         "qcdw_ctx_set_stream": (i, [p, p]),
+        "qcdw_ctx_tuned": (i, [p, ctypes.c_char_p, ctypes.POINTER(i)]),
         "qcdw_clover_build": (i, [p, lat, p, p]),
         "qcdw_clover_apply": (i, [p, lat, p, p, p, d, d]),
         "qcdw_clover_invert": (i, [p, lat, p, d, d, p]),
@@ -473,6 +475,13 @@ def make_params(tol=1e-10, maxiter=10000, inner="f64", delta=0.1, check_every=8,
     prm.gmres_fallback = 1 if gmres_fallback else 0
     prm.inner_resume = 1 if inner_resume else 0
     return prm
+
+
+def qcdw_ctx_tuned(ctx: Context, key: str):
+    """The tuned kernel form of a tuning key (see include/qcdw.h), or None if nothing is tuned for it."""
+    v = ctypes.c_int()
+    st = load_library().qcdw_ctx_tuned(ctx.handle, key.encode(), ctypes.byref(v))
+    return v.value if st == QCDW_OK else None
 
 
 def qcdw_op_hop_form(op: Operator, prec: str = "f64"):

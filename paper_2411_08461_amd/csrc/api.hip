@@ -6,6 +6,39 @@
 
 #include "host.h"
 
+namespace {
+
+// multi-RHS hop forms (tuning-cache value of "mrhs_hop/..."): bit 0 set: one block per (tile, RHS), links
+// re-read from L2; else the register loop, in slice-group order of (v & 1023) / 2 c-tiles when nonzero, on
+// the matrix cores when MRHS_MFMA is set (16-bit storage)
+constexpr int MRHS_MFMA = 1024;
+
+bool mrhs_variant_fits(const qcdw::Geom& g, int prec, int v)
+{
+    if (v == 1) return true;
+    if ((v & 1) || (v & ~(MRHS_MFMA | 1023))) return false;
+    if ((v & MRHS_MFMA) && prec != qcdw::BF16 && prec != qcdw::F16) return false;
+    const int cg = (v & 1023) >> 1;
+    return cg == 0 || hop_cgroup_fits(g, cg);
+}
+
+int mrhs_blocks(const qcdw::Geom& g, int v)
+{
+    const int cg = (v & 1) ? 0 : (v & 1023) >> 1;
+    return cg > 0 ? hop_ctiles(g) * g.Lt : hop_blocks(g.Vh);
+}
+
+hipError_t launch_mrhs_variant(hipStream_t st, int prec, int epi, int red, qcdw::HopArgs a, const qcdw::Scal* S,
+                               int v, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    a.cgroup = (v & 1) ? 0 : (v & 1023) >> 1;
+    if (v & 1) return qcdw::launch_hop_rhs(st, prec, epi, red, a, S, e0, e1);
+    if (v & MRHS_MFMA) return qcdw::launch_hop_mrhs_mfma(st, prec, epi, red, a, S, e0, e1);
+    return qcdw::launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
+}
+
+}  // namespace
+
 extern "C" {
 
 void qcdw_solver_params_default(qcdw_solver_params* p)
@@ -71,6 +104,15 @@ qcdw_status qcdw_ctx_set_stream(qcdw_ctx* ctx, void* hip_stream)
 {
     if (!ctx) return QCDW_EINVAL;
     ctx->stream = (hipStream_t)hip_stream;
+    return QCDW_OK;
+}
+
+qcdw_status qcdw_ctx_tuned(const qcdw_ctx* ctx, const char* key, int* value)
+{
+    if (!ctx || !key || !value) return QCDW_EINVAL;
+    const auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end()) return QCDW_EINVAL;
+    *value = it->second;
     return QCDW_OK;
 }
 
@@ -509,13 +551,19 @@ qcdw_status qcdw_op_matpc_multi(qcdw_op* op, qcdw_prec prec, int nrhs, const voi
     for (int k = 0; k < nrhs; k++)
         HIPCHK(ctx, launch_pack_spinor(s, prec, g, (const char*)in_e + k * half, 0,
                                        (char*)in.p + (size_t)k * n * cplx_bytes(prec), 1.0));
+    // the kernel form cached for this shape by a multi-RHS solve (or a tuning file), else the register loop
+    int form = 0;
+    char key[96];
+    snprintf(key, sizeof key, "mrhs_hop/p%d/L%dx%dx%dx%d/n%d", (int)prec, g.Lx, g.Ly, g.Lz, g.Lt, nrhs);
+    const auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end() && mrhs_variant_fits(g, prec, it->second)) form = it->second;
     HopArgs a = hop_args(g, 1);
     a.psi = in.p;
     a.out = tmp.p;
     a.gauge = v.gauge;
     a.clov = v.Ainv[1];
     a.nrhs = nrhs;
-    HIPCHK(ctx, launch_hop_mrhs(s, prec, EPI_CLOV, RED_NONE, a, nullptr));
+    HIPCHK(ctx, launch_mrhs_variant(s, prec, EPI_CLOV, RED_NONE, a, nullptr, form));
     HopArgs b2 = hop_args(g, 0);
     b2.psi = tmp.p;
     b2.out = out.p;
@@ -524,7 +572,7 @@ qcdw_status qcdw_op_matpc_multi(qcdw_op* op, qcdw_prec prec, int nrhs, const voi
     b2.y = in.p;
     b2.a = op->kappa * op->kappa;
     b2.nrhs = nrhs;
-    HIPCHK(ctx, launch_hop_mrhs(s, prec, EPI_CLOV_XPAY, RED_NONE, b2, nullptr));
+    HIPCHK(ctx, launch_mrhs_variant(s, prec, EPI_CLOV_XPAY, RED_NONE, b2, nullptr, form));
     for (int k = 0; k < nrhs; k++)
         HIPCHK(ctx, launch_unpack_spinor(s, prec, g, (const char*)out.p + (size_t)k * n * cplx_bytes(prec), 0,
                                          (char*)out_e + k * half, 1.0));
@@ -597,8 +645,8 @@ struct Solver {
     int nb_blas;                 // BLAS partials per problem
     const long2* map;            // device (off, len) per problem (batch) or nullptr (uniform)
     const int* nbs;              // device hop tiles per problem (batch) or nullptr
-    int variant = 0;             // multi-RHS kernel form (0 register loop, 1 L2 reuse), batch grid, or
-                                 // single-RHS sites per thread along t
+    int variant = 0;             // multi-RHS kernel form (mrhs_variant_fits), batch grid, or the single-RHS
+                                 // hop form
     int nt = 1, cg = 0, fma = 0;  // single-RHS hop: sites per thread along t, c-tile group, arithmetic form
     int fuse_nb;                 // largest partials count (all problems of a launch) whose scalars are
                                  // formed in the vector kernels
@@ -683,11 +731,7 @@ struct Solver {
         // the reduction partials of this form must fit the workspace sized for nb_hop_cap
         if (red != RED_NONE && nprob == 1 && hop_blocks_nt(op->g, a.nt, a.cgroup) > nb_hop_cap)
             return hipErrorInvalidValue;
-        if (nprob > 1) {  // variant: kernel form (bit 0: 0 register loop, 1 L2 reuse) + 2 * c-tile group
-            a.cgroup = (variant & 1) ? 0 : variant >> 1;
-            return (variant & 1) ? launch_hop_rhs(st, prec, epi, red, a, S, e0, e1)
-                                 : launch_hop_mrhs(st, prec, epi, red, a, S, e0, e1);
-        }
+        if (nprob > 1) return launch_mrhs_variant(st, prec, epi, red, a, S, variant, e0, e1);
         return launch_hop(st, prec, v.recon, epi, red, a, e0, e1);
     }
 
@@ -757,18 +801,22 @@ struct Solver {
                         if (std::find(cand.begin(), cand.end(), 2 * d) == cand.end()) cand.push_back(2 * d);
                         break;
                     }
+            if (kprec == BF16 || kprec == F16) {  // the matrix-core form, in both tile orders
+                const size_t n = cand.size();
+                for (size_t c = 0; c < n; c++)
+                    if ((cand[c] & 1) == 0) cand.push_back(MRHS_MFMA | cand[c]);
+            }
         }
         auto choose = [&](int v) {
             variant = v;
             // multi-RHS register loop in slice-group order: one block per (c-tile, t)
-            if (!batch && nprob > 1)
-                nb_hop = (v & 1) == 0 && (v >> 1) > 0 ? hop_ctiles(ops[0]->g) * ops[0]->g.Lt : hop_blocks(ops[0]->g.Vh);
+            if (!batch && nprob > 1) nb_hop = mrhs_blocks(ops[0]->g, v);
         };
         auto it = ctx->tune.find(key);
         if (it != ctx->tune.end()) {
             const int v = it->second;
             const bool fits = batch ? std::find(cand.begin(), cand.end(), v) != cand.end()
-                                    : (v == 0 || v == 1 || ((v & 1) == 0 && hop_cgroup_fits(ops[0]->g, v >> 1)));
+                                    : mrhs_variant_fits(ops[0]->g, kprec, v);
             if (fits) {
                 choose(v);
                 return QCDW_OK;

@@ -185,6 +185,10 @@ hipError_t launch_fin_beta(hipStream_t s, Scal* S, const double* partials, int n
 // partials [y][hop_blocks][3]
 hipError_t launch_hop_mrhs(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// the same with the link products on the matrix cores (BF16 / FP16 storage only; hipErrorInvalidValue
+// otherwise); same grid and partials as launch_hop_mrhs
+hipError_t launch_hop_mrhs_mfma(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S,
+                                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the same operation with one block per (tile, rhs), rhs fastest (links and clover re-read from L2)
 hipError_t launch_hop_rhs(hipStream_t s, int prec, int epi, int red, const HopArgs& a, const Scal* S,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

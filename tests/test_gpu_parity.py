@@ -665,14 +665,15 @@ def test_mixed_solve_resuming_the_recurrence(ctx, inner):
     op.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 4, 1024, 1028])
 def test_multi_rhs_forms(tmp_path, monkeypatch, variant):
     """Lockstep multi-RHS solves with each hop form forced through the tuning cache (register loop,
-    L2-reuse per RHS, register loop in slice-group order with groups of 1 or 2 c-tiles) reach an
-    oracle-checked true residual <= 1e-10 for every RHS, in FP64 and BF16-mixed."""
+    L2-reuse per RHS, register loop in slice-group order with groups of 1 or 2 c-tiles, and the
+    matrix-core form of the BF16 hop in both tile orders) reach an oracle-checked true residual <= 1e-10
+    for every RHS, in FP64 and BF16-mixed, the BF16-mixed ones without falling back to FP64."""
     for L in ((8, 8, 8, 16), (6, 4, 2, 8)):
         nct = (L[0] // 2 * L[1] * L[2] + 63) // 64
-        if (variant & 1) == 0 and nct % max(variant >> 1, 1):
+        if (variant & 1) == 0 and nct % max((variant & 1023) >> 1, 1):
             continue
         nrhs = 3
         cache = tmp_path / f"tune_mrhs_{variant}_{L[0]}.txt"
@@ -689,11 +690,62 @@ def test_multi_rhs_forms(tmp_path, monkeypatch, variant):
             xh = host(x)
             for k in range(nrhs):
                 assert infos[k].status == q.QCDW_OK, (L, inner, k, infos[k])
+                assert infos[k].fallback == 0, (L, inner, k, infos[k])
                 assert _oracle_true_res(L, U, xh[k], bs[k], kappa, csw) <= 1e-10
         op.close()
         torch.cuda.synchronize()
         c.close()
         assert f" {variant}" in cache.read_text()
+
+
+@pytest.mark.parametrize("L,t_bc,cg", [((6, 4, 2, 6), 1, 0), ((10, 6, 4, 6), -1, 0), ((8, 8, 8, 16), -1, 2)])
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("aniso", [False, True])
+def test_matpc_multi_mfma_form(tmp_path, monkeypatch, L, t_bc, cg, prec, aniso):
+    """The matrix-core multi-RHS hop (forced through the tuning cache, plain and slice-group tile order)
+    gives M_hat within the storage rounding of the oracle for every RHS (the single-RHS bounds), and
+    agrees with the vector register loop to the same rounding; lattices with ragged tiles, both time
+    boundaries, and the anisotropic weights with antiperiodic time."""
+    nrhs = 12
+    key = f"mrhs_hop/p{q.PREC[prec]}/L{L[0]}x{L[1]}x{L[2]}x{L[3]}/n{nrhs}"
+    cache = tmp_path / "tune_mfma.txt"
+    cache.write_text(f"{key} {1024 + 2 * cg}\n")
+    monkeypatch.setenv("QCDW_TUNE_CACHE", str(cache))
+    c_mfma = q.Context(0)
+    monkeypatch.delenv("QCDW_TUNE_CACHE")
+    c_vec = q.Context(0)
+    U = _gauge(L, 0.3, 61)
+    Vh = int(np.prod(L)) // 2
+    xs = np.stack([li.gaussian_source(L, 62 + k).reshape(-1, 4, 3)[:Vh] for k in range(nrhs)])
+    if aniso:
+        xi0, nu, ct, cr = 2.464, 0.95, 0.91, 1.07
+        kappa, csw, kw = oracle.aniso_kappa(0.3, xi0, nu), 0.0, dict(aniso=(xi0, nu, ct, cr))
+        C = oracle.clover_build(L, U, plane_weights=(ct, cr / xi0))
+        Ainv, _ = oracle.clover_invert(L, C, kappa, 1.0)
+        weights = oracle.aniso_weights(xi0, nu)
+    else:
+        kappa, csw, kw = 0.124, 1.0, {}
+        Ainv, _ = oracle.clover_invert(L, oracle.clover_build(L, U), kappa, csw)
+        weights = None
+    outs = []
+    for c in (c_mfma, c_vec):
+        op = q.Operator(c, q.make_lattice(L, t_bc), dev(U), kappa, csw, prec, 12, **kw)
+        out = torch.empty(xs.shape, dtype=torch.complex128, device="cuda")
+        q.qcdw_op_matpc_multi(op, prec, dev(xs), out)
+        outs.append(host(out))
+        op.close()
+    bound = {"bf16": 2e-2, "f16": 4e-3}[prec]
+    for k in range(nrhs):
+        if weights is None:
+            expect = oracle.schur_matpc(L, U, Ainv, xs[k], kappa, t_bc)
+        else:
+            expect = oracle.schur_matpc(L, U, Ainv, xs[k], kappa, t_bc, weights=weights)
+        err = np.linalg.norm(outs[0][k] - expect) / np.linalg.norm(expect)
+        assert err < bound, (k, err)
+        assert np.linalg.norm(outs[0][k] - outs[1][k]) / np.linalg.norm(outs[1][k]) < bound / 2, k
+    torch.cuda.synchronize()
+    c_mfma.close()
+    c_vec.close()
 
 
 @pytest.mark.parametrize("inner", ["f64", "bf16"])
