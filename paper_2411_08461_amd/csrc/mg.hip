@@ -328,36 +328,51 @@ __global__ __launch_bounds__(256) void k_mg_coarse_build(MgDev m, const double2*
 // ---------------------------------------------------------------------------
 // restriction, prolongation, coarse operator
 // ---------------------------------------------------------------------------
-// out[cs][chi][k] = sum over the block's sites of parity p < np and the spins of chi of conj(W_k) f,
-// f = (f0, f1) internal fields of the two parities (f1 unused when np = 1).  One block per coarse site,
-// wave w handles the vectors k = w, w + 4, ..; lanes stride over the contiguous run of W_k.
+// out[cs][chi][k] = sum over the block's sites of parity p < np and the spins of chi of conj(W_k) f, for
+// f = (f0, f1) internal fields of the two parities (f1 unused when np = 1).  Block (cs, kb): wave w handles
+// vector k = 4 kb + w, its lanes stride over the contiguous run of W_k in chunks of 16 sites x 12 components
+// (lane l takes components l, l + 64, l + 128 of each chunk: fixed (site offset, spin-colour) pairs, so the
+// loop has no divisions).
 template <class PW, class PF>
 __global__ __launch_bounds__(256) void k_mg_restrict(MgDev m, const void* W, const void* f0, const void* f1, int np,
                                                       double2* out)
 {
-    const int cs = blockIdx.x;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int len = np * m.hb * 12;
-    for (int k = wv; k < m.N; k += 4) {
-        double a[4] = {0.0, 0.0, 0.0, 0.0};  // (re, im) for chirality 0, then 1
-        const long wb = w_index(m, cs, k, 0, 0);
-        for (int e = lane; e < len; e += 64) {
-            const int p = e / (m.hb * 12), rem = e - p * m.hb * 12;
-            const int j = rem / 12, sc = rem % 12;
-            const int site = m.blk_sites[((long)cs * 2 + p) * m.hb + j];
-            const auto wk = PW::ld(W, wb + e);
-            const auto fv = PF::ld(p == 0 ? f0 : f1, sp_idx(sc / 3, site, sc % 3, m.g.Vh));
-            const double wr = wk.re, wi = wk.im, fr = fv.re, fi = fv.im;
-            const int h = sc < 6 ? 0 : 2;
-            a[h] += wr * fr + wi * fi;
-            a[h + 1] += wr * fi - wi * fr;
-        }
+    const int kb = blockIdx.x % ((m.N + 3) / 4), cs = blockIdx.x / ((m.N + 3) / 4);
+    const int lane = threadIdx.x & 63;
+    const int k = 4 * kb + (threadIdx.x >> 6);
+    if (k >= m.N) return;  // whole waves
+    int dj[3], sc[3];
 #pragma unroll
-        for (int q = 0; q < 4; q++) a[q] = wave_sum(a[q]);
-        if (lane == 0) {
-            out[((long)cs * 2 + 0) * m.N + k] = make_double2(a[0], a[1]);
-            out[((long)cs * 2 + 1) * m.N + k] = make_double2(a[2], a[3]);
+    for (int i = 0; i < 3; i++) {
+        dj[i] = (lane + 64 * i) / 12;
+        sc[i] = (lane + 64 * i) % 12;
+    }
+    double a[4] = {0.0, 0.0, 0.0, 0.0};  // (re, im) for chirality 0, then 1
+    for (int p = 0; p < np; p++) {
+        const void* f = p == 0 ? f0 : f1;
+        const long wb = w_index(m, cs, k, p, 0);
+        const int* sites = m.blk_sites + ((long)cs * 2 + p) * m.hb;
+        for (int j0 = 0; j0 < m.hb; j0 += 16) {
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const int j = j0 + dj[i];
+                if (j < m.hb) {
+                    const int site = sites[j];
+                    const auto wk = PW::ld(W, wb + (long)j * 12 + sc[i]);
+                    const auto fv = PF::ld(f, sp_idx(sc[i] / 3, site, sc[i] % 3, m.g.Vh));
+                    const double wr = wk.re, wi = wk.im, fr = fv.re, fi = fv.im;
+                    const int h = sc[i] < 6 ? 0 : 2;
+                    a[h] += wr * fr + wi * fi;
+                    a[h + 1] += wr * fi - wi * fr;
+                }
+            }
         }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) a[q] = wave_sum(a[q]);
+    if (lane == 0) {
+        out[((long)cs * 2 + 0) * m.N + k] = make_double2(a[0], a[1]);
+        out[((long)cs * 2 + 1) * m.N + k] = make_double2(a[2], a[3]);
     }
 }
 
@@ -391,8 +406,10 @@ __global__ __launch_bounds__(256) void k_mg_prolong(MgDev m, const void* W, cons
     }
 }
 
-// out = D_c in, one thread per (coarse site, row); red = RED_WDOT: partials of (w, out); RED_TS: partials
-// of (out, y) and ||out||^2; nothing when *stop != 0 (the solve has finished)
+// out = D_c in, one block per coarse site: thread items (stencil entry d, row) form the partial sums over the
+// columns of entry d (consecutive threads read consecutive rows of a column), which are then summed over d in
+// a fixed order; red = RED_WDOT: partials of (w, out); RED_TS: partials of (out, y) and ||out||^2 (one
+// partial per coarse site); nothing when *stop != 0 (the solve has finished)
 // (PY: storage of the stencil, P: of the vectors)
 template <class PY, class P, int RED>
 __global__ __launch_bounds__(256) void k_mg_coarse_apply(MgDev m, const void* Yt, const void* in, void* out,
@@ -400,22 +417,30 @@ __global__ __launch_bounds__(256) void k_mg_coarse_apply(MgDev m, const void* Yt
 {
     if (stop && *stop) return;
     using T = typename P::real;
-    const int nc = m.nc;
-    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
-    const int cs = (int)(tid / nc), row = (int)(tid - (long)cs * nc);
-    const bool valid = cs < m.Vc;
+    __shared__ cx<T> part[9][2 * MG_MAX_N];
+    const int nc = m.nc, cs = blockIdx.x;
+    const long ne = (long)nc * nc;
+    for (int it = threadIdx.x; it < 9 * nc; it += 256) {
+        const int d = it / nc, row = it - d * nc;
+        const int nb = d == 0 ? cs : m.cnbr[(long)cs * 8 + (d - 1)];
+        const long yb = ((long)cs * 9 + d) * ne + row;
+        const long ib = (long)nb * nc;
+        cx<T> acc = {T(0), T(0)};
+        for (int col = 0; col < nc; col++) {
+            const auto yv = PY::ld(Yt, yb + (long)col * nc);
+            cmac(acc, cx<T>{(T)yv.re, (T)yv.im}, P::ld(in, ib + col));
+        }
+        part[d][row] = acc;
+    }
+    __syncthreads();
+    const int row = threadIdx.x;
+    const bool valid = row < nc;
+    const long tid = (long)cs * nc + row;
     cx<T> acc = {T(0), T(0)};
     if (valid) {
-        const long ne = (long)nc * nc;
-        for (int d = 0; d < 9; d++) {
-            const int nb = d == 0 ? cs : m.cnbr[(long)cs * 8 + (d - 1)];
-            const long yb = ((long)cs * 9 + d) * ne + row;
-            const long ib = (long)nb * nc;
-            for (int col = 0; col < nc; col++) {
-                const auto yv = PY::ld(Yt, yb + (long)col * nc);
-                cmac(acc, cx<T>{(T)yv.re, (T)yv.im}, P::ld(in, ib + col));
-            }
-        }
+        acc = part[0][row];
+#pragma unroll
+        for (int d = 1; d < 9; d++) acc = acc + part[d][row];
         P::st(out, tid, acc);
     }
     if constexpr (RED != RED_NONE) {
@@ -631,7 +656,8 @@ qcdw_status mg_precondition(qcdw_mg* mg, qcdw_op* op, const void* v, void* z)
     const long n = 12L * m.g.Vh;
     // coarse right-hand side P^+ (A_ee v) on the even sites
     HIPCHK(ctx, launch_clov_apply_internal(s, F64, m.g, op->A64[0].p, v, mg->t64.p));
-    hipLaunchKernelGGL((k_mg_restrict<P32, P64>), dim3(m.Vc), dim3(256), 0, s, m, mg->W32.p, mg->t64.p, nullptr, 1,
+    hipLaunchKernelGGL((k_mg_restrict<P32, P64>), dim3(m.Vc * ((m.N + 3) / 4)), dim3(256), 0, s, m, mg->W32.p,
+                       mg->t64.p, nullptr, 1,
                        (double2*)mg->rc.p);
     HIPCHK(ctx, hipGetLastError());
     // coarse BiCGStab on the normalised right-hand side, FP32 vectors, scalars on the device
@@ -816,7 +842,7 @@ extern "C" qcdw_status qcdw_mg_create(qcdw_op* op, const qcdw_mg_params* params,
     CHK(mg_build_coarse(mg.get(), op));
     // solve workspace
     mg->n_c = (long)m.Vc * m.nc;
-    mg->nb_apply = (int)((mg->n_c + 255) / 256);
+    mg->nb_apply = m.Vc;  // one block (and one reduction partial) per coarse site
     mg->nb_blas = blas_blocks(mg->n_c);
     const long nfe = 12L * g.Vh;
     mg->nb_fine = blas_blocks(nfe);
@@ -878,7 +904,7 @@ extern "C" qcdw_status qcdw_mg_restrict(qcdw_mg* mg, const void* fine, void* coa
     HIPCHK(ctx, f.alloc(2 * vb));
     HIPCHK(ctx, launch_pack_spinor(s, F64, m.g, fine, 0, f.p, 1.0));
     HIPCHK(ctx, launch_pack_spinor(s, F64, m.g, fine, 1, (char*)f.p + vb, 1.0));
-    hipLaunchKernelGGL((k_mg_restrict<P64, P64>), dim3(m.Vc), dim3(256), 0, s, m, mg->W64.p, f.p,
+    hipLaunchKernelGGL((k_mg_restrict<P64, P64>), dim3(m.Vc * ((m.N + 3) / 4)), dim3(256), 0, s, m, mg->W64.p, f.p,
                        (const char*)f.p + vb, 2, (double2*)coarse);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
