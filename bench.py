@@ -188,7 +188,7 @@ def net_only(L):
     xe = torch.from_numpy(li.gaussian_source(L, 1000).reshape(-1, 4, 3)[:Vh].copy()).cuda()
     out = torch.empty_like(xe)
     runs = []
-    for mfma in (0, 1):  # a fresh context reads the tuning file that fixes the layer kind
+    for mfma in (0, 3):  # a fresh context reads the tuning file that fixes the layer kinds (3: both on MFMA)
         path = os.path.join(tempfile.gettempdir(), f"qcdw_net_mfma_{mfma}.txt")
         with open(path, "w") as fh:
             fh.write(f"net_mfma/h12/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {mfma}\n")

@@ -21,7 +21,7 @@ struct qcdw_net {
     PoolBuf diff, tmp64, partials, res;
     int adam_step = 0;
     bool bf_dirty = true;
-    int mfma = 0;  // BF16 application layers on the matrix cores (chosen by timing at creation)
+    int mfma = 0;  // BF16 application layers on the matrix cores: bit 0 the first, bit 1 the second (timed)
 };
 
 namespace {
@@ -74,9 +74,9 @@ qcdw_status net_forward_internal(qcdw_net* net, int prec, const void* in_int, vo
     if (prec == BF16) {
         CHK(net_refresh_bf16(net));
         HIPCHK(ctx, launch_net_layer(s, F32, BF16, 4, h, net->act0.p, net->hid16.p, net->gauge32.p, net->W1bf.p, g,
-                                     net->mfma));
+                                     net->mfma & 1));
         HIPCHK(ctx, launch_net_layer(s, BF16, F32, h, 4, net->hid16.p, net->z.p, net->gauge32.p, net->W2bf.p, g,
-                                     net->mfma));
+                                     (net->mfma >> 1) & 1));
     } else {
         HIPCHK(ctx, launch_net_layer(s, F32, F32, 4, h, net->act0.p, net->hid.p, net->gauge32.p, net->W1.p, g));
         HIPCHK(ctx, launch_net_layer(s, F32, F32, h, 4, net->hid.p, net->z.p, net->gauge32.p, net->W2.p, g));
@@ -85,9 +85,10 @@ qcdw_status net_forward_internal(qcdw_net* net, int prec, const void* in_int, vo
     return QCDW_OK;
 }
 
-// Layer kernels of the BF16 application: channel mixing on the matrix cores or on vector FMA, whichever
-// is faster on this lattice (timed on zero fields; cached per lattice and width on the context and in
-// the tuning file as "net_mfma/h<hidden>/L<Lx>x<Ly>x<Lz>x<Lt> 0|1").
+// Layer kernels of the BF16 application: each layer's channel mixing on the matrix cores or on vector FMA,
+// whichever pair is fastest on this lattice (timed on zero fields; cached per lattice and width on the
+// context and in the tuning file as "net_mfma/h<hidden>/L<Lx>x<Ly>x<Lz>x<Lt> m", bit 0 of m the first
+// layer on the matrix cores, bit 1 the second).
 qcdw_status net_tune_layers(qcdw_net* net)
 {
     qcdw_ctx* ctx = net->ctx;
@@ -95,7 +96,7 @@ qcdw_status net_tune_layers(qcdw_net* net)
     char key[96];
     snprintf(key, sizeof key, "net_mfma/h%d/L%dx%dx%dx%d", net->hidden, g.Lx, g.Ly, g.Lz, g.Lt);
     auto it = ctx->tune.find(key);
-    if (it != ctx->tune.end() && (it->second == 0 || it->second == 1)) {
+    if (it != ctx->tune.end() && it->second >= 0 && it->second <= 3) {
         net->mfma = it->second;
         return QCDW_OK;
     }
@@ -108,7 +109,7 @@ qcdw_status net_tune_layers(qcdw_net* net)
     float best = 1e30f;
     int best_m = 0;
     qcdw_status st = QCDW_OK;
-    for (int m : {0, 1}) {
+    for (int m : {0, 1, 2, 3}) {
         net->mfma = m;
         st = net_forward_internal(net, BF16, net->tmp64.p, net->diff.p);  // warm-up
         hipError_t e = hipEventRecord(e0, s);

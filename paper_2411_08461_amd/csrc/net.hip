@@ -98,127 +98,218 @@ __device__ __forceinline__ void transport(const void* in, const void* gauge, con
 
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef __bf16 nb2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ short bf16_bits(float f) { return (short)f2bf_bits(f); }
+// two floats rounded to BF16 (nearest even) and packed low, high
+__device__ __forceinline__ uint32_t pk_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(nf2{lo, hi}, nb2));
+}
+__device__ __forceinline__ mfma_s4 s4_of(uint32_t lo, uint32_t hi) { return __builtin_bit_cast(mfma_s4, make_uint2(lo, hi)); }
 
-// The layer with its channel mixing on the matrix cores in BF16 (v_mfma_f32_16x16x16_bf16, FP32
-// accumulation): the application path of the preconditioner, whose weights are BF16 values.  For each
-// colour k the layer is the real product  OUT_k[site, n] = sum_kk A_k[site, kk] B[kk, n]:  rows are the
-// 16 sites of a wave, kk runs over (pair (a, c), re/im) with A the transported inputs (T_a phi_c)(site)_k
-// rounded to BF16, and n over (output channel d, re/im) with B the weights in real form
-// [[Re W, Im W], [-Im W, Re W]].  The instruction takes A[m][kk] from lane m + 16 (kk / 4), element
-// kk % 4, and B[kk][n] from lane n + 16 (kk / 4), element kk % 4 (16 kk per step), so each 16-lane group
-// q of a wave supplies 4 reals per step: two of its PG = 9 CIN / 4 pairs (channels q, q + 4, ... of
-// each hop, hop-major, padded to an even count with zero pairs) for its lane's site, and the matching
-// rows of B.  The result D[m][n] sits in lane n + 16 (m / 4), element m % 4.  A hop's link and
-// neighbour serve its CIN / 4 consecutive pairs.
+// The layers with their channel mixing on the matrix cores in BF16 (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation): the application path of the preconditioner.  For each colour k the mixing of hop a is the
+// real product  D[m][n] = sum_kk A[m][kk] B[kk][n]  with the weights as A (rows m = 2 d + re/im of output
+// channel d; K: kk = 2 c + re/im of input channel c; the real form [[Re W, -Im W], [Im W, Re W]]) and the
+// sites of a wave as the 16 columns n.  The instruction takes A[m][kk] from lane m + 16 (kk / 4) and B[kk][n]
+// from lane n + 16 (kk / 4), elements kk % 4, 16 kk per step, and leaves D[m][n] in lane n + 16 (m / 4),
+// element m % 4: lane L = n + 16 g supplies input channels 2 g, 2 g + 1 (+ 8 per step) of site n and
+// receives output channels 2 g, 2 g + 1 (+ 8 per row tile) of the same site, as whole complex numbers.
+// Two orders of the same sum, chosen by the cheaper transport: CIN <= COUT transports the CIN inputs first
+// (B = T_a phi, one accumulator over all hops); CIN > COUT mixes the neighbour's raw inputs first
+// (B = phi(x + a), the 16-bit inputs taken as they are stored) and transports the COUT mixed channels.
+
+// A operand of hop a, row tile t, K step s for this lane
+template <int CIN, int COUT>
+__device__ __forceinline__ mfma_s4 net_wop(const float2* __restrict__ W, int a, int t, int s, int lane)
+{
+    const int m = 16 * t + (lane & 15), d = m >> 1, rho = m & 1, grp = lane >> 4;
+    uint32_t v[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int c = 8 * s + 2 * grp + h;
+        float x = 0.f, y = 0.f;
+        if (d < COUT && c < CIN) {
+            const float2 w = W[((long)a * COUT + d) * CIN + c];
+            x = rho ? w.y : w.x;   // row re: (Re W, -Im W); row im: (Im W, Re W)
+            y = rho ? w.x : -w.y;
+        }
+        v[h] = pk_bf16(x, y);
+    }
+    return s4_of(v[0], v[1]);
+}
+
+// B operand dword of input channel c (colour k) of site (p, i): a 16-bit complex as stored, or FP32 rounded
+template <class PI>
+__device__ __forceinline__ uint32_t net_in_bits(const void* in, long idx)
+{
+    if constexpr (PI::cbytes == 4) {
+        return reinterpret_cast<const uint32_t*>(in)[idx];
+    } else {
+        const auto v = PI::ld(in, idx);
+        return pk_bf16((float)v.re, (float)v.im);
+    }
+}
+
+// W v with W = U (forward hop) or U^+ (backward hop)
+__device__ __forceinline__ void net_link_mul(const cx<float> (&u)[9], int back, const cx<float> (&v)[3],
+                                             cx<float> (&y)[3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        cx<float> sacc = {0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 3; k++) sacc = back == 0 ? sacc + u[3 * r + k] * v[k] : sacc + cmul_conj(u[3 * k + r], v[k]);
+        y[r] = sacc;
+    }
+}
+
 template <class PI, class PO, int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_net_layer_mfma(NetArgs n)
 {
-    constexpr int PG = 9 * CIN / 4;
-    constexpr int STEPS = (PG + 1) / 2;
-    constexpr int NTILE = (2 * COUT + 15) / 16;
-    static_assert(9 * CIN % 4 == 0, "pairs must split over the four lane groups");
+    constexpr int NT = (2 * COUT + 15) / 16;  // row tiles of the output channels
+    constexpr int NS = (2 * CIN + 15) / 16;   // K steps over the input channels
+    constexpr bool TFIRST = CIN <= COUT;
     const Geom g = n.g;
     const long Vh = g.Vh;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
+    // the weight operands of every (hop, row tile, K step) for the 64 lane positions, built once per block
+    __shared__ uint2 wop[9 * NT * NS][64];
+    for (int e = threadIdx.x; e < 9 * NT * NS * 64; e += 256) {
+        const int l = e & 63, q = e >> 6, s2 = q % NS, tl = (q / NS) % NT, a = q / (NS * NT);
+        wop[q][l] = __builtin_bit_cast(uint2, net_wop<CIN, COUT>(n.W, a, tl, s2, l));
+    }
+    __syncthreads();
     const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int row = lane & 15, grp = lane >> 4;
-    const long gsite = wave * 16 + row;  // this lane's A row: site over both parities
-    const bool valid = gsite < 2 * Vh;
+    const long gsite = wave * 16 + (lane & 15);
+    const bool valid = gsite < 2 * Vh;  // other lanes compute on site 0 and store nothing
     const int p = valid ? (int)(gsite / Vh) : 0, i = valid ? (int)(gsite % Vh) : 0;
     int x, y, z, t;
     site_coords(g, i, p, x, y, z, t);
-    mfma_f4 acc[3][NTILE];
-#pragma unroll
-    for (int k = 0; k < 3; k++)
-#pragma unroll
-        for (int tl = 0; tl < NTILE; tl++) acc[k][tl] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-    int cur_a = -1, nb = i;
-    cx<float> u[9];
-    for (int st = 0; st < STEPS; st++) {
-        mfma_s4 A[3], B[NTILE];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {  // the two pairs of this step
-            const int s2 = 2 * st + h;
-            const bool real_pair = s2 < PG;
-            // group q takes channels q, q + 4, ... of every hop, hop-major: all groups are on the
-            // same hop at each step, so link loads and the identity hop stay uniform over the wave
-            const int s2r = real_pair ? s2 : 0, a = s2r / (CIN / 4), c = grp + 4 * (s2r - a * (CIN / 4));
-            cx<float> Y[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-            if (valid && real_pair) {
-                const int mu = (a - 1) >> 1, back = (a - 1) & 1;
-                if (a != cur_a) {
-                    cur_a = a;
-                    if (a > 0) {
-                        nb = nbr_index(g, i, x, y, z, t, mu, back);
-                        su3_row3(n.gauge, mu, back == 0 ? p : 1 - p, back == 0 ? i : nb, Vh, u);
-                    }
-                }
-                if (a == 0) {
-#pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        const auto v = PI::ld(n.in, sp_idx((long)p * CIN + c, i, k, Vh));
-                        Y[k] = {(float)v.re, (float)v.im};
-                    }
-                } else {
-                    cx<float> v[3];
-#pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        const auto w = PI::ld(n.in, sp_idx((long)(1 - p) * CIN + c, nb, k, Vh));
-                        v[k] = {(float)w.re, (float)w.im};
-                    }
-#pragma unroll
-                    for (int r = 0; r < 3; r++) {
-                        cx<float> sacc = {0.f, 0.f};
-#pragma unroll
-                        for (int k = 0; k < 3; k++)
-                            sacc = back == 0 ? sacc + u[3 * r + k] * v[k] : sacc + cmul_conj(u[3 * k + r], v[k]);
-                        Y[r] = sacc;
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                A[k][2 * h] = bf16_bits(Y[k].re);
-                A[k][2 * h + 1] = bf16_bits(Y[k].im);
-            }
-            // B rows (pair, re) and (pair, im) for column (d, re/im) = lane & 15 + 16 tl
-#pragma unroll
-            for (int tl = 0; tl < NTILE; tl++) {
-                const int col = row + 16 * tl, d = col >> 1;
-                float bre = 0.f, bim = 0.f;
-                if (real_pair && d < COUT) {
-                    const float2 w = n.W[((long)a * COUT + d) * CIN + c];
-                    bre = (col & 1) ? w.y : w.x;
-                    bim = (col & 1) ? w.x : -w.y;
-                }
-                B[tl][2 * h] = bf16_bits(bre);
-                B[tl][2 * h + 1] = bf16_bits(bim);
-            }
-        }
+    using TO = typename PO::real;
+    if constexpr (TFIRST) {
+        mfma_f4 acc[3][NT];
 #pragma unroll
         for (int k = 0; k < 3; k++)
 #pragma unroll
-            for (int tl = 0; tl < NTILE; tl++)
-                acc[k][tl] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[k], B[tl], acc[k][tl], 0, 0, 0);
-    }
-    using TO = typename PO::real;
+            for (int tl = 0; tl < NT; tl++) acc[k][tl] = mfma_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = 0; k < 3; k++)
+        for (int a = 0; a < 9; a++) {
+            const int mu = (a - 1) >> 1, back = (a - 1) & 1;
+            const int j = a == 0 ? i : nbr_index(g, i, x, y, z, t, mu, back);
+            const int pj = a == 0 ? p : 1 - p;
+            cx<float> u[9];
+            const bool link = a > 0 && 2 * grp < CIN;
+            if (link) su3_row3(n.gauge, mu, back == 0 ? p : 1 - p, back == 0 ? i : j, Vh, u);
+            mfma_s4 B[NS][3];
 #pragma unroll
-        for (int tl = 0; tl < NTILE; tl++)
+            for (int s2 = 0; s2 < NS; s2++) {
+                const int c0 = 8 * s2 + 2 * grp;
+                uint32_t bw[2][3];
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const float v = acc[k][tl][e];
-                const float vp = __shfl_xor(v, 1, 64);  // the partner lane holds the other part
-                const int col = row + 16 * tl, d = col >> 1;
-                const long srow = wave * 16 + 4 * grp + e;
-                if ((col & 1) == 0 && d < COUT && srow < 2 * Vh) {
-                    const int pp = (int)(srow / Vh), ii = (int)(srow % Vh);
-                    PO::st(n.out, sp_idx((long)pp * COUT + d, ii, k, Vh), cx<TO>{(TO)v, (TO)vp});
+                for (int h = 0; h < 2; h++) {
+                    const int c = c0 + h;
+                    cx<float> v[3], yv[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+                    if (c < CIN) {  // (u is loaded only by lanes with input channels)
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            const auto w = PI::ld(n.in, sp_idx((long)pj * CIN + c, j, k, Vh));
+                            v[k] = {(float)w.re, (float)w.im};
+                        }
+                        if (a > 0)
+                            net_link_mul(u, back, v, yv);
+                        else
+#pragma unroll
+                            for (int k = 0; k < 3; k++) yv[k] = v[k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; k++) bw[h][k] = pk_bf16(yv[k].re, yv[k].im);
+                }
+#pragma unroll
+                for (int k = 0; k < 3; k++) B[s2][k] = s4_of(bw[0][k], bw[1][k]);
+            }
+#pragma unroll
+            for (int tl = 0; tl < NT; tl++)
+#pragma unroll
+                for (int s2 = 0; s2 < NS; s2++) {
+                    const mfma_s4 A = __builtin_bit_cast(mfma_s4, wop[(a * NT + tl) * NS + s2][lane]);
+#pragma unroll
+                    for (int k = 0; k < 3; k++)
+                        acc[k][tl] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[s2][k], acc[k][tl], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int tl = 0; tl < NT; tl++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int d = 8 * tl + 2 * grp + h;
+                if (valid && d < COUT) {
+#pragma unroll
+                    for (int k = 0; k < 3; k++)
+                        PO::st(n.out, sp_idx((long)p * COUT + d, i, k, Vh),
+                               cx<TO>{(TO)acc[k][tl][2 * h], (TO)acc[k][tl][2 * h + 1]});
                 }
             }
+    } else {
+        static_assert(NT == 1, "the mix-first order keeps one row tile");
+        cx<float> o[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) o[h][k] = {0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            const int mu = (a - 1) >> 1, back = (a - 1) & 1;
+            const int j = a == 0 ? i : nbr_index(g, i, x, y, z, t, mu, back);
+            const int pj = a == 0 ? p : 1 - p;
+            cx<float> u[9];
+            if (a > 0 && 2 * grp < COUT) su3_row3(n.gauge, mu, back == 0 ? p : 1 - p, back == 0 ? i : j, Vh, u);
+            mfma_f4 acc[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc[k] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s2 = 0; s2 < NS; s2++) {
+                const int c0 = 8 * s2 + 2 * grp;
+                mfma_s4 B[3];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const uint32_t b0 = c0 < CIN ? net_in_bits<PI>(n.in, sp_idx((long)pj * CIN + c0, j, k, Vh)) : 0u;
+                    const uint32_t b1 =
+                        c0 + 1 < CIN ? net_in_bits<PI>(n.in, sp_idx((long)pj * CIN + c0 + 1, j, k, Vh)) : 0u;
+                    B[k] = s4_of(b0, b1);
+                }
+                const mfma_s4 A = __builtin_bit_cast(mfma_s4, wop[a * NS + s2][lane]);
+#pragma unroll
+                for (int k = 0; k < 3; k++) acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[k], acc[k], 0, 0, 0);
+            }
+            // this lane's mixed channels d = 2 grp + h of the neighbour, then their transport
+            if (2 * grp < COUT) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    cx<float> v[3], yv[3];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) v[k] = {acc[k][2 * h], acc[k][2 * h + 1]};
+                    if (a > 0)
+                        net_link_mul(u, back, v, yv);
+                    else
+#pragma unroll
+                        for (int k = 0; k < 3; k++) yv[k] = v[k];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) o[h][k] = o[h][k] + yv[k];
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int d = 2 * grp + h;
+            if (valid && d < COUT) {
+#pragma unroll
+                for (int k = 0; k < 3; k++)
+                    PO::st(n.out, sp_idx((long)p * COUT + d, i, k, Vh), cx<TO>{(TO)o[h][k].re, (TO)o[h][k].im});
+            }
+        }
+    }
 }
 
 template <class PI, class PO, int CIN, int COUT>

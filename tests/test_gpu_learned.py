@@ -39,12 +39,13 @@ def _setup(ctx, L, seed=0, kappa=0.12, init_scale=0.3, hidden=12):
     return U, op, net
 
 
-@pytest.mark.parametrize("mfma", [0, 1])
+@pytest.mark.parametrize("mfma", [0, 1, 2, 3])
 @pytest.mark.parametrize("L,hidden", [((6, 4, 2, 6), 12), ((8, 4, 4, 8), 12), ((6, 4, 4, 6), 4), ((10, 6, 2, 4), 12)])
 def test_net_forward_matches_oracle(tmp_path, monkeypatch, L, hidden, mfma):
-    """FP32 application and BF16 application against the FP64 oracle, with the BF16 layers' channel
-    mixing forced (through the tuning cache) onto vector FMA or onto the BF16 matrix cores; the
-    10x6x2x4 lattice leaves a ragged last wave of 16 sites."""
+    """FP32 application and BF16 application against the FP64 oracle, with each BF16 layer's channel
+    mixing forced (through the tuning cache) onto vector FMA or onto the BF16 matrix cores (bit 0 the
+    first layer, which transports its inputs first, bit 1 the second, which mixes first when it narrows
+    the channels); the 10x6x2x4 lattice leaves a ragged last wave of 16 sites."""
     cache = tmp_path / "tune.txt"
     cache.write_text(f"net_mfma/h{hidden}/L{L[0]}x{L[1]}x{L[2]}x{L[3]} {mfma}\n")
     monkeypatch.setenv("QCDW_TUNE_CACHE", str(cache))
