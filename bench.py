@@ -693,7 +693,7 @@ def batch(q, li, np, torch, ctx, fields, args):
     return out
 
 
-LEARNED_TRAIN_SEEDS = range(1, 5)
+LEARNED_TRAIN_SEEDS = range(1, 9)
 LEARNED_STRIDE = 20  # training pairs: errors of BiCGStab iterates restarted every 20 iterations
 
 
@@ -705,9 +705,9 @@ def learned_jobs(li):
 
 
 def learned(q, li, np, torch, ctx, fields, args):
-    """32^3x64 near the critical kappa: train the gauge-covariant net on 4 other fields of the ensemble
+    """32^3x64 near the critical kappa: train the gauge-covariant net on 8 other fields of the ensemble
     (32 solver-generated pairs each: the errors of BiCGStab iterates against an FP64 solution of a Gaussian
-    source of that field, 128 in all), then FGMRES(32)+net against plain FP64 and mixed BiCGStab
+    source of that field, 256 in all), then FGMRES(32)+net against plain FP64 and mixed BiCGStab
     and FGMRES(32) without the net, all to an FP64 true residual of 1e-10 from the Gaussian source."""
     w = li.WORKLOADS["wc32x64"]
     if w["kappa"] is None:
@@ -715,7 +715,7 @@ def learned(q, li, np, torch, ctx, fields, args):
     L, kappa, csw = w["L"], w["kappa"], w["csw"]
     lat = q.make_lattice(L)
     out = {"workload": f"32^3x64, kappa {kappa} (bisected), csw 1.0, eps 0.15, Gaussian source"}
-    # training on fields 1..4
+    # training on fields 1..8
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net, losses, prev = None, [], None
