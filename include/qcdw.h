@@ -289,10 +289,11 @@ qcdw_status qcdw_invert(qcdw_op *op, const void *b, void *x, const qcdw_solver_p
 /* nrhs (1..16) right-hand sides solved together (Sec. III.B: a propagator is
    12 solves).  b, x: nrhs consecutive fermion fields.  info: nrhs entries.
    Every launch of the iteration serves all RHS (one multi-RHS hop per parity
-   block applies each link to all RHS of a site; of its two forms, links held
-   in registers or re-read from L2, the faster is picked by timing on first
-   use); each RHS keeps its own BiCGStab scalars, targets and flags, and stops
-   on its own (masked). */
+   block applies each link to all RHS of a site; of its forms, links held in
+   registers (vector or, for 16-bit storage, matrix-core products) or re-read
+   from L2, the fastest is picked by timing on first use, see qcdw_ctx_tuned);
+   each RHS keeps its own BiCGStab scalars, targets and flags, and stops on its
+   own (masked). */
 qcdw_status qcdw_invert_multi(qcdw_op *op, int nrhs, const void *b, void *x, const qcdw_solver_params *params,
                               qcdw_solve_info *info);
 
@@ -405,9 +406,12 @@ typedef struct {
    smooth_iters 2. */
 void qcdw_mg_params_default(qcdw_mg_params *p);
 /* Set up the multigrid for op (the loadGauge step that builds it, Sec. III.B).  vecs: NULL (generate) or
-   nvec device fields in the fermion layout, read.  The object holds the block vectors (FP64 and FP32), the
-   coarse stencil (FP64 and FP32) and the coarse solver workspace; op must outlive it.  EINVAL for a block
-   that does not tile the lattice, nvec out of range or linearly dependent vectors on an aggregate. */
+   nvec device fields in the fermion layout, read.  Generated vectors relax M v = 0 from seeded Gaussian
+   fields: setup_iters iterations of BiCGStab in the operator's inner precision on M y = M eta from y = 0,
+   one vector after the other, v = eta - y.  The object holds the block vectors (FP64
+   and FP32), the coarse stencil (FP64, and BF16 for the preconditioner's coarse solve) and the coarse
+   solver workspace; op must outlive it.  EINVAL for a block that does not tile the lattice, nvec out of
+   range or linearly dependent vectors on an aggregate. */
 qcdw_status qcdw_mg_create(qcdw_op *op, const qcdw_mg_params *params, const void *vecs, qcdw_mg **mg);
 void qcdw_mg_destroy(qcdw_mg *mg);
 /* coarse_dims: 4 host ints, L / block; nvec: host int */
