@@ -56,14 +56,12 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
     using T = typename P::real;
     const long Vh = a.g.Vh;
     const int gq = q >> 1;
-    const int lane = threadIdx.x & 63;
-    const int src = (lane & ~3) + (q < 2 ? q + 2 : 3 - q);
     cx<T> res[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < 3; c++) {  // partner lane: q < 2 ? q + 2 : 3 - q
         const cx<T> mine = gq == 0 ? acc_u[c] : acc_l[c];
         const cx<T> theirs = gq == 0 ? acc_l[c] : acc_u[c];
-        res[c] = mine + shfl_cx(theirs, src);
+        res[c] = mine + quad_dpp_cx<QUAD_PARTNER>(theirs);
     }
 
     cx<T> outv[3];
@@ -87,14 +85,14 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
         if constexpr (EPI == EPI_XPAY_CLOVY) {
             cx<T> ox[3], by[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(yv[c], 1);
+            for (int c = 0; c < 3; c++) ox[c] = quad_dpp_cx<QUAD_XOR1>(yv[c]);
             herm_rows<QCDW_CLOV_FMA != 0>(win, q & 1, yv, ox, by);
 #pragma unroll
             for (int c = 0; c < 3; c++) outv[c] = by[c] - aa * res[c];
         } else {
             cx<T> ox[3], br[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
+            for (int c = 0; c < 3; c++) ox[c] = quad_dpp_cx<QUAD_XOR1>(res[c]);
             herm_rows<QCDW_CLOV_FMA != 0>(win, q & 1, res, ox, br);
             if constexpr (EPI == EPI_CLOV) {
 #pragma unroll

@@ -98,15 +98,28 @@ __device__ __forceinline__ void load_window(const void* clov, long Vh, int site,
     for (int e = 0; e < 27; e++) win[e] = P::ldr(clov, base + (long)e * CLOV_STRIDE);
 }
 
-template <typename T>
-__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src)
+// In-quad permutations through DPP (a VALU operand modifier, no trip through the LDS crossbar): lane
+// 4 b + i receives the value of lane 4 b + sel_i, CTRL = sel_0 | sel_1 << 2 | sel_2 << 4 | sel_3 << 6.
+// Every lane of the quad must be active.
+constexpr int QUAD_XOR1 = 0xB1;      // (1, 0, 3, 2): the partner spin of a chirality block
+constexpr int QUAD_PARTNER = 0x1E;   // (2, 3, 1, 0): the lane holding the other half of a spin's hops
+template <int CTRL>
+__device__ __forceinline__ float quad_dpp(float v)
 {
-    return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
-template <typename T>
-__device__ __forceinline__ cx<T> shfl_xor_cx(cx<T> v, int m)
+template <int CTRL>
+__device__ __forceinline__ double quad_dpp(double v)
 {
-    return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
+    const uint2 u = __builtin_bit_cast(uint2, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)u.x, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)u.y, CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, make_uint2((unsigned)lo, (unsigned)hi));
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cx<T> quad_dpp_cx(cx<T> v)
+{
+    return {quad_dpp<CTRL>(v.re), quad_dpp<CTRL>(v.im)};
 }
 
 // The four hops of one lane at one site: neighbour indices (input parity), link

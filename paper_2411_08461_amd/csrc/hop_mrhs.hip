@@ -42,8 +42,6 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
     const int gq = q >> 1, k = q & 1;
     const long Vh = g.Vh;
     const long field = 12L * Vh;  // complex per RHS
-    const int lane = threadIdx.x & 63;
-    const int src = (lane & ~3) + (q < 2 ? q + 2 : 3 - q);  // in-quad partner finishing the other spin
     const int su = k, sl = gq == 0 ? 3 - k : 2 + k;
 
     // per-lane hop geometry, links (row 2 rebuilt once) and clover window, shared by all RHS
@@ -117,7 +115,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
         for (int c = 0; c < 3; c++) {
             const cx<T> mine = gq == 0 ? acc_u[c] : acc_l[c];
             const cx<T> theirs = gq == 0 ? acc_l[c] : acc_u[c];
-            res[c] = mine + shfl_cx(theirs, src);
+            res[c] = mine + quad_dpp_cx<QUAD_PARTNER>(theirs);
         }
         cx<T> outv[3], yv[3];
         if constexpr (EPI == EPI_CLOV_XPAY || RED == RED_TS) {
@@ -131,7 +129,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
         } else {
             cx<T> ox[3], br[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
+            for (int c = 0; c < 3; c++) ox[c] = quad_dpp_cx<QUAD_XOR1>(res[c]);
             herm_rows<true>(win, q & 1, res, ox, br);
             const T aa = (T)a.a;
 #pragma unroll
@@ -413,7 +411,7 @@ __global__ __launch_bounds__(256) void hop_mrhs_mfma_kernel(HopArgs a, const Sca
         } else {
             cx<float> ox[3], br[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) ox[c] = shfl_xor_cx(res[c], 1);
+            for (int c = 0; c < 3; c++) ox[c] = quad_dpp_cx<QUAD_XOR1>(res[c]);
             herm_rows<true>(win, q & 1, res, ox, br);
             const float aa = (float)a.a;
 #pragma unroll
