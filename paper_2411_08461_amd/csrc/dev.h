@@ -70,15 +70,24 @@ __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; 
 // ---------------------------------------------------------------------------
 // storage precisions: FP64, FP32, BF16, FP16.  `real` is the arithmetic type.
 // ---------------------------------------------------------------------------
+// BF16 bits (low half of b) to float: exact
+__device__ __forceinline__ float bf_bits2f(uint32_t b) { return __uint_as_float(b << 16); }
+// float to BF16 bits, round to nearest even, in integer arithmetic (NaN kept quiet): the scalar store
+// uses it so that an FP64 value is rounded to FP32 first and then to BF16, whatever the compiler folds
+// (it turns a double -> float -> bfloat conversion chain into one direct rounding)
 __device__ __forceinline__ uint32_t f2bf_bits(float f)
 {
-    // round to nearest even; NaN kept quiet
     uint32_t u = __float_as_uint(f);
     if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
     u += 0x7fffu + ((u >> 16) & 1u);
     return u >> 16;
 }
-__device__ __forceinline__ float bf_bits2f(uint32_t b) { return __uint_as_float(b << 16); }
+// float to BF16 by the conversion instruction (v_cvt_pk_bf16_f32: round to nearest even, NaN stays
+// NaN), two values packed low, high; written as a conversion, not as bit arithmetic, so that the
+// compiler folds a rounded value that is rounded again into one instruction
+typedef float bf_f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf_b2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf_b2 f2bf2(float lo, float hi) { return __builtin_convertvector(bf_f2{lo, hi}, bf_b2); }
 
 struct P64 {
     using real = double;
@@ -122,19 +131,17 @@ struct PBF16 {
         uint32_t v = reinterpret_cast<const uint32_t*>(base)[k];
         return {bf_bits2f(v & 0xffffu), bf_bits2f(v >> 16)};
     }
-    __device__ static void st(void* base, long k, cx<float> z)
+    __device__ static void st(void* base, long k, cx<float> z) { reinterpret_cast<bf_b2*>(base)[k] = f2bf2(z.re, z.im); }
+    __device__ static cx<float> rt(cx<float> z)
     {
-        reinterpret_cast<uint32_t*>(base)[k] = f2bf_bits(z.re) | (f2bf_bits(z.im) << 16);
+        const bf_f2 f = __builtin_convertvector(f2bf2(z.re, z.im), bf_f2);
+        return {f.x, f.y};
     }
-    __device__ static cx<float> rt(cx<float> z) { return {bf_bits2f(f2bf_bits(z.re)), bf_bits2f(f2bf_bits(z.im))}; }
     __device__ static float ldr(const void* base, long k)
     {
         return bf_bits2f(reinterpret_cast<const uint16_t*>(base)[k]);
     }
-    __device__ static void str(void* base, long k, float v)
-    {
-        reinterpret_cast<uint16_t*>(base)[k] = (uint16_t)f2bf_bits(v);
-    }
+    __device__ static void str(void* base, long k, float v) { reinterpret_cast<uint16_t*>(base)[k] = (uint16_t)f2bf_bits(v); }
 };
 
 struct PF16 {

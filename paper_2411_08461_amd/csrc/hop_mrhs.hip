@@ -82,26 +82,26 @@ __global__ __launch_bounds__(256) void hop_mrhs_kernel(HopArgs a, const Scal* S)
         for (int j = 0; j < RS; j++)
 #pragma unroll
             for (int c = 0; c < 3; c++) acc2_u[j][c] = acc2_l[j][c] = {T(0), T(0)};
-        if (valid) {
+        // lanes past the last site run too (their neighbour offsets point at site 0 and their links are
+        // zero) and store nothing: no divergent branch around the loads
 #pragma unroll
-            for (int h = 0; h < 4; h++) {
-                cx<T> hv[RS][3];
+        for (int h = 0; h < 4; h++) {
+            cx<T> hv[RS][3];
 #pragma unroll
-                for (int j = 0; j < RS; j++) {
-                    cx<T> pu[3], pl[3];
-                    if (act[j]) {
-                        load_pair<P>((const char*)a.psi + (long)(r0 + j) * field * P::cbytes, Vh, su, sl, L.nbh[h],
-                                     pu, pl);
-                    } else {
+            for (int j = 0; j < RS; j++) {
+                cx<T> pu[3], pl[3];
+                if (act[j]) {
+                    load_pair<P>((const char*)a.psi + (long)(r0 + j) * field * P::cbytes, Vh, su, sl, L.nbh[h], pu,
+                                 pl);
+                } else {
 #pragma unroll
-                        for (int c = 0; c < 3; c++) pu[c] = pl[c] = {T(0), T(0)};
-                    }
-                    project<true>(pu, pl, L.cs[h], h < 2, hv[j]);
+                    for (int c = 0; c < 3; c++) pu[c] = pl[c] = {T(0), T(0)};
                 }
-#pragma unroll
-                for (int j = 0; j < RS; j++)
-                    hop_rows<true>(ur[h], h & 1, h < 2, L.fsg[h], L.cs[h], hv[j], acc2_u[j], acc2_l[j]);
+                project<true>(pu, pl, L.cs[h], h < 2, hv[j]);
             }
+#pragma unroll
+            for (int j = 0; j < RS; j++)
+                hop_rows<true>(ur[h], h & 1, h < 2, L.fsg[h], L.cs[h], hv[j], acc2_u[j], acc2_l[j]);
         }
 #pragma unroll
         for (int j = 0; j < RS; j++) {
@@ -225,7 +225,7 @@ template <class P>
 struct Mfma16;
 template <>
 struct Mfma16<PBF16> {
-    __device__ static uint32_t bits(float f) { return f2bf_bits(f); }
+    __device__ static uint32_t bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
     __device__ static float val(uint32_t b) { return bf_bits2f(b & 0xffffu); }
     __device__ static mf4 mma(ms4 a, ms4 b, mf4 c) { return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0); }
 };

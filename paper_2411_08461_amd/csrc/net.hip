@@ -98,13 +98,11 @@ __device__ __forceinline__ void transport(const void* in, const void* gauge, con
 
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 typedef short mfma_s4 __attribute__((ext_vector_type(4)));
-typedef float nf2 __attribute__((ext_vector_type(2)));
-typedef __bf16 nb2 __attribute__((ext_vector_type(2)));
 
 // two floats rounded to BF16 (nearest even) and packed low, high
 __device__ __forceinline__ uint32_t pk_bf16(float lo, float hi)
 {
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(nf2{lo, hi}, nb2));
+    return __builtin_bit_cast(uint32_t, f2bf2(lo, hi));
 }
 __device__ __forceinline__ mfma_s4 s4_of(uint32_t lo, uint32_t hi) { return __builtin_bit_cast(mfma_s4, make_uint2(lo, hi)); }
 
