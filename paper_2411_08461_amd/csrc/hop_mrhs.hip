@@ -212,10 +212,10 @@ hipError_t launch_hop_mrhs(hipStream_t s, int prec, int epi, int red, const HopA
 // is rebuilt in FP32 and rounded to 16 bits once per site (the only rounding the vector form does not have);
 // the products are exact in FP32 and all eight directions accumulate there (the spatial ones first, their sum
 // then scaled by the spatial weight).  Link operands are built once per site and kept in registers for all
-// right-hand sides; the clover epilogue is the vector form's.  Measured at 24^3x64 with 12 RHS (BF16): 371 us
-// against 323 us for the vector register loop, with 14 % fewer vector instructions: both kernels are bound
-// by the vector-memory address path (TA busy ~77 % of the kernel, half of it stalled on the L1), not by
-// arithmetic.  The multi-RHS tuner times this form beside the others.
+// right-hand sides; the clover epilogue is the vector form's.  Measured at 24^3x64 with 12 RHS (BF16): 370 us
+// against 306 us for the vector register loop, with a third fewer vector instructions: the vector form keeps
+// its SIMDs issuing 74 % of the time and its address unit 86 % busy, while this form waits on its loads with
+// less work in flight.  The multi-RHS tuner times this form beside the others.
 // ---------------------------------------------------------------------------
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef short ms4 __attribute__((ext_vector_type(4)));
