@@ -17,7 +17,8 @@ bool mrhs_variant_fits(const qcdw::Geom& g, int prec, int v)
 {
     if (v == 1) return true;
     if ((v & 1) || (v & ~(MRHS_MFMA | 1023))) return false;
-    if ((v & MRHS_MFMA) && prec != qcdw::BF16 && prec != qcdw::F16) return false;
+    // the matrix-core form keeps its neighbour offsets (complex index within one RHS) in 32 bits
+    if ((v & MRHS_MFMA) && ((prec != qcdw::BF16 && prec != qcdw::F16) || 12L * g.Vh > 0x7fffffffL)) return false;
     const int cg = (v & 1023) >> 1;
     return cg == 0 || hop_cgroup_fits(g, cg);
 }
@@ -804,7 +805,8 @@ struct Solver {
             if (kprec == BF16 || kprec == F16) {  // the matrix-core form, in both tile orders
                 const size_t n = cand.size();
                 for (size_t c = 0; c < n; c++)
-                    if ((cand[c] & 1) == 0) cand.push_back(MRHS_MFMA | cand[c]);
+                    if ((cand[c] & 1) == 0 && mrhs_variant_fits(g, kprec, MRHS_MFMA | cand[c]))
+                        cand.push_back(MRHS_MFMA | cand[c]);
             }
         }
         auto choose = [&](int v) {

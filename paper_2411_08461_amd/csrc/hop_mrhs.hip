@@ -481,6 +481,7 @@ hipError_t launch_hop_mrhs_mfma(hipStream_t s, int prec, int epi, int red, const
                                 hipEvent_t e0, hipEvent_t e1)
 {
     if (a.g.Vh <= 0 || a.nrhs <= 0) return hipSuccess;
+    if (12L * a.g.Vh > 0x7fffffffL) return hipErrorInvalidValue;  // 32-bit neighbour offsets
     switch (prec) {
     case BF16: return launch_mrhs_mfma_p<PBF16>(s, epi, red, a, S, e0, e1);
     case F16: return launch_mrhs_mfma_p<PF16>(s, epi, red, a, S, e0, e1);
