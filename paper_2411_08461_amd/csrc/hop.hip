@@ -75,7 +75,9 @@ __device__ __forceinline__ void hop_finish(const HopArgs& a, int site, bool vali
         for (int c = 0; c < 3; c++) outv[c] = res[c];
     } else {
         T win[27];
-        if (valid) {
+        if constexpr (QCDW_WIN_SHARE != 0) {
+            load_window_shared<P>(a.clov, Vh, site, q, valid, win);
+        } else if (valid) {
             load_window<P>(a.clov, Vh, site, q, win);
         } else {
 #pragma unroll
